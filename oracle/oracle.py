@@ -1,0 +1,218 @@
+"""Python access to the CPU oracle (test infrastructure only).
+
+The oracle is a plain C++ implementation of the sector tracker, compiled with
+g++ (no contraction, no fast-math) into ``oracle/_build/liborc.so``.  Only the
+tests, the smoke check and the benchmark's CPU-baseline leg may use it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "tpc_oracle.cpp")
+BUILD_DIR = os.path.join(HERE, "_build")
+LIB = os.path.join(BUILD_DIR, "liborc.so")
+
+CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
+            "-fno-math-errno", "-Wall", "-Wextra", "-Wdouble-promotion", "-Werror",
+            "-shared", "-fPIC", "-pthread"]
+
+
+def build(force: bool = True) -> str:
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.run(["g++", *CXXFLAGS, "-o", tmp, SRC], check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n_sectors", ctypes.c_int32), ("n_rows", ctypes.c_int32),
+                ("row_x", ctypes.c_float * 160), ("bz_tesla", ctypes.c_float),
+                ("tan_half_angle", ctypes.c_float), ("z_max", ctypes.c_float),
+                ("sigma_y0", ctypes.c_float), ("sigma_y1", ctypes.c_float),
+                ("sigma_z0", ctypes.c_float), ("sigma_z1", ctypes.c_float)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nf_window", ctypes.c_float), ("nf_mmax", ctypes.c_float),
+                ("chi2_max", ctypes.c_float), ("k_win", ctypes.c_float),
+                ("w_max", ctypes.c_float), ("s_max", ctypes.c_float),
+                ("c_s0", ctypes.c_float), ("c_t0", ctypes.c_float), ("c_q0", ctypes.c_float),
+                ("m_edge", ctypes.c_float), ("m_z", ctypes.c_float),
+                ("n_gap", ctypes.c_int32), ("n_min_tracklet", ctypes.c_int32),
+                ("n_min_track", ctypes.c_int32)]
+
+
+# The oracle's own constants for the tracker (the values this project
+# adopted for a method the paper names without numbers).
+DEFAULT_PARAMS = dict(nf_window=3.0, nf_mmax=16.0, chi2_max=16.0, k_win=4.0, w_max=5.0,
+                      s_max=0.95, c_s0=1.0, c_t0=1.0, c_q0=100.0, m_edge=1.0, m_z=1.0,
+                      n_gap=6, n_min_tracklet=10, n_min_track=10)
+
+TRACK_DTYPE = np.dtype([("sector", "<i4"), ("n_hits", "<i4"), ("row_in", "<i4"),
+                        ("row_out", "<i4"), ("hit_off", "<i8"), ("inner_id", "<i4"),
+                        ("start_id", "<i4"), ("x_ref", "<f8"), ("par", "<f8", (5,)),
+                        ("cov", "<f8", (15,)), ("chi2", "<f8"), ("ndf", "<i4"),
+                        ("tracklet", "<i4")], align=True)
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=False)
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        L.orc_run.restype = P
+        L.orc_run.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(Params), ctypes.c_int,
+                              ctypes.c_int64, P, P, P, P, ctypes.c_int, ctypes.c_int]
+        L.orc_free.argtypes = [P]
+        for f in ("orc_n_tracks", "orc_n_track_hits", "orc_n_starts"):
+            getattr(L, f).restype = ctypes.c_int64
+            getattr(L, f).argtypes = [P]
+        L.orc_get_links.argtypes = [P, P, P, P, P]
+        L.orc_get_starts.argtypes = [P, P]
+        L.orc_get_tracks.argtypes = [P, P, P]
+        L.orc_replay_tracks.restype = ctypes.c_int64
+        L.orc_replay_tracks.argtypes = [P, P]
+        L.orc_n_tracklets.restype = ctypes.c_int64
+        L.orc_n_tracklets.argtypes = [P, ctypes.c_int]
+        L.orc_get_tracklets.argtypes = [P, ctypes.c_int, P, P, P, P]
+        f32, f64 = ctypes.c_float, ctypes.c_double
+        L.orc_predict_f.argtypes = [P, P, f32, f32, f32]
+        L.orc_predict_d.argtypes = [P, P, f64, f64, f64]
+        L.orc_update_f.argtypes = [P, P, f32, f32, f32, f32, f32, f32, ctypes.c_int, P]
+        L.orc_update_d.argtypes = [P, P, f64, f64, f64, f64, f64, f64, ctypes.c_int, P]
+        _lib = L
+    return _lib
+
+
+def make_geometry(geo: dict) -> Geometry:
+    g = Geometry()
+    g.n_sectors = int(geo["n_sectors"])
+    g.n_rows = int(geo["n_rows"])
+    rx = np.zeros(160, np.float32)
+    rx[: g.n_rows] = geo["row_x"]
+    for i in range(160):
+        g.row_x[i] = float(rx[i])
+    for k in ("bz_tesla", "tan_half_angle", "z_max", "sigma_y0", "sigma_y1",
+              "sigma_z0", "sigma_z1"):
+        setattr(g, k, float(geo[k]))
+    return g
+
+
+def make_params(**over) -> Params:
+    d = dict(DEFAULT_PARAMS)
+    d.update(over)
+    p = Params()
+    for k, v in d.items():
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class OracleResult:
+    precision: int
+    up: np.ndarray
+    dn: np.ndarray
+    upc: np.ndarray
+    dnc: np.ndarray
+    starts: np.ndarray
+    tracks: np.ndarray        # TRACK_DTYPE, canonical order
+    hits: np.ndarray          # i32, track hit lists (ascending row)
+    replay: np.ndarray | None = None   # TRACK_DTYPE, double replay of a float run
+    replay_bad: int = 0
+    tracklets: dict | None = None
+
+    def track_hits(self, k: int) -> np.ndarray:
+        t = self.tracks[k]
+        return self.hits[t["hit_off"]: t["hit_off"] + t["n_hits"]]
+
+
+def run(sector, row, y, z, geo: dict, precision: int = 32, exhaustive: bool = False,
+        nthreads: int = 1, replay: bool = False, tracklet_sectors=(), params=None) -> OracleResult:
+    """Track one event on the CPU.  Inputs are the cluster SoA; the cluster
+    ID of a cluster is its index."""
+    L = lib()
+    sector = np.ascontiguousarray(sector, np.uint8)
+    row = np.ascontiguousarray(row, np.uint8)
+    y = np.ascontiguousarray(y, np.float32)
+    z = np.ascontiguousarray(z, np.float32)
+    n = len(y)
+    g = make_geometry(geo)
+    p = params if params is not None else make_params()
+    h = L.orc_run(ctypes.byref(g), ctypes.byref(p), precision, n, _ptr(sector), _ptr(row),
+                  _ptr(y), _ptr(z), int(exhaustive), int(nthreads))
+    try:
+        up, dn, upc, dnc = (np.empty(n, np.int32) for _ in range(4))
+        L.orc_get_links(h, _ptr(up), _ptr(dn), _ptr(upc), _ptr(dnc))
+        starts = np.empty(L.orc_n_starts(h), np.int32)
+        L.orc_get_starts(h, _ptr(starts))
+        nt = L.orc_n_tracks(h)
+        tracks = np.zeros(nt, TRACK_DTYPE)
+        hits = np.empty(L.orc_n_track_hits(h), np.int32)
+        L.orc_get_tracks(h, _ptr(tracks), _ptr(hits))
+        res = OracleResult(precision, up, dn, upc, dnc, starts, tracks, hits)
+        if replay:
+            rep = np.zeros(nt, TRACK_DTYPE)
+            res.replay_bad = int(L.orc_replay_tracks(h, _ptr(rep)))
+            res.replay = rep
+        if tracklet_sectors:
+            res.tracklets = {}
+            for s in tracklet_sectors:
+                m = L.orc_n_tracklets(h, s)
+                info = np.empty((m, 6), np.int32)
+                w = np.empty(m, np.uint32)
+                uh = np.empty((m, 159), np.int32)
+                dh = np.empty((m, 159), np.int32)
+                if m:
+                    L.orc_get_tracklets(h, s, _ptr(info), _ptr(w), _ptr(uh), _ptr(dh))
+                res.tracklets[s] = dict(start=info[:, 0], n=info[:, 1], row_in=info[:, 2],
+                                        row_out=info[:, 3], valid=info[:, 4].astype(bool),
+                                        r0=info[:, 5], weight=w, uhit=uh, dhit=dh)
+        return res
+    finally:
+        L.orc_free(h)
+
+
+def run_event(ev, **kw) -> OracleResult:
+    return run(ev.sector, ev.row, ev.y, ev.z, ev.geometry(), **kw)
+
+
+# ---- single Kalman steps ----------------------------------------------------
+
+def predict(p, C, dx, b, smax=0.95, precision=64):
+    dt = np.float64 if precision == 64 else np.float32
+    p = np.array(p, dt)
+    C = np.array(C, dt)
+    f = lib().orc_predict_d if precision == 64 else lib().orc_predict_f
+    ok = f(_ptr(p), _ptr(C), dx, b, smax)
+    return bool(ok), p, C
+
+
+def update(p, C, my, mz, vy, vz, chi2max=16.0, smax=0.95, gated=True, precision=64):
+    dt = np.float64 if precision == 64 else np.float32
+    p = np.array(p, dt)
+    C = np.array(C, dt)
+    chi2 = np.zeros(1, dt)
+    f = lib().orc_update_d if precision == 64 else lib().orc_update_f
+    ok = f(_ptr(p), _ptr(C), my, mz, vy, vz, chi2max, smax, int(gated), _ptr(chi2))
+    return bool(ok), p, C, float(chi2[0])
+
+
+def curvature_b(bz_tesla: float) -> float:
+    """b = -c Bz in cm^-1 per (c/GeV); d(phi)/dl = b * q/pT."""
+    return -0.00299792458 * float(bz_tesla)
