@@ -1,0 +1,220 @@
+/*
+ * tpcca.h -- C ABI of the MI355X TPC sector tracker.
+ *
+ * The tracker is the hot path the paper puts at the centre of its online
+ * reconstruction (Abstract; Section 2: tracking is the most compute-intense
+ * reconstruction step; the GPU tracker is built on a Cellular Automaton and
+ * the Kalman filter).  Clusters (pad row, y, z, charge) of the 36 sectors x
+ * 159 pad rows of the TPC go in; track hit lists with fitted helix
+ * parameters and covariances come out.  Each sector is tracked on its own
+ * (a detector link sees one part of every event, Section 2).
+ *
+ * Steps, all in HIP kernels on one GPU: stage and validate clusters; pad-row
+ * hit grid; neighbours finder (best up/down link per hit); link cleaner and
+ * start hits; tracklet construction (float Kalman filter out- and inward);
+ * hit ownership and tracklet selection; output refit (double Kalman filter)
+ * and canonical ordering.
+ *
+ * Conventions
+ *  - Return codes: TPC_OK (0) or a negative TPC_E* code; tpc_last_error()
+ *    gives a message.  Arguments are checked on the host before any device
+ *    work is enqueued, so a failed call has enqueued nothing.
+ *  - A context owns no device memory: the caller passes one device
+ *    workspace (e.g. a torch uint8 tensor's data pointer) of at least
+ *    tpc_workspace_bytes() and a HIP stream; all work of the context is
+ *    enqueued on that stream, in call order.  A context is not thread-safe.
+ *  - Cluster ID = index of the cluster in the event's input arrays; IDs must
+ *    be < 2^24 per event.
+ *  - Slots: a context has params->max_slots slots.  A slot holds one event
+ *    (tpc_load_clusters) or a batch of events tracked together
+ *    (tpc_load_batch: events are concatenated, sector g of the slot is sector
+ *    g % 36 of event g / 36).
+ */
+#ifndef TPCCA_H
+#define TPCCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPC_N_SECTORS 36
+#define TPC_N_ROWS 159
+
+enum {
+  TPC_OK = 0,
+  TPC_EINVAL = -1,     /* bad argument or bad cluster data */
+  TPC_ENOMEM = -2,     /* workspace too small for the requested capacity */
+  TPC_EOVERFLOW = -3,  /* caller output buffer too small (required sizes returned) */
+  TPC_EDEVICE = -4,    /* a HIP call failed */
+  TPC_ESTATE = -5,     /* call out of order for the slot */
+  TPC_EBUSY = -6       /* (serving) slot still in flight */
+};
+
+/* where the cluster arrays passed to tpc_load_* live */
+enum { TPC_HOST = 1, TPC_DEVICE = 2 };
+
+/* Detector description (inputs; the tracker has no built-in geometry). */
+typedef struct tpc_geometry {
+  int32_t n_sectors;        /* must be 36 */
+  int32_t n_rows;           /* must be 159 */
+  float row_x[160];         /* pad-row radius x_r (cm), 159 used, increasing */
+  float bz_tesla;           /* solenoid field */
+  float tan_half_angle;     /* tan of half the sector opening (20 deg sectors) */
+  float z_max;              /* drift length (cm) */
+  float sigma_y0, sigma_y1; /* cluster error sigma_y(z) = y0 + y1 |z| / z_max */
+  float sigma_z0, sigma_z1; /* same for z */
+} tpc_geometry;
+
+/* Tracker constants and capacities.  tpc_params_default() fills the values
+ * this implementation was tuned with. */
+typedef struct tpc_params {
+  float nf_window;          /* neighbours-finder window half width (cm) */
+  float nf_mmax;            /* max triplet deviation metric */
+  float chi2_max;           /* Kalman gate */
+  float k_win;              /* search window, units of sqrt(residual variance) */
+  float w_max;              /* search window cap (cm) */
+  float s_max;              /* max |sin phi| */
+  float c_s0, c_t0, c_q0;   /* prior variances of sin phi, tan lambda, q/pT */
+  float m_edge;             /* sector edge margin (cm) */
+  float m_z;                /* membrane / drift-length margin (cm) */
+  int32_t n_gap;            /* consecutive rows without hit that end a phase */
+  int32_t n_min_tracklet;   /* hits of a valid tracklet */
+  int32_t n_min_track;      /* owned hits of an output track */
+  float bin_target;         /* grid: clusters per bin aimed at (tuning only) */
+  float bin_min_edge;       /* grid: smallest bin edge (cm) (tuning only) */
+  int32_t max_slots;        /* slots of a context */
+  int32_t max_events;       /* events per slot */
+  int64_t max_clusters;     /* clusters per slot */
+} tpc_params;
+
+/* One output track.  par / cov are given at x_ref, the pad-row radius of
+ * the innermost hit: (y, z, sin phi, tan lambda, q/pT [c/GeV]); cov is the
+ * lower triangle (yy, zy, zz, sy, sz, ss, Ty, Tz, Ts, TT, Qy, Qz, Qs, QT, QQ). */
+typedef struct tpc_track {
+  int32_t event;            /* event index inside the slot */
+  int32_t sector;           /* 0..35 */
+  int32_t n_hits;
+  int32_t row_in;           /* innermost pad row */
+  int32_t row_out;          /* outermost pad row */
+  int32_t ndf;              /* 2 n_hits - 5 */
+  int64_t hit_off;          /* first entry in the event's hit-ID list */
+  int32_t inner_id;         /* cluster ID of the innermost hit (order key) */
+  int32_t start_id;         /* cluster ID of the tracklet's start hit */
+  double x_ref;
+  double par[5];
+  double cov[15];
+  double chi2;
+} tpc_track;
+
+typedef struct tpc_ctx tpc_ctx;
+
+/* Fill *p with the default constants; max_slots = 1, max_events = 1,
+ * max_clusters = 4M.  Returns TPC_EINVAL if p is NULL. */
+int tpc_params_default(tpc_params* p);
+
+/* Device bytes a context with these capacities needs (0 if p is invalid). */
+size_t tpc_workspace_bytes(const tpc_params* p);
+
+/* Create a context.  g, p: copied.  dev_workspace: device memory of
+ * ws_bytes >= tpc_workspace_bytes(p), owned by the caller and used by the
+ * context until tpc_destroy.  hip_stream: a hipStream_t (NULL = default
+ * stream).  Errors: TPC_EINVAL (geometry not 36 x 159 increasing rows,
+ * bad params), TPC_ENOMEM (workspace too small). */
+int tpc_init_geometry(tpc_ctx** out, const tpc_geometry* g, const tpc_params* p,
+                      void* dev_workspace, size_t ws_bytes, void* hip_stream);
+
+/* Stage one event into a slot: n clusters as structure-of-arrays,
+ * sector[i] < 36, row[i] < 159, finite y[i], z[i] (local sector frame, cm),
+ * q[i] charge (carried, unused; may be NULL).  flags: TPC_DEVICE (arrays in
+ * device memory, used in place: the caller keeps them alive and unchanged
+ * until the slot's tracks are read) or TPC_HOST (copied asynchronously into
+ * the slot; the caller keeps the arrays alive until the next synchronising
+ * call).  Bad cluster values are detected on the device and reported by
+ * tpc_get_tracks as TPC_EINVAL.  Errors: TPC_EINVAL (slot, n, pointers,
+ * flags), TPC_ENOMEM (n > max_clusters). */
+int tpc_load_clusters(tpc_ctx* ctx, int slot, const uint8_t* sector, const uint8_t* row,
+                      const float* y, const float* z, const float* q, int64_t n, int flags);
+
+/* Stage a batch of n_events events into one slot.  event_offsets (host,
+ * n_events + 1 entries, non-decreasing, event_offsets[0] = 0) delimit the
+ * events inside the concatenated arrays.  Otherwise as tpc_load_clusters. */
+int tpc_load_batch(tpc_ctx* ctx, int slot, int n_events, const int64_t* event_offsets,
+                   const uint8_t* sector, const uint8_t* row, const float* y, const float* z,
+                   const float* q, int flags);
+
+/* Track one sector of a staged slot (sector < 36 * events in the slot):
+ * the grid is built on the slot's first tracking call, then the neighbours
+ * finder, cleaner, tracklets, selection and refit run for this sector only,
+ * each as its own launch.  Errors: TPC_EINVAL, TPC_ESTATE (slot not loaded,
+ * or already finalised). */
+int tpc_track_sector(tpc_ctx* ctx, int slot, int sector);
+
+/* Track every sector of every event in the slot: each step is one launch
+ * over all sectors of the slot, then the tracks are put in canonical order
+ * (event, innermost cluster ID).  Asynchronous; results are read with
+ * tpc_get_tracks.  Errors: TPC_EINVAL, TPC_ESTATE. */
+int tpc_track_event(tpc_ctx* ctx, int slot);
+
+/* Wait for the slot and copy the tracks of one event of it (event = 0 for
+ * tpc_load_clusters) into caller host memory: out[max_tracks],
+ * hit_ids[max_hits] (cluster IDs, each track's hits ascending by row).
+ * *n_tracks, *n_hits receive the event's counts.  If sectors were tracked
+ * one by one, finalises the slot first.  Errors: TPC_EOVERFLOW (buffers too
+ * small; counts still returned, nothing copied), TPC_EINVAL (bad cluster
+ * data or a pad row with more than 4096 clusters), TPC_ESTATE, TPC_EDEVICE. */
+int tpc_get_tracks(tpc_ctx* ctx, int slot, int event, tpc_track* out, int64_t max_tracks,
+                   int32_t* hit_ids, int64_t max_hits, int64_t* n_tracks, int64_t* n_hits);
+
+/* Device-resident results of a tracked slot, without copies or
+ * synchronisation: tracks of all events of the slot in canonical order,
+ * hit IDs, per-event offsets (device arrays of n_events + 1 entries, into
+ * the track array and the hit array) and the slot's [track, hit] totals
+ * (device array of 2).  Pointers stay valid until the slot is loaded again. */
+int tpc_device_results(tpc_ctx* ctx, int slot, const tpc_track** tracks, const int32_t** hit_ids,
+                       const uint32_t** event_track_off, const uint32_t** event_hit_off,
+                       const uint32_t** totals);
+
+/* Diagnostics of the finding steps for one event of a tracked slot, copied
+ * to host arrays of the event's cluster count: the neighbours finder's
+ * up/down links and the cleaned links, as cluster IDs (-1 = none).  Any
+ * pointer may be NULL.  Synchronises.  Errors: TPC_EINVAL, TPC_ESTATE. */
+int tpc_get_links(tpc_ctx* ctx, int slot, int event, int32_t* up, int32_t* dn, int32_t* up_clean,
+                  int32_t* dn_clean);
+
+/* Apply one float transport + gated update to each of n states on the
+ * device (the tracklet filter's primitives, for bit-level tests).  All
+ * arrays are device memory: state[n][20] = (y, z, s, T, Q, C[15]) in/out,
+ * dx[n], meas[n][4] = (y, z, var_y, var_z), result[n][2] = (int bits:
+ * transport ok | update accepted << 1, chi2 as float).  Uses the context's
+ * b, s_max, chi2_max.  Asynchronous on the context stream. */
+int tpc_kf_step_f32(tpc_ctx* ctx, float* state, const float* dx, const float* meas,
+                    float* result, int64_t n);
+
+/* Stage timing.  With profiling on, tpc_track_event records HIP events on
+ * the context stream around its steps; tpc_get_profile waits for the stream
+ * and returns, for the last tracked slot, the milliseconds of each step
+ * (ms[TPC_N_STAGES]: grid, neighbours, clean+starts, tracklets,
+ * weights+selection, refit, output) and the slot's work counters
+ * (counters[8]: tracklets, tracklet row visits, search-window hits
+ * examined, tracks, clusters, sorted hits, 0, 0).  Either pointer may be
+ * NULL.  Errors: TPC_EINVAL, TPC_ESTATE (nothing profiled yet), TPC_EDEVICE. */
+#define TPC_N_STAGES 7
+int tpc_set_profiling(tpc_ctx* ctx, int enable);
+int tpc_get_profile(tpc_ctx* ctx, double* ms, uint64_t* counters);
+
+/* Message of the last failed call of ctx (or of the last failed
+ * tpc_init_geometry when ctx is NULL). */
+const char* tpc_last_error(const tpc_ctx* ctx);
+
+/* Release the context (host memory only; the workspace stays the caller's).
+ * Waits for the context's stream. */
+int tpc_destroy(tpc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPCCA_H */

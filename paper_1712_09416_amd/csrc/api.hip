@@ -1,0 +1,634 @@
+// C ABI of the tracker: argument checks, workspace carving, launch order.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tpc_device.h"
+#include "tpc_kernels.h"
+
+using namespace tpc;
+
+namespace {
+
+constexpr int kScanTile = 1024;
+
+struct SlotHost {
+  Slot d{};
+  int state = 0;   // 0 empty, 1 staged, 2 grid built, 3 sectors tracked, 4 final
+  int64_t n = 0;
+  int n_events = 0;
+  std::vector<int64_t> ev_off;
+  uint8_t* own_sector = nullptr;
+  uint8_t* own_row = nullptr;
+  float* own_y = nullptr;
+  float* own_z = nullptr;
+};
+
+// __global__ helpers local to this file
+__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+__global__ void k_kf_step(DevConst K, float* state, const float* dx, const float* meas, float* result,
+                          int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float* st = state + i * 20;
+  Helix<float> h;
+  h.y = st[0];
+  h.z = st[1];
+  h.s = st[2];
+  h.t = st[3];
+  h.q = st[4];
+  for (int k = 0; k < 15; ++k) h.c[k] = st[5 + k];
+  int bits = 0;
+  float chi2 = 0.0f;
+  if (transport(h, dx[i], K.b, K.smax)) {
+    bits = 1;
+    const float* m = meas + i * 4;
+    if (kalman_update(h, m[0], m[1], m[2], m[3], K.chi2max, K.smax, true, &chi2)) bits |= 2;
+  }
+  st[0] = h.y;
+  st[1] = h.z;
+  st[2] = h.s;
+  st[3] = h.t;
+  st[4] = h.q;
+  for (int k = 0; k < 15; ++k) st[5 + k] = h.c[k];
+  int* ri = reinterpret_cast<int*>(result + i * 2);
+  ri[0] = bits;
+  result[i * 2 + 1] = chi2;
+}
+
+// Links of one event as cluster IDs (diagnostics).
+__global__ void k_links_out(Slot S, int e, int32_t* up, int32_t* dn, int32_t* upc, int32_t* dnc) {
+  const uint32_t b = S.row_off[e * kSectorsPerEvent * kRows];
+  const uint32_t t = S.row_off[(e + 1) * kSectorsPerEvent * kRows];
+  const int64_t ev0 = S.ev_off[e];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t p = b + blockIdx.x * blockDim.x + threadIdx.x; p < t; p += stride) {
+    const int64_t id = (int64_t)S.hid[p] - ev0;
+    const int32_t l[4] = {S.up[p], S.dn[p], S.upc[p], S.dnc[p]};
+    int32_t* o[4] = {up, dn, upc, dnc};
+    for (int k = 0; k < 4; ++k)
+      o[k][id] = l[k] >= 0 ? (int32_t)((int64_t)S.hid[l[k]] - ev0) : -1;
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+struct Carver {
+  uint8_t* base;
+  size_t off = 0;
+  bool dry;
+  template <class T>
+  T* take(int64_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = dry ? nullptr : reinterpret_cast<T*>(base + off);
+    off += sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    return p;
+  }
+};
+
+void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
+  const int64_t N = p.max_clusters;
+  const int E = p.max_events;
+  const int64_t S = (int64_t)E * kSectorsPerEvent;
+  const int64_t SR = S * kRows;
+  const int64_t cap_tl = N / 3 + S;
+  const int64_t cap_tk = N / 10 + S;
+  uint8_t* own_sector = c.take<uint8_t>(N);
+  uint8_t* own_row = c.take<uint8_t>(N);
+  float* own_y = c.take<float>(N);
+  float* own_z = c.take<float>(N);
+  if (h) {
+    h->own_sector = own_sector;
+    h->own_row = own_row;
+    h->own_y = own_y;
+    h->own_z = own_z;
+  }
+  s.ev_off = c.take<int64_t>(E + 1);
+  s.row_cnt = c.take<uint32_t>(SR);
+  s.row_off = c.take<uint32_t>(SR + 1);
+  s.bins = c.take<RowBins>(SR);
+  s.bin_off = c.take<uint32_t>(N + SR + 1);
+  s.rank = c.take<uint32_t>(N);
+  s.ty = c.take<float>(N);
+  s.tz = c.take<float>(N);
+  s.tid = c.take<uint32_t>(N);
+  s.hy = c.take<float>(N);
+  s.hz = c.take<float>(N);
+  s.hid = c.take<uint32_t>(N);
+  s.up = c.take<int32_t>(N);
+  s.dn = c.take<int32_t>(N);
+  s.upc = c.take<int32_t>(N);
+  s.dnc = c.take<int32_t>(N);
+  s.tl_base = c.take<uint32_t>(S + 1);
+  s.tk_base = c.take<uint32_t>(S + 1);
+  s.n_start = c.take<uint32_t>(S);
+  s.n_track = c.take<uint32_t>(S);
+  s.flat_tl = c.take<uint32_t>(S + 1);
+  s.flat_tk = c.take<uint32_t>(S + 1);
+  s.start_hit = c.take<int32_t>(cap_tl);
+  s.tl_hits = c.take<int32_t>(cap_tl * kRows);
+  s.tl_info = c.take<int32_t>(cap_tl * 4);
+  s.tl_weight = c.take<uint32_t>(cap_tl);
+  s.tl_state = c.take<float>(cap_tl * 5);
+  s.weight = c.take<uint32_t>(N);
+  s.tk_tracklet = c.take<int32_t>(cap_tk);
+  s.tk_info = c.take<int32_t>(cap_tk * 4);
+  s.tk_par = c.take<double>(cap_tk * 5);
+  s.tk_cov = c.take<double>(cap_tk * 15);
+  s.tk_chi2 = c.take<double>(cap_tk);
+  s.tmap = c.take<int32_t>(N);
+  s.scan_a = c.take<uint32_t>(N + 1);
+  s.scan_b = c.take<uint32_t>(std::max<int64_t>(N + 1, cap_tk + 1) / kScanTile + 4);
+  s.out_count = c.take<uint32_t>(2);
+  s.out_ntk = c.take<uint32_t>(cap_tk + 1);
+  s.out_order = c.take<int32_t>(cap_tk);
+  s.out_tracks = c.take<tpc_track>(cap_tk);
+  s.out_hits = c.take<int32_t>(N);
+  s.ev_track_off = c.take<uint32_t>(E + 1);
+  s.ev_hit_off = c.take<uint32_t>(E + 1);
+  s.err = c.take<uint32_t>(4);
+  s.stats = c.take<unsigned long long>(8);
+  s.cap_n = N;
+  s.cap_tl = cap_tl;
+  s.cap_tk = cap_tk;
+  s.cap_e = E;
+}
+
+bool params_ok(const tpc_params* p) {
+  if (!p) return false;
+  if (!(p->max_slots >= 1 && p->max_slots <= 1024)) return false;
+  if (!(p->max_events >= 1 && p->max_events <= 4096)) return false;
+  if (!(p->max_clusters >= 1 && p->max_clusters <= (int64_t)0x7FFFFFFF)) return false;
+  if (!(p->n_gap >= 1 && p->n_min_tracklet >= 2 && p->n_min_track >= 3)) return false;
+  if (!(p->s_max > 0.0f && p->s_max < 1.0f && p->chi2_max > 0.0f)) return false;
+  if (!(p->nf_window > 0.0f && p->k_win > 0.0f && p->w_max > 0.0f)) return false;
+  if (!(p->c_s0 > 0.0f && p->c_t0 > 0.0f && p->c_q0 > 0.0f)) return false;
+  if (!(p->bin_target > 0.0f && p->bin_min_edge > 0.0f)) return false;
+  return true;
+}
+
+thread_local std::string g_init_error;
+
+}  // namespace
+
+struct tpc_ctx {
+  DevConst k;
+  tpc_params p;
+  tpc_geometry g;
+  hipStream_t stream;
+  uint8_t* ws;
+  size_t ws_bytes;
+  std::vector<SlotHost> slots;
+  std::string err;
+  bool prof = false;
+  bool prof_valid = false;
+  int prof_slot = -1;
+  hipEvent_t ev[TPC_N_STAGES + 1] = {};
+  int fail(int code, const std::string& m) {
+    err = m;
+    return code;
+  }
+};
+
+#define TPC_HIP(call)                                                         \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      return ctx->fail(TPC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define TPC_LAUNCHED()                                                        \
+  do {                                                                        \
+    hipError_t e_ = hipGetLastError();                                        \
+    if (e_ != hipSuccess)                                                     \
+      return ctx->fail(TPC_EDEVICE, std::string("launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+void mark(tpc_ctx* ctx, int i) {
+  if (ctx->prof) (void)hipEventRecord(ctx->ev[i], ctx->stream);
+}
+
+int grid_stride_blocks(int64_t n, int threads, int cap = 4096) {
+  const int64_t b = (n + threads - 1) / threads;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+int build_grid(tpc_ctx* ctx, SlotHost& h) {
+  Slot& s = h.d;
+  hipStream_t st = ctx->stream;
+  const int64_t SR = (int64_t)s.n_sectors * kRows;
+  k_zero_u32<<<grid_stride_blocks(SR, 256), 256, 0, st>>>(s.row_cnt, SR);
+  k_zero_u32<<<1, 64, 0, st>>>(s.err, 4);
+  k_zero_u32<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t*>(s.stats), 16);
+  k_count<<<grid_stride_blocks(h.n, 256), 256, 0, st>>>(s);
+  k_scan_rows<<<1, 1024, 0, st>>>(s, ctx->k);
+  k_scatter<<<grid_stride_blocks(h.n, 256), 256, 0, st>>>(s);
+  k_row_sort<<<(unsigned)SR, 256, 0, st>>>(s);
+  TPC_LAUNCHED();
+  h.state = 2;
+  return TPC_OK;
+}
+
+int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns) {
+  Slot& s = h.d;
+  hipStream_t st = ctx->stream;
+  // work estimate for the persistent grids (the exact counts live on the device)
+  const int64_t est = std::max<int64_t>(1, h.n / 3 * ns / s.n_sectors);
+  const int nb = grid_stride_blocks(est, 64, 4096);
+  k_neighbours<<<dim3(kRows, ns), 256, 0, st>>>(s, ctx->k, g0);
+  mark(ctx, 2);
+  k_clean_start<<<dim3(kRows, ns), 256, 0, st>>>(s, g0);
+  k_flatten<<<1, 1024, 0, st>>>(s.n_start, s.flat_tl, g0, ns);
+  mark(ctx, 3);
+  k_tracklets<<<nb, 64, 0, st>>>(s, ctx->k, g0, ns);
+  mark(ctx, 4);
+  k_weights<<<nb, 64, 0, st>>>(s, g0, ns);
+  k_select<<<nb, 64, 0, st>>>(s, ctx->k, g0, ns);
+  k_flatten<<<1, 1024, 0, st>>>(s.n_track, s.flat_tk, g0, ns);
+  mark(ctx, 5);
+  k_refit<<<nb, 64, 0, st>>>(s, ctx->k, g0, ns);
+  mark(ctx, 6);
+  TPC_LAUNCHED();
+  return TPC_OK;
+}
+
+void scan_u32(hipStream_t st, uint32_t* data, const uint32_t* n_dev, int64_t n_bound,
+              uint32_t* partial, uint32_t* total_out) {
+  const int nb = (int)std::max<int64_t>(1, (n_bound + kScanTile - 1) / kScanTile);
+  k_scan_tiles<<<nb, 256, 0, st>>>(data, n_dev, n_bound, partial);
+  k_scan_partials<<<1, 1024, 0, st>>>(partial, nb, data, n_dev, n_bound, total_out);
+  k_scan_apply<<<nb, 256, 0, st>>>(data, n_dev, n_bound, partial, data);
+}
+
+int finalize(tpc_ctx* ctx, SlotHost& h) {
+  Slot& s = h.d;
+  hipStream_t st = ctx->stream;
+  const int nbn = grid_stride_blocks(h.n, 256);
+  k_flags<<<nbn, 256, 0, st>>>(s);
+  scan_u32(st, s.scan_a, nullptr, h.n, s.scan_b, nullptr);
+  k_order<<<std::max(nbn, (h.n_events + 256) / 256), 256, 0, st>>>(s);
+  scan_u32(st, s.out_ntk, s.out_count, s.cap_tk, s.scan_b, s.out_count + 1);
+  k_event_hits<<<(h.n_events + 1 + 255) / 256, 256, 0, st>>>(s);
+  k_write_out<<<grid_stride_blocks(std::max<int64_t>(1, h.n / 50), 64), 64, 0, st>>>(s, ctx->k);
+  mark(ctx, 7);
+  TPC_LAUNCHED();
+  h.state = 4;
+  return TPC_OK;
+}
+
+int stage(tpc_ctx* ctx, int slot, int n_events, const int64_t* offs, const uint8_t* sector,
+          const uint8_t* row, const float* y, const float* z, int flags) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  if (n_events < 1 || n_events > ctx->p.max_events)
+    return ctx->fail(TPC_EINVAL, "number of events out of range");
+  if (!offs || offs[0] != 0) return ctx->fail(TPC_EINVAL, "event offsets must start at 0");
+  for (int e = 0; e < n_events; ++e) {
+    if (offs[e + 1] < offs[e]) return ctx->fail(TPC_EINVAL, "event offsets decrease");
+    if (offs[e + 1] - offs[e] > (int64_t)(1 << 24))
+      return ctx->fail(TPC_EINVAL, "more than 2^24 clusters in one event");
+  }
+  const int64_t n = offs[n_events];
+  if (n > ctx->p.max_clusters) return ctx->fail(TPC_ENOMEM, "more clusters than max_clusters");
+  if (n > 0 && (!sector || !row || !y || !z)) return ctx->fail(TPC_EINVAL, "null cluster array");
+  if (flags != TPC_HOST && flags != TPC_DEVICE) return ctx->fail(TPC_EINVAL, "flags must be TPC_HOST or TPC_DEVICE");
+  SlotHost& h = ctx->slots[slot];
+  Slot& s = h.d;
+  hipStream_t st = ctx->stream;
+  h.n = n;
+  h.n_events = n_events;
+  h.ev_off.assign(offs, offs + n_events + 1);
+  s.n = n;
+  s.n_events = n_events;
+  s.n_sectors = n_events * kSectorsPerEvent;
+  if (flags == TPC_DEVICE) {
+    s.sector = sector;
+    s.row = row;
+    s.y = y;
+    s.z = z;
+  } else {
+    TPC_HIP(hipMemcpyAsync(h.own_sector, sector, n, hipMemcpyHostToDevice, st));
+    TPC_HIP(hipMemcpyAsync(h.own_row, row, n, hipMemcpyHostToDevice, st));
+    TPC_HIP(hipMemcpyAsync(h.own_y, y, n * 4, hipMemcpyHostToDevice, st));
+    TPC_HIP(hipMemcpyAsync(h.own_z, z, n * 4, hipMemcpyHostToDevice, st));
+    s.sector = h.own_sector;
+    s.row = h.own_row;
+    s.y = h.own_y;
+    s.z = h.own_z;
+  }
+  TPC_HIP(hipMemcpyAsync(s.ev_off, h.ev_off.data(), (n_events + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice, st));
+  h.state = 1;
+  return TPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tpc_params_default(tpc_params* p) {
+  if (!p) return TPC_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->nf_window = 3.0f;
+  p->nf_mmax = 16.0f;
+  p->chi2_max = 16.0f;
+  p->k_win = 4.0f;
+  p->w_max = 5.0f;
+  p->s_max = 0.95f;
+  p->c_s0 = 1.0f;
+  p->c_t0 = 1.0f;
+  p->c_q0 = 100.0f;
+  p->m_edge = 1.0f;
+  p->m_z = 1.0f;
+  p->n_gap = 6;
+  p->n_min_tracklet = 10;
+  p->n_min_track = 10;
+  p->bin_target = 2.0f;
+  p->bin_min_edge = 2.0f;
+  p->max_slots = 1;
+  p->max_events = 1;
+  p->max_clusters = 4 << 20;
+  return TPC_OK;
+}
+
+size_t tpc_workspace_bytes(const tpc_params* p) {
+  if (!params_ok(p)) return 0;
+  Carver c{nullptr, 0, true};
+  for (int i = 0; i < p->max_slots; ++i) {
+    Slot s{};
+    carve_slot(c, *p, s, nullptr);
+  }
+  return c.off + 256;
+}
+
+int tpc_init_geometry(tpc_ctx** out, const tpc_geometry* g, const tpc_params* p, void* dev_workspace,
+                      size_t ws_bytes, void* hip_stream) {
+  g_init_error.clear();
+  if (!out || !g || !p) {
+    g_init_error = "null argument";
+    return TPC_EINVAL;
+  }
+  *out = nullptr;
+  if (g->n_sectors != TPC_N_SECTORS || g->n_rows != TPC_N_ROWS) {
+    g_init_error = "geometry must have 36 sectors of 159 pad rows";
+    return TPC_EINVAL;
+  }
+  for (int r = 0; r < TPC_N_ROWS; ++r) {
+    if (!(std::isfinite(g->row_x[r]) && g->row_x[r] > 0.0f) ||
+        (r > 0 && !(g->row_x[r] > g->row_x[r - 1]))) {
+      g_init_error = "pad-row radii must be positive and increasing";
+      return TPC_EINVAL;
+    }
+  }
+  if (!(g->z_max > 0.0f && g->tan_half_angle > 0.0f && g->sigma_y0 > 0.0f && g->sigma_z0 > 0.0f &&
+        g->sigma_y1 >= 0.0f && g->sigma_z1 >= 0.0f && std::isfinite(g->bz_tesla))) {
+    g_init_error = "bad geometry constants";
+    return TPC_EINVAL;
+  }
+  if (!params_ok(p)) {
+    g_init_error = "bad params";
+    return TPC_EINVAL;
+  }
+  const size_t need = tpc_workspace_bytes(p);
+  if (!dev_workspace || ws_bytes < need) {
+    g_init_error = "workspace too small: need " + std::to_string(need) + " bytes";
+    return TPC_ENOMEM;
+  }
+  tpc_ctx* ctx = new tpc_ctx();
+  ctx->p = *p;
+  ctx->g = *g;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  ctx->ws = reinterpret_cast<uint8_t*>(dev_workspace);
+  ctx->ws_bytes = ws_bytes;
+  DevConst& k = ctx->k;
+  std::memset(&k, 0, sizeof(k));
+  for (int r = 0; r < kRows; ++r) k.row_x[r] = g->row_x[r];
+  k.tanh_half = g->tan_half_angle;
+  k.z_max = g->z_max;
+  k.sy0 = g->sigma_y0;
+  k.sy1 = g->sigma_y1;
+  k.sz0 = g->sigma_z0;
+  k.sz1 = g->sigma_z1;
+  // curvature per unit q/pT: d(phi)/dl = b q/pT, b = -c Bz, c = 0.00299792458 GeV/(T cm)
+  k.bd = -0.00299792458 * (double)g->bz_tesla;
+  k.b = (float)k.bd;
+  k.nf_w = p->nf_window;
+  k.nf_mmax = p->nf_mmax;
+  k.chi2max = p->chi2_max;
+  k.kwin = p->k_win;
+  k.wmax = p->w_max;
+  k.smax = p->s_max;
+  k.cs0 = p->c_s0;
+  k.ct0 = p->c_t0;
+  k.cq0 = p->c_q0;
+  k.medge = p->m_edge;
+  k.mz = p->m_z;
+  k.n_gap = p->n_gap;
+  k.n_min_tracklet = p->n_min_tracklet;
+  k.n_min_track = p->n_min_track;
+  k.bin_target = p->bin_target;
+  k.bin_min_edge = p->bin_min_edge;
+  Carver c{ctx->ws, 0, false};
+  ctx->slots.resize(p->max_slots);
+  for (int i = 0; i < p->max_slots; ++i) carve_slot(c, *p, ctx->slots[i].d, &ctx->slots[i]);
+  *out = ctx;
+  return TPC_OK;
+}
+
+int tpc_load_clusters(tpc_ctx* ctx, int slot, const uint8_t* sector, const uint8_t* row,
+                      const float* y, const float* z, const float* q, int64_t n, int flags) {
+  (void)q;
+  if (!ctx) return TPC_EINVAL;
+  if (n < 0) return ctx->fail(TPC_EINVAL, "negative cluster count");
+  const int64_t offs[2] = {0, n};
+  return stage(ctx, slot, 1, offs, sector, row, y, z, flags);
+}
+
+int tpc_load_batch(tpc_ctx* ctx, int slot, int n_events, const int64_t* event_offsets,
+                   const uint8_t* sector, const uint8_t* row, const float* y, const float* z,
+                   const float* q, int flags) {
+  (void)q;
+  return stage(ctx, slot, n_events, event_offsets, sector, row, y, z, flags);
+}
+
+int tpc_track_sector(tpc_ctx* ctx, int slot, int sector) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  SlotHost& h = ctx->slots[slot];
+  if (h.state < 1 || h.state == 4) return ctx->fail(TPC_ESTATE, "slot not staged or already final");
+  if (sector < 0 || sector >= h.d.n_sectors) return ctx->fail(TPC_EINVAL, "sector out of range");
+  if (h.state < 2) {
+    const int rc = build_grid(ctx, h);
+    if (rc) return rc;
+  }
+  const int rc = track_range(ctx, h, sector, 1);
+  if (rc) return rc;
+  h.state = 3;
+  return TPC_OK;
+}
+
+int tpc_track_event(tpc_ctx* ctx, int slot) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  SlotHost& h = ctx->slots[slot];
+  if (h.state < 1 || h.state >= 3) return ctx->fail(TPC_ESTATE, "slot not staged or already tracked");
+  mark(ctx, 0);
+  if (h.state < 2) {
+    const int rc = build_grid(ctx, h);
+    if (rc) return rc;
+  }
+  mark(ctx, 1);
+  int rc = track_range(ctx, h, 0, h.d.n_sectors);
+  if (rc) return rc;
+  rc = finalize(ctx, h);
+  if (rc) return rc;
+  ctx->prof_valid = ctx->prof;
+  ctx->prof_slot = slot;
+  return TPC_OK;
+}
+
+int tpc_set_profiling(tpc_ctx* ctx, int enable) {
+  if (!ctx) return TPC_EINVAL;
+  if (enable && !ctx->ev[0]) {
+    for (int i = 0; i <= TPC_N_STAGES; ++i) TPC_HIP(hipEventCreate(&ctx->ev[i]));
+  }
+  ctx->prof = enable != 0;
+  ctx->prof_valid = false;
+  return TPC_OK;
+}
+
+int tpc_get_profile(tpc_ctx* ctx, double* ms, uint64_t* counters) {
+  if (!ctx) return TPC_EINVAL;
+  if (!ctx->prof_valid || ctx->prof_slot < 0) return ctx->fail(TPC_ESTATE, "nothing profiled");
+  SlotHost& h = ctx->slots[ctx->prof_slot];
+  TPC_HIP(hipStreamSynchronize(ctx->stream));
+  if (ms) {
+    for (int i = 0; i < TPC_N_STAGES; ++i) {
+      float t = 0.0f;
+      TPC_HIP(hipEventElapsedTime(&t, ctx->ev[i], ctx->ev[i + 1]));
+      ms[i] = t;
+    }
+  }
+  if (counters) {
+    unsigned long long st[8];
+    TPC_HIP(hipMemcpy(st, h.d.stats, sizeof(st), hipMemcpyDeviceToHost));
+    uint32_t sorted = 0;
+    TPC_HIP(hipMemcpy(&sorted, h.d.row_off + (size_t)h.d.n_sectors * kRows, 4, hipMemcpyDeviceToHost));
+    for (int i = 0; i < 8; ++i) counters[i] = st[i];
+    counters[4] = (uint64_t)h.n;
+    counters[5] = sorted;
+  }
+  return TPC_OK;
+}
+
+int tpc_device_results(tpc_ctx* ctx, int slot, const tpc_track** tracks, const int32_t** hit_ids,
+                       const uint32_t** event_track_off, const uint32_t** event_hit_off,
+                       const uint32_t** totals) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  SlotHost& h = ctx->slots[slot];
+  if (h.state == 3) {
+    const int rc = finalize(ctx, h);
+    if (rc) return rc;
+  }
+  if (h.state != 4) return ctx->fail(TPC_ESTATE, "slot not tracked");
+  if (tracks) *tracks = h.d.out_tracks;
+  if (hit_ids) *hit_ids = h.d.out_hits;
+  if (event_track_off) *event_track_off = h.d.ev_track_off;
+  if (event_hit_off) *event_hit_off = h.d.ev_hit_off;
+  if (totals) *totals = h.d.out_count;
+  return TPC_OK;
+}
+
+int tpc_get_tracks(tpc_ctx* ctx, int slot, int event, tpc_track* out, int64_t max_tracks,
+                   int32_t* hit_ids, int64_t max_hits, int64_t* n_tracks, int64_t* n_hits) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  SlotHost& h = ctx->slots[slot];
+  if (event < 0 || event >= std::max(1, h.n_events)) return ctx->fail(TPC_EINVAL, "event out of range");
+  if (max_tracks < 0 || max_hits < 0) return ctx->fail(TPC_EINVAL, "negative buffer size");
+  if ((max_tracks > 0 && !out) || (max_hits > 0 && !hit_ids))
+    return ctx->fail(TPC_EINVAL, "null output buffer");
+  if (h.state == 3) {
+    const int rc = finalize(ctx, h);
+    if (rc) return rc;
+  }
+  if (h.state != 4) return ctx->fail(TPC_ESTATE, "slot not tracked");
+  hipStream_t st = ctx->stream;
+  uint32_t err[4], toff[2], hoff[2];
+  TPC_HIP(hipMemcpyAsync(err, h.d.err, sizeof(err), hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipMemcpyAsync(toff, h.d.ev_track_off + event, sizeof(toff), hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipMemcpyAsync(hoff, h.d.ev_hit_off + event, sizeof(hoff), hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipStreamSynchronize(st));
+  if (err[0]) return ctx->fail(TPC_EINVAL, std::to_string(err[0]) + " invalid clusters (sector, row or coordinates)");
+  if (err[1]) return ctx->fail(TPC_EINVAL, "a pad row holds more than 4096 clusters");
+  if (err[2]) return ctx->fail(TPC_EDEVICE, "internal capacity exceeded");
+  const int64_t nt = (int64_t)toff[1] - toff[0];
+  const int64_t nh = (int64_t)hoff[1] - hoff[0];
+  if (n_tracks) *n_tracks = nt;
+  if (n_hits) *n_hits = nh;
+  if (nt > max_tracks || nh > max_hits) return ctx->fail(TPC_EOVERFLOW, "output buffers too small");
+  if (nt) TPC_HIP(hipMemcpyAsync(out, h.d.out_tracks + toff[0], nt * sizeof(tpc_track), hipMemcpyDeviceToHost, st));
+  if (nh) TPC_HIP(hipMemcpyAsync(hit_ids, h.d.out_hits + hoff[0], nh * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipStreamSynchronize(st));
+  return TPC_OK;
+}
+
+int tpc_get_links(tpc_ctx* ctx, int slot, int event, int32_t* up, int32_t* dn, int32_t* up_clean,
+                  int32_t* dn_clean) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  SlotHost& h = ctx->slots[slot];
+  if (h.state < 3) return ctx->fail(TPC_ESTATE, "slot not tracked");
+  if (event < 0 || event >= h.n_events) return ctx->fail(TPC_EINVAL, "event out of range");
+  const int64_t ne = h.ev_off[event + 1] - h.ev_off[event];
+  hipStream_t st = ctx->stream;
+  int32_t* tmp[4] = {reinterpret_cast<int32_t*>(h.d.rank), reinterpret_cast<int32_t*>(h.d.ty),
+                     reinterpret_cast<int32_t*>(h.d.tz), reinterpret_cast<int32_t*>(h.d.tid)};
+  for (int k = 0; k < 4; ++k) k_fill_i32<<<grid_stride_blocks(ne, 256), 256, 0, st>>>(tmp[k], ne, -1);
+  k_links_out<<<grid_stride_blocks(ne, 256), 256, 0, st>>>(h.d, event, tmp[0], tmp[1], tmp[2], tmp[3]);
+  TPC_LAUNCHED();
+  int32_t* dst[4] = {up, dn, up_clean, dn_clean};
+  for (int k = 0; k < 4; ++k)
+    if (dst[k] && ne) TPC_HIP(hipMemcpyAsync(dst[k], tmp[k], ne * 4, hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipStreamSynchronize(st));
+  return TPC_OK;
+}
+
+int tpc_kf_step_f32(tpc_ctx* ctx, float* state, const float* dx, const float* meas, float* result,
+                    int64_t n) {
+  if (!ctx) return TPC_EINVAL;
+  if (n < 0 || (n > 0 && (!state || !dx || !meas || !result)))
+    return ctx->fail(TPC_EINVAL, "bad arguments");
+  if (n == 0) return TPC_OK;
+  k_kf_step<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(ctx->k, state, dx, meas, result, n);
+  TPC_LAUNCHED();
+  return TPC_OK;
+}
+
+const char* tpc_last_error(const tpc_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+int tpc_destroy(tpc_ctx* ctx) {
+  if (!ctx) return TPC_EINVAL;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (int i = 0; i <= TPC_N_STAGES; ++i)
+    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  delete ctx;
+  return TPC_OK;
+}
+
+}  // extern "C"

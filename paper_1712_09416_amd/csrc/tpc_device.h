@@ -1,0 +1,324 @@
+// Device-side building blocks of the TPC sector tracker for gfx950:
+// slot layout, pad-row bin geometry and the Kalman-filter transport/update.
+//
+// Method (paper, Abstract and Section 2): track finding by a cellular
+// automaton over pad-row hits followed by Kalman-filter track following.
+// The paper gives no formulas; the arithmetic below is the project's written
+// definition of those steps (helix in the local sector frame, state
+// (y, z, sin phi, tan lambda, q/pT) at the pad-row x).  Float decisions are
+// bit-reproducible against a CPU evaluation in the same operation order:
+// every kernel is built with -ffp-contract=off and correctly rounded
+// division and square root, and each expression below is evaluated left to
+// right exactly as written.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tpcca.h"
+
+namespace tpc {
+
+constexpr int kRows = 159;
+constexpr int kSectorsPerEvent = 36;
+constexpr int kMaxRowHits = 4096;         // LDS sort capacity of one pad row
+constexpr uint32_t kNoHit = 0xFFFFFFFFu;
+
+// ---------------------------------------------------------------------------
+// constants handed to every kernel by value
+// ---------------------------------------------------------------------------
+struct DevConst {
+  float row_x[kRows + 1];
+  float tanh_half;
+  float z_max;
+  float sy0, sy1, sz0, sz1;
+  float b;          // curvature per unit q/pT, float
+  double bd;        // same, double (refit)
+  float nf_w, nf_mmax, chi2max, kwin, wmax, smax, cs0, ct0, cq0, medge, mz;
+  int n_gap, n_min_tracklet, n_min_track;
+  float bin_target;  // clusters per grid bin aimed at
+  float bin_min_edge;
+};
+
+// per (sector, row) grid description
+struct RowBins {
+  float y0, z0, iby, ibz;   // lower edges and inverse bin sizes
+  int32_t ny, nz;           // bins in y and z
+  int32_t base;             // first entry of this row in bin_off
+  int32_t pad;
+};
+
+// One slot: a batch of events whose clusters are concatenated; sector g of
+// the slot is sector g % 36 of event g / 36.
+struct Slot {
+  // input (caller device memory, or the slot's own copy)
+  const uint8_t* sector;
+  const uint8_t* row;
+  const float* y;
+  const float* z;
+  int64_t* ev_off;          // [E+1] cluster offsets of the events
+  int32_t n_events;
+  int32_t n_sectors;        // 36 * n_events
+  int64_t n;                // clusters
+  // grid
+  uint32_t* row_cnt;        // [SR]
+  uint32_t* row_off;        // [SR+1] first sorted hit of each (sector, row)
+  RowBins* bins;            // [SR]
+  uint32_t* bin_off;        // [n + SR + 1]
+  uint32_t* rank;           // [n]
+  float* ty;                // [n] row-ordered, unsorted within a row
+  float* tz;
+  uint32_t* tid;
+  float* hy;                // [n] sorted by (sector, row, bin, id)
+  float* hz;
+  uint32_t* hid;            // global cluster index of each sorted hit
+  // links (sorted-hit indices, -1 none)
+  int32_t* up;
+  int32_t* dn;
+  int32_t* upc;
+  int32_t* dnc;
+  // per-sector regions: starts / tracklets and tracks
+  uint32_t* tl_base;        // [S+1] tracklet region of each sector
+  uint32_t* tk_base;        // [S+1] track region of each sector
+  uint32_t* n_start;        // [S]
+  uint32_t* n_track;        // [S]
+  uint32_t* flat_tl;        // [S+1] prefix of n_start over the launched range
+  uint32_t* flat_tk;        // [S+1] prefix of n_track over the launched range
+  int32_t* start_hit;       // [tl capacity] sorted index of the start hit
+  // tracklets
+  int32_t* tl_hits;         // [tl capacity][kRows] sorted index per row, -1 none
+  int32_t* tl_info;         // [tl capacity][4]: n, row_in, row_out, valid
+  uint32_t* tl_weight;      // [tl capacity]
+  float* tl_state;          // [tl capacity][5] inner state (y, z, s, T, Q)
+  uint32_t* weight;         // [n] per sorted hit, 0 = unowned
+  // tracks (temporary, per-sector regions)
+  int32_t* tk_tracklet;     // [tk capacity]
+  int32_t* tk_info;         // [tk capacity][4]: ok, n, row_in, row_out
+  double* tk_par;           // [tk capacity][5]
+  double* tk_cov;           // [tk capacity][15]
+  double* tk_chi2;          // [tk capacity]
+  // canonical order
+  int32_t* tmap;            // [n] per global cluster: temp track whose innermost hit it is
+  uint32_t* scan_a;         // [n+1] scratch for the device scans
+  uint32_t* scan_b;         // [block partials]
+  uint32_t* out_count;      // [2]: tracks, hits of the slot
+  uint32_t* out_ntk;        // [tk capacity+1] hit counts in canonical order, then offsets
+  int32_t* out_order;       // [tk capacity] temporary track of each canonical position
+  tpc_track* out_tracks;    // [tk capacity]
+  int32_t* out_hits;        // [n]
+  uint32_t* ev_track_off;   // [E+1]
+  uint32_t* ev_hit_off;     // [E+1]
+  uint32_t* err;            // [4]: invalid clusters, dense rows, overflow, spare
+  unsigned long long* stats; // [8] work counters (see tpc_get_profile)
+  // capacities
+  int64_t cap_n;
+  int64_t cap_tl;
+  int64_t cap_tk;
+  int32_t cap_e;
+};
+
+// ---------------------------------------------------------------------------
+// pad-row bins: monotone in y and z, identical in every kernel
+// ---------------------------------------------------------------------------
+// (a NaN coordinate maps to bin 0: every index stays inside the row)
+__device__ __forceinline__ int bin_y(const RowBins& b, float y) {
+  const float f = (y - b.y0) * b.iby;
+  return f >= 0.0f ? (int)fminf(f, (float)(b.ny - 1)) : 0;
+}
+__device__ __forceinline__ int bin_z(const RowBins& b, float z) {
+  const float f = (z - b.z0) * b.ibz;
+  return f >= 0.0f ? (int)fminf(f, (float)(b.nz - 1)) : 0;
+}
+
+__device__ __forceinline__ float sigma_y(const DevConst& k, float z) {
+  return k.sy0 + k.sy1 * fabsf(z) / k.z_max;
+}
+__device__ __forceinline__ float sigma_z(const DevConst& k, float z) {
+  return k.sz0 + k.sz1 * fabsf(z) / k.z_max;
+}
+
+// ---------------------------------------------------------------------------
+// Kalman filter on the helix state.  Template over float (tracklet phases,
+// which take decisions) and double (the output refit).
+// Covariance packed as the lower triangle of (y, z, s, T, Q):
+//   0:yy 1:zy 2:zz 3:sy 4:sz 5:ss 6:Ty 7:Tz 8:Ts 9:TT 10:Qy 11:Qz 12:Qs 13:QT 14:QQ
+// ---------------------------------------------------------------------------
+// sum over the wave, then one atomic per wave (all 64 lanes must call)
+__device__ __forceinline__ void wave_add_u64(unsigned long long* dst, unsigned long long v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
+}
+
+template <class F>
+struct Helix {
+  F y, z, s, t, q;
+  F c[15];
+};
+
+template <class F> __device__ __forceinline__ F fabs_(F v);
+template <> __device__ __forceinline__ float fabs_(float v) { return fabsf(v); }
+template <> __device__ __forceinline__ double fabs_(double v) { return fabs(v); }
+template <class F> __device__ __forceinline__ F sqrt_(F v);
+template <> __device__ __forceinline__ float sqrt_(float v) { return sqrtf(v); }
+template <> __device__ __forceinline__ double sqrt_(double v) { return sqrt(v); }
+
+// Move the state by dx along the circle of curvature b*q.  sin(phi) grows
+// linearly with x; y advances by dx times the tangent of the mid-angle
+// (N/D below); z advances by T times the arc, the arc being the chord
+// times asin(u)/u = 1 + u^2/6 + 3u^4/40 (u = half chord * curvature).
+// Returns false, leaving the state untouched, if |sin phi| would pass smax.
+template <class F>
+__device__ __forceinline__ bool transport(Helix<F>& h, F dx, F b, F smax) {
+  const F one = F(1), half = F(0.5), two = F(2);
+  const F bq = b * h.q;
+  const F s1 = h.s + bq * dx;
+  if (!(fabs_(s1) <= smax)) return false;
+  const F s0 = h.s;
+  const F c0 = sqrt_(one - s0 * s0);
+  const F c1 = sqrt_(one - s1 * s1);
+  const F N = s0 + s1;
+  const F D = c0 + c1;
+  const F tmid = N / D;
+  const F chord = fabs_(dx) * sqrt_(one + tmid * tmid);
+  const F u = half * bq * chord;
+  const F u2 = u * u;
+  F arc = chord * (one + u2 * (one / F(6) + u2 * (F(3) / F(40))));
+  if (dx < F(0)) arc = -arc;
+
+  const F D2 = D * D;
+  const F r0 = s0 / c0;
+  const F r1 = s1 / c1;
+  const F dy_ds = dx * (two * D + N * (r0 + r1)) / D2;
+  const F dy_dq = b * dx * dx * (D + N * r1) / D2;
+  const F dz_ds = h.t * dx * N / (c0 * c1 * D);
+  const F dz_dt = arc;
+  const F sm = half * N;
+  const F cm = sqrt_(one - sm * sm);
+  const F dz_dq = h.t * b * sm * dx * dx / (two * cm * cm * cm);
+  const F ds_dq = b * dx;
+
+  h.y = h.y + dx * tmid;
+  h.z = h.z + h.t * arc;
+  h.s = s1;
+
+  F* c = h.c;
+  const F yy = c[0], zy = c[1], zz = c[2], sy = c[3], sz = c[4], ss = c[5];
+  const F ty = c[6], tz = c[7], ts = c[8], tt = c[9];
+  const F qy = c[10], qz = c[11], qs = c[12], qt = c[13], qq = c[14];
+
+  // rows y, z, s of J*C
+  const F jy_y = yy + dy_ds * sy + dy_dq * qy;
+  const F jy_s = sy + dy_ds * ss + dy_dq * qs;
+  const F jy_q = qy + dy_ds * qs + dy_dq * qq;
+  const F jz_y = zy + dz_ds * sy + dz_dt * ty + dz_dq * qy;
+  const F jz_z = zz + dz_ds * sz + dz_dt * tz + dz_dq * qz;
+  const F jz_s = sz + dz_ds * ss + dz_dt * ts + dz_dq * qs;
+  const F jz_t = tz + dz_ds * ts + dz_dt * tt + dz_dq * qt;
+  const F jz_q = qz + dz_ds * qs + dz_dt * qt + dz_dq * qq;
+  const F js_y = sy + ds_dq * qy;
+  const F js_z = sz + ds_dq * qz;
+  const F js_s = ss + ds_dq * qs;
+  const F js_t = ts + ds_dq * qt;
+  const F js_q = qs + ds_dq * qq;
+
+  // (J*C)*J^T, lower triangle
+  c[0] = jy_y + dy_ds * jy_s + dy_dq * jy_q;
+  c[1] = jz_y + dy_ds * jz_s + dy_dq * jz_q;
+  c[2] = jz_z + dz_ds * jz_s + dz_dt * jz_t + dz_dq * jz_q;
+  c[3] = js_y + dy_ds * js_s + dy_dq * js_q;
+  c[4] = js_z + dz_ds * js_s + dz_dt * js_t + dz_dq * js_q;
+  c[5] = js_s + ds_dq * js_q;
+  c[6] = ty + dy_ds * ts + dy_dq * qt;
+  c[7] = tz + dz_ds * ts + dz_dt * tt + dz_dq * qt;
+  c[8] = ts + ds_dq * qt;
+  c[10] = qy + dy_ds * qs + dy_dq * qq;
+  c[11] = qz + dz_ds * qs + dz_dt * qt + dz_dq * qq;
+  c[12] = qs + ds_dq * qq;
+  return true;
+}
+
+// Inverse of the 2x2 residual covariance S = C_(y,z) + diag(vy, vz).
+template <class F>
+struct Resid {
+  F w00, w01, w11, s00, s11;
+};
+
+template <class F>
+__device__ __forceinline__ Resid<F> resid_weights(const Helix<F>& h, F vy, F vz) {
+  Resid<F> r;
+  const F s00 = h.c[0] + vy;
+  const F s01 = h.c[1];
+  const F s11 = h.c[2] + vz;
+  const F det = s00 * s11 - s01 * s01;
+  const F inv = F(1) / det;
+  r.w00 = s11 * inv;
+  r.w01 = -s01 * inv;
+  r.w11 = s00 * inv;
+  r.s00 = s00;
+  r.s11 = s11;
+  return r;
+}
+
+template <class F>
+__device__ __forceinline__ F chi2_of(const Resid<F>& w, F ry, F rz) {
+  return ry * (w.w00 * ry + w.w01 * rz) + rz * (w.w01 * ry + w.w11 * rz);
+}
+
+// Kalman update with the measurement (my, mz).  gated: refuse (state
+// untouched) when chi2 > chi2max, a variance would not stay positive or
+// |sin phi| would reach smax.
+template <class F>
+__device__ __forceinline__ bool kalman_update(Helix<F>& h, F my, F mz, F vy, F vz, F chi2max,
+                                              F smax, bool gated, F* chi2_out) {
+  const Resid<F> w = resid_weights(h, vy, vz);
+  const F ry = my - h.y;
+  const F rz = mz - h.z;
+  const F chi2 = chi2_of(w, ry, rz);
+  *chi2_out = chi2;
+  if (gated && !(chi2 <= chi2max)) return false;
+  const F* c = h.c;
+  // covariance column of each state entry with y and with z
+  const F cy[5] = {c[0], c[1], c[3], c[6], c[10]};
+  const F cz[5] = {c[1], c[2], c[4], c[7], c[11]};
+  F ky[5], kz[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    ky[i] = cy[i] * w.w00 + cz[i] * w.w01;
+    kz[i] = cy[i] * w.w01 + cz[i] * w.w11;
+  }
+  Helix<F> o;
+  o.y = h.y + (ky[0] * ry + kz[0] * rz);
+  o.z = h.z + (ky[1] * ry + kz[1] * rz);
+  o.s = h.s + (ky[2] * ry + kz[2] * rz);
+  o.t = h.t + (ky[3] * ry + kz[3] * rz);
+  o.q = h.q + (ky[4] * ry + kz[4] * rz);
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+#pragma unroll
+    for (int j = 0; j <= i; ++j, ++k) o.c[k] = c[k] - (ky[i] * cy[j] + kz[i] * cz[j]);
+  }
+  if (gated) {
+    if (!(o.c[0] > F(0) && o.c[2] > F(0) && o.c[5] > F(0) && o.c[9] > F(0) && o.c[14] > F(0) &&
+          fabs_(o.s) < smax))
+      return false;
+  }
+  h = o;
+  return true;
+}
+
+// Prior covariance: measurement variances in y and z at the hit, wide
+// diagonal for the angles and the curvature.
+template <class F>
+__device__ __forceinline__ void reset_cov(Helix<F>& h, F vy, F vz, F cs0, F ct0, F cq0) {
+#pragma unroll
+  for (int i = 0; i < 15; ++i) h.c[i] = F(0);
+  h.c[0] = vy;
+  h.c[2] = vz;
+  h.c[5] = cs0;
+  h.c[9] = ct0;
+  h.c[14] = cq0;
+}
+
+}  // namespace tpc

@@ -1,0 +1,218 @@
+// a5: tracklet construction (paper, Abstract: Kalman-filter track
+// following).  One lane per start hit, float arithmetic; the lane's state
+// and per-row decisions live in registers, its hit list in global memory
+// (row-indexed, written only for the rows the lane visits).
+#include "tpc_device.h"
+#include "tpc_kernels.h"
+
+namespace tpc {
+
+template <class Fn>
+__device__ __forceinline__ void for_window_t(const Slot& S, int sr, float yc, float zc, float wy,
+                                             float wz, Fn&& fn) {
+  const RowBins b = S.bins[sr];
+  const float eps = 1e-3f;
+  const int iy0 = bin_y(b, yc - wy - eps), iy1 = bin_y(b, yc + wy + eps);
+  const int iz0 = bin_z(b, zc - wz - eps), iz1 = bin_z(b, zc + wz + eps);
+  for (int iz = iz0; iz <= iz1; ++iz) {
+    const int first = b.base + iz * b.ny;
+    const uint32_t p0 = S.bin_off[first + iy0];
+    const uint32_t p1 = S.bin_off[first + iy1 + 1];
+    for (uint32_t p = p0; p < p1; ++p) fn(p);
+  }
+}
+
+// Stop rules after a transport to row r: left the sector sideways, crossed
+// the membrane, or left the drift volume.
+__device__ __forceinline__ bool inside(const DevConst& K, const Helix<float>& h, int r, bool side_c) {
+  if (!(fabsf(h.y) <= K.row_x[r] * K.tanh_half + K.medge)) return false;
+  if (!(fabsf(h.z) <= K.z_max + K.mz)) return false;
+  if (side_c ? (h.z > K.mz) : (h.z < -K.mz)) return false;
+  return true;
+}
+
+// Best hit of row sr for the predicted state: inside
+// |r_y| <= min(k sqrt(S_yy), w_max), |r_z| <= min(k sqrt(S_zz), w_max),
+// smallest chi2, ties to the smaller cluster ID.  -1 if none.
+__device__ __forceinline__ int32_t search_row(const Slot& S, const DevConst& K, int sr,
+                                              const Helix<float>& h, float vy, float vz,
+                                              unsigned& examined) {
+  const Resid<float> w = resid_weights(h, vy, vz);
+  float wy = K.kwin * sqrtf(w.s00);
+  if (wy > K.wmax) wy = K.wmax;
+  float wz = K.kwin * sqrtf(w.s11);
+  if (wz > K.wmax) wz = K.wmax;
+  const float yc = h.y, zc = h.z;
+  int32_t best = -1;
+  float bchi = 0.0f;
+  uint32_t bid = 0;
+  for_window_t(S, sr, yc, zc, wy, wz, [&](uint32_t p) {
+    ++examined;
+    const float ry = S.hy[p] - yc, rz = S.hz[p] - zc;
+    if (!(fabsf(ry) <= wy && fabsf(rz) <= wz)) return;
+    const float ch = chi2_of(w, ry, rz);
+    const uint32_t id = S.hid[p];
+    if (best < 0 || ch < bchi || (ch == bchi && id < bid)) {
+      best = (int32_t)p;
+      bchi = ch;
+      bid = id;
+    }
+  });
+  return best;
+}
+
+__device__ __forceinline__ bool try_hit(const Slot& S, const DevConst& K, Helix<float>& h, int32_t p,
+                                        float vy, float vz) {
+  float ch;
+  return kalman_update(h, S.hy[p], S.hz[p], vy, vz, K.chi2max, K.smax, true, &ch);
+}
+
+__device__ __forceinline__ int row_of(const uint32_t* row_off, int g, uint32_t p) {
+  int lo = 0, hi = kRows - 1;
+  const uint32_t* ro = row_off + g * kRows;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ro[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int flat_find(const uint32_t* flat, int ns, uint32_t t) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (flat[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// For each start hit h0 (row r0) with cleaned up-link h1:
+//  seed  (y, z) = h0, sin phi and tan lambda from h0 -> h1, q/pT = 0, prior
+//        covariance (hit variances, wide angles and curvature);
+//  out   rows r0+1..158: transport, stop rules; follow the cleaned chain while
+//        its hits pass the gate, then (for good) take the best-chi2 hit of
+//        each row's window; stop after n_gap consecutive rows without hit;
+//  in    restart at the outermost hit with the prior covariance and the
+//        outward (s, T, Q); rows down to 0: re-confirm the outward hit, else
+//        search; same gap rule.  The inward hits form the tracklet.
+__global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0, int ns) {
+  const uint32_t total = S.flat_tl[ns];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  unsigned visits = 0, examined = 0, done = 0;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+    ++done;
+    const int gi = flat_find(S.flat_tl, ns, t);
+    const int g = g0 + gi;
+    const uint32_t T = S.tl_base[g] + (t - S.flat_tl[gi]);
+    const bool side_c = (g % kSectorsPerEvent) >= kSectorsPerEvent / 2;
+    const int64_t ev0 = S.ev_off[g / kSectorsPerEvent];
+    const int32_t p0 = S.start_hit[T];
+    const int r0 = row_of(S.row_off, g, (uint32_t)p0);
+    const int32_t p1 = S.upc[p0];
+    int32_t* hits = S.tl_hits + (size_t)T * kRows;
+
+    Helix<float> st;
+    {
+      const float dx = K.row_x[r0 + 1] - K.row_x[r0];
+      const float dy = S.hy[p1] - S.hy[p0];
+      const float dz = S.hz[p1] - S.hz[p0];
+      const float L = sqrtf(dx * dx + dy * dy);
+      st.y = S.hy[p0];
+      st.z = S.hz[p0];
+      st.s = dy / L;
+      st.t = dz / L;
+      st.q = 0.0f;
+      const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
+      reset_cov(st, sy * sy, sz * sz, K.cs0, K.ct0, K.cq0);
+    }
+    hits[r0] = p0;
+
+    // outward
+    Helix<float> last = st;
+    int rout = r0;
+    int32_t cur = p0;
+    bool chain = true;
+    int miss = 0;
+    for (int r = r0 + 1; r < kRows; ++r) {
+      ++visits;
+      if (!transport(st, K.row_x[r] - K.row_x[r - 1], K.b, K.smax)) break;
+      if (!inside(K, st, r, side_c)) break;
+      const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
+      const float vy = sy * sy, vz = sz * sz;
+      int32_t got = -1;
+      if (chain) {
+        const int32_t nx = S.upc[cur];
+        if (nx >= 0 && try_hit(S, K, st, nx, vy, vz)) got = nx;
+        else chain = false;
+      }
+      if (got < 0) {
+        const int32_t bh = search_row(S, K, g * kRows + r, st, vy, vz, examined);
+        if (bh >= 0 && try_hit(S, K, st, bh, vy, vz)) got = bh;
+      }
+      hits[r] = got;
+      if (got >= 0) {
+        cur = got;
+        miss = 0;
+        last = st;
+        rout = r;
+      } else if (++miss >= K.n_gap) {
+        break;
+      }
+    }
+
+    // inward, covariance reset at the outermost hit
+    const int32_t hout = hits[rout];
+    st = last;
+    st.y = S.hy[hout];
+    st.z = S.hz[hout];
+    {
+      const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
+      reset_cov(st, sy * sy, sz * sz, K.cs0, K.ct0, K.cq0);
+    }
+    int n = 1;
+    int rin = rout;
+    last = st;
+    miss = 0;
+    for (int r = rout - 1; r >= 0; --r) {
+      ++visits;
+      if (!transport(st, K.row_x[r] - K.row_x[r + 1], K.b, K.smax)) break;
+      if (!inside(K, st, r, side_c)) break;
+      const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
+      const float vy = sy * sy, vz = sz * sz;
+      int32_t got = -1;
+      const int32_t uh = r >= r0 ? hits[r] : -1;
+      if (uh >= 0 && try_hit(S, K, st, uh, vy, vz)) got = uh;
+      if (got < 0) {
+        const int32_t bh = search_row(S, K, g * kRows + r, st, vy, vz, examined);
+        if (bh >= 0 && try_hit(S, K, st, bh, vy, vz)) got = bh;
+      }
+      hits[r] = got;
+      if (got >= 0) {
+        ++n;
+        miss = 0;
+        last = st;
+        rin = r;
+      } else if (++miss >= K.n_gap) {
+        break;
+      }
+    }
+    int32_t* info = S.tl_info + (size_t)T * 4;
+    info[0] = n;
+    info[1] = rin;
+    info[2] = rout;
+    info[3] = n >= K.n_min_tracklet ? 1 : 0;
+    const uint32_t id0 = (uint32_t)((int64_t)S.hid[p0] - ev0);
+    S.tl_weight[T] = ((uint32_t)n << 24) | (0xFFFFFFu - id0);
+    float* sv = S.tl_state + (size_t)T * 5;
+    sv[0] = last.y;
+    sv[1] = last.z;
+    sv[2] = last.s;
+    sv[3] = last.t;
+    sv[4] = last.q;
+  }
+  wave_add_u64(&S.stats[0], done);
+  wave_add_u64(&S.stats[1], visits);
+  wave_add_u64(&S.stats[2], examined);
+}
+
+}  // namespace tpc

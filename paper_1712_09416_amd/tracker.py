@@ -1,0 +1,163 @@
+"""Thin Python wrapper over the C ABI: torch supplies the device workspace and
+the stream; every step of the tracker runs in libtpcca.so."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import TRACK_DTYPE, Geometry, Params, check
+
+
+def make_geometry(geo: dict) -> Geometry:
+    g = Geometry()
+    g.n_sectors = int(geo["n_sectors"])
+    g.n_rows = int(geo["n_rows"])
+    rx = np.zeros(160, np.float32)
+    rx[: g.n_rows] = np.asarray(geo["row_x"], np.float32)
+    ctypes.memmove(g.row_x, rx.ctypes.data, 160 * 4)
+    for k in ("bz_tesla", "tan_half_angle", "z_max", "sigma_y0", "sigma_y1", "sigma_z0",
+              "sigma_z1"):
+        setattr(g, k, float(geo[k]))
+    return g
+
+
+def default_params(**over) -> Params:
+    p = Params()
+    check(_lib.load().tpc_params_default(ctypes.byref(p)))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t) -> int:
+    if isinstance(t, torch.Tensor):
+        return t.data_ptr()
+    return t.ctypes.data
+
+
+class Tracker:
+    """One tracker context on one GPU.
+
+    geometry: dict with n_sectors, n_rows, row_x, bz_tesla, tan_half_angle,
+    z_max, sigma_y0/y1/z0/z1 (see tpcgen.geometry.geometry_dict).
+    """
+
+    def __init__(self, geometry: dict, max_slots: int = 1, max_events: int = 1,
+                 max_clusters: int = 4 << 20, device: str = "cuda:0", stream=None, **params):
+        self.L = _lib.load()
+        self.device = torch.device(device)
+        self.params = default_params(max_slots=max_slots, max_events=max_events,
+                                     max_clusters=int(max_clusters), **params)
+        self.geometry = make_geometry(geometry)
+        nbytes = self.L.tpc_workspace_bytes(ctypes.byref(self.params))
+        if nbytes == 0:
+            raise ValueError("invalid tracker parameters")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = ctypes.c_void_p()
+        rc = self.L.tpc_init_geometry(ctypes.byref(self.ctx), ctypes.byref(self.geometry),
+                                      ctypes.byref(self.params), self.workspace.data_ptr(),
+                                      nbytes, self.stream.cuda_stream)
+        check(rc, None)
+        self._keep = {}
+
+    # -- staging -------------------------------------------------------------
+    def load(self, slot: int, sector, row, y, z, q=None):
+        """Stage one event.  Torch tensors on the GPU are used in place;
+        numpy arrays are copied to the device asynchronously."""
+        dev = isinstance(y, torch.Tensor) and y.is_cuda
+        arrs = self._prep(sector, row, y, z, dev)
+        self._keep[slot] = arrs
+        flags = _lib.TPC_DEVICE if dev else _lib.TPC_HOST
+        n = int(arrs[2].shape[0])
+        check(self.L.tpc_load_clusters(self.ctx, slot, _ptr(arrs[0]), _ptr(arrs[1]), _ptr(arrs[2]),
+                                       _ptr(arrs[3]), None, n, flags), self.ctx)
+
+    def load_batch(self, slot: int, offsets, sector, row, y, z):
+        """Stage len(offsets)-1 events, concatenated, into one slot."""
+        dev = isinstance(y, torch.Tensor) and y.is_cuda
+        arrs = self._prep(sector, row, y, z, dev)
+        offs = np.ascontiguousarray(offsets, np.int64)
+        self._keep[slot] = arrs + (offs,)
+        flags = _lib.TPC_DEVICE if dev else _lib.TPC_HOST
+        check(self.L.tpc_load_batch(self.ctx, slot, len(offs) - 1, offs.ctypes.data, _ptr(arrs[0]),
+                                    _ptr(arrs[1]), _ptr(arrs[2]), _ptr(arrs[3]), None, flags),
+              self.ctx)
+
+    @staticmethod
+    def _prep(sector, row, y, z, dev):
+        if dev:
+            return (sector.to(torch.uint8).contiguous(), row.to(torch.uint8).contiguous(),
+                    y.to(torch.float32).contiguous(), z.to(torch.float32).contiguous())
+        return (np.ascontiguousarray(sector, np.uint8), np.ascontiguousarray(row, np.uint8),
+                np.ascontiguousarray(y, np.float32), np.ascontiguousarray(z, np.float32))
+
+    # -- tracking --------------------------------------------------------------
+    def track_event(self, slot: int = 0):
+        check(self.L.tpc_track_event(self.ctx, slot), self.ctx)
+
+    def track_sector(self, slot: int, sector: int):
+        check(self.L.tpc_track_sector(self.ctx, slot, sector), self.ctx)
+
+    # -- results ---------------------------------------------------------------
+    def get_tracks(self, slot: int = 0, event: int = 0):
+        """(tracks as a TRACK_DTYPE array, hit IDs int32) of one event."""
+        nt, nh = ctypes.c_int64(0), ctypes.c_int64(0)
+        rc = self.L.tpc_get_tracks(self.ctx, slot, event, None, 0, None, 0, ctypes.byref(nt),
+                                   ctypes.byref(nh))
+        if rc not in (_lib.TPC_OK, _lib.TPC_EOVERFLOW):
+            check(rc, self.ctx)
+        tracks = np.zeros(nt.value, TRACK_DTYPE)
+        hits = np.zeros(nh.value, np.int32)
+        check(self.L.tpc_get_tracks(self.ctx, slot, event, tracks.ctypes.data, len(tracks),
+                                    hits.ctypes.data, len(hits), ctypes.byref(nt),
+                                    ctypes.byref(nh)), self.ctx)
+        return tracks, hits
+
+    def get_links(self, slot: int, event: int, n: int):
+        out = [np.empty(n, np.int32) for _ in range(4)]
+        check(self.L.tpc_get_links(self.ctx, slot, event, *[o.ctypes.data for o in out]), self.ctx)
+        return dict(up=out[0], dn=out[1], upc=out[2], dnc=out[3])
+
+    def device_results(self, slot: int = 0):
+        P = ctypes.c_void_p
+        ptrs = [P() for _ in range(5)]
+        check(self.L.tpc_device_results(self.ctx, slot, *[ctypes.byref(p) for p in ptrs]), self.ctx)
+        return [p.value for p in ptrs]
+
+    def kf_step(self, state: torch.Tensor, dx: torch.Tensor, meas: torch.Tensor):
+        """One float transport + gated update per row of state[n, 20]
+        (in place).  Returns (bits int32[n], chi2 float32[n])."""
+        n = state.shape[0]
+        res = torch.zeros((n, 2), dtype=torch.float32, device=state.device)
+        check(self.L.tpc_kf_step_f32(self.ctx, state.data_ptr(), dx.data_ptr(), meas.data_ptr(),
+                                     res.data_ptr(), n), self.ctx)
+        return res[:, 0].contiguous().view(torch.int32), res[:, 1].contiguous()
+
+    def set_profiling(self, on: bool = True):
+        check(self.L.tpc_set_profiling(self.ctx, int(on)), self.ctx)
+
+    def profile(self):
+        """(stage milliseconds dict, counters dict) of the last tracked slot."""
+        ms = np.zeros(len(_lib.STAGES), np.float64)
+        cnt = np.zeros(8, np.uint64)
+        check(self.L.tpc_get_profile(self.ctx, ms.ctypes.data, cnt.ctypes.data), self.ctx)
+        names = ("tracklets", "row_visits", "window_hits", "tracks", "clusters", "sorted_hits")
+        return dict(zip(_lib.STAGES, ms.tolist())), {k: int(cnt[i]) for i, k in enumerate(names)}
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if self.ctx:
+            self.L.tpc_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,139 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, and rejects bad arguments before it would touch the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1712_09416_amd import _lib
+from paper_1712_09416_amd.tracker import default_params, make_geometry
+import tpcgen
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "tpcca.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(L):
+    src = open(HEADER).read()
+    declared = set(re.findall(r"^\w[\w\s\*]*?\b(tpc_\w+)\s*\(", src, re.M))
+    assert {"tpc_init_geometry", "tpc_load_clusters", "tpc_track_sector", "tpc_track_event",
+            "tpc_get_tracks"} <= declared
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == set(_lib.EXPORTS)
+
+
+def test_track_struct_layout():
+    assert _lib.TRACK_DTYPE.itemsize == 216
+    assert _lib.TRACK_DTYPE.fields["hit_off"][1] == 24
+    assert _lib.TRACK_DTYPE.fields["par"][1] == 48
+
+
+def test_params_defaults_match_oracle(L):
+    from oracle.oracle import DEFAULT_PARAMS
+    p = default_params()
+    for k, v in DEFAULT_PARAMS.items():
+        assert getattr(p, k) == pytest.approx(v), k
+
+
+def test_workspace_bytes(L):
+    p = default_params(max_clusters=1 << 20)
+    a = L.tpc_workspace_bytes(ctypes.byref(p))
+    p2 = default_params(max_clusters=2 << 20)
+    b = L.tpc_workspace_bytes(ctypes.byref(p2))
+    p3 = default_params(max_clusters=1 << 20, max_slots=3)
+    c = L.tpc_workspace_bytes(ctypes.byref(p3))
+    assert 0 < a < b and c >= 3 * a - 3 * 4096
+    bad = default_params(max_slots=0)
+    assert L.tpc_workspace_bytes(ctypes.byref(bad)) == 0
+    bad = default_params(s_max=1.5)
+    assert L.tpc_workspace_bytes(ctypes.byref(bad)) == 0
+
+
+def _geo(**over):
+    g = tpcgen.geometry.geometry_dict()
+    g.update(over)
+    return make_geometry(g)
+
+
+def _ctx(L, ws_ptr=0x100000, **over):
+    p = default_params(max_clusters=1 << 16, **over)
+    need = L.tpc_workspace_bytes(ctypes.byref(p))
+    ctx = ctypes.c_void_p()
+    rc = L.tpc_init_geometry(ctypes.byref(ctx), ctypes.byref(_geo()), ctypes.byref(p),
+                             ws_ptr, need, None)
+    assert rc == _lib.TPC_OK
+    return ctx, p
+
+
+def test_init_rejects_bad_geometry_and_workspace(L):
+    p = default_params(max_clusters=1 << 16)
+    need = L.tpc_workspace_bytes(ctypes.byref(p))
+    ctx = ctypes.c_void_p()
+    g = _geo(n_sectors=18)
+    assert L.tpc_init_geometry(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p), 0x1000, need,
+                               None) == _lib.TPC_EINVAL
+    assert b"36 sectors" in L.tpc_last_error(None)
+    rx = tpcgen.geometry.row_x().copy()
+    rx[10] = rx[9]
+    g = _geo(row_x=rx)
+    assert L.tpc_init_geometry(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p), 0x1000, need,
+                               None) == _lib.TPC_EINVAL
+    assert L.tpc_init_geometry(ctypes.byref(ctx), ctypes.byref(_geo()), ctypes.byref(p), 0x1000,
+                               need - 1, None) == _lib.TPC_ENOMEM
+    assert L.tpc_init_geometry(ctypes.byref(ctx), ctypes.byref(_geo()), ctypes.byref(p), None,
+                               need, None) == _lib.TPC_ENOMEM
+    assert L.tpc_init_geometry(None, ctypes.byref(_geo()), ctypes.byref(p), 0x1000, need,
+                               None) == _lib.TPC_EINVAL
+
+
+def test_calls_rejected_before_device_work(L):
+    """Every check below fails on the host; no HIP call is made (there is no
+    GPU here), so reaching the device would show up as TPC_EDEVICE."""
+    ctx, p = _ctx(L)
+    a = np.zeros(10, np.uint8)
+    f = np.zeros(10, np.float32)
+    P = lambda x: x.ctypes.data  # noqa: E731
+    assert L.tpc_load_clusters(ctx, 1, P(a), P(a), P(f), P(f), None, 10, _lib.TPC_HOST) == _lib.TPC_EINVAL
+    assert L.tpc_load_clusters(ctx, -1, P(a), P(a), P(f), P(f), None, 10, _lib.TPC_HOST) == _lib.TPC_EINVAL
+    assert L.tpc_load_clusters(ctx, 0, P(a), P(a), P(f), P(f), None, -1, _lib.TPC_HOST) == _lib.TPC_EINVAL
+    assert L.tpc_load_clusters(ctx, 0, P(a), P(a), P(f), P(f), None, (1 << 16) + 1,
+                               _lib.TPC_HOST) == _lib.TPC_ENOMEM
+    assert L.tpc_load_clusters(ctx, 0, None, P(a), P(f), P(f), None, 10, _lib.TPC_HOST) == _lib.TPC_EINVAL
+    assert L.tpc_load_clusters(ctx, 0, P(a), P(a), P(f), P(f), None, 10, 7) == _lib.TPC_EINVAL
+    offs = np.array([0, 5, 3], np.int64)
+    assert L.tpc_load_batch(ctx, 0, 2, offs.ctypes.data, P(a), P(a), P(f), P(f), None,
+                            _lib.TPC_HOST) == _lib.TPC_EINVAL          # decreasing / too many events
+    offs = np.array([1, 5], np.int64)
+    assert L.tpc_load_batch(ctx, 0, 1, offs.ctypes.data, P(a), P(a), P(f), P(f), None,
+                            _lib.TPC_HOST) == _lib.TPC_EINVAL
+    assert L.tpc_track_event(ctx, 0) == _lib.TPC_ESTATE
+    assert L.tpc_track_event(ctx, 3) == _lib.TPC_EINVAL
+    assert L.tpc_track_sector(ctx, 0, 0) == _lib.TPC_ESTATE
+    nt, nh = ctypes.c_int64(), ctypes.c_int64()
+    assert L.tpc_get_tracks(ctx, 0, 0, None, 0, None, 0, ctypes.byref(nt),
+                            ctypes.byref(nh)) == _lib.TPC_ESTATE
+    assert L.tpc_get_tracks(ctx, 0, 0, None, 5, None, 0, ctypes.byref(nt),
+                            ctypes.byref(nh)) == _lib.TPC_EINVAL
+    assert L.tpc_get_tracks(ctx, 0, 0, None, -1, None, 0, None, None) == _lib.TPC_EINVAL
+    assert L.tpc_get_links(ctx, 0, 0, None, None, None, None) == _lib.TPC_ESTATE
+    assert L.tpc_kf_step_f32(ctx, None, None, None, None, 5) == _lib.TPC_EINVAL
+    assert L.tpc_kf_step_f32(ctx, None, None, None, None, 0) == _lib.TPC_OK
+    assert L.tpc_last_error(ctx)
+    assert L.tpc_track_event(None, 0) == _lib.TPC_EINVAL
+
+
+def test_batch_event_limit(L):
+    ctx, p = _ctx(L, max_events=4)
+    a = np.zeros(10, np.uint8)
+    f = np.zeros(10, np.float32)
+    offs = np.zeros(6, np.int64)
+    assert L.tpc_load_batch(ctx, 0, 5, offs.ctypes.data, a.ctypes.data, a.ctypes.data,
+                            f.ctypes.data, f.ctypes.data, None, _lib.TPC_HOST) == _lib.TPC_EINVAL
