@@ -28,9 +28,9 @@ def say(*a):
     print(*a, flush=True)
 
 
-def gpu_run(ev, dev, mode="event", tracker=None, links=True):
+def gpu_run(ev, dev, mode="event", tracker=None, links=True, geometry=None):
     from paper_1712_09416_amd import Tracker
-    trk = tracker or Tracker(ev.geometry(), max_clusters=max(ev.n, 4096))
+    trk = tracker or Tracker(geometry or ev.geometry(), max_clusters=max(ev.n, 4096))
     ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.sector, ev.row, ev.y, ev.z)]
     trk.load(0, *ins)
     if mode == "event":
@@ -190,7 +190,7 @@ def test_central_event_sampled_sectors(dev, oracle_lib):
 
 def test_batch_equals_single_events(dev, oracle_lib):
     """Events tracked together in one slot give exactly their single-event
-    results."""
+    results (one cluster-error model for the whole slot: the Pb-Pb one)."""
     from paper_1712_09416_amd import Tracker
     evs = [tpcgen.pbpb_event(tpcgen.seed_for(3, e), m) for e, m in enumerate([50, 900, 3000])]
     evs.insert(1, tpcgen.pp_event())
@@ -200,13 +200,14 @@ def test_batch_equals_single_events(dev, oracle_lib):
     evs.insert(2, empty)
     offs = np.concatenate([[0], np.cumsum([e.n for e in evs])])
     cat = [np.concatenate([getattr(e, k) for e in evs]) for k in ("sector", "row", "y", "z")]
-    trk = Tracker(evs[0].geometry() | {}, max_events=8, max_clusters=int(offs[-1]) + 16)
+    geo = evs[0].geometry()
+    trk = Tracker(geo, max_events=8, max_clusters=int(offs[-1]) + 16)
     trk.load_batch(0, offs, *[torch.from_numpy(a).to(dev) for a in cat])
     trk.track_event(0)
     for e, ev in enumerate(evs):
         tb, hb = trk.get_tracks(0, e)
         assert np.all(tb["event"] == e)
-        ts, hs, _ = gpu_run(ev, dev, links=False)
+        ts, hs, _ = gpu_run(ev, dev, links=False, geometry=geo)
         assert np.array_equal(hb, hs)
         for k in ("n_hits", "inner_id", "hit_off", "par", "cov", "chi2", "sector"):
             assert np.array_equal(tb[k], ts[k]), (e, k)
