@@ -56,6 +56,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=3,
                     help="steps of the per-sector (plain) launch sequence, for comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the tracker "
@@ -68,6 +70,13 @@ def main() -> int:
     from paper_1712_09416_amd import Tracker
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ev = tpcgen.central_event()
     print(f"bench: central event {ev.n} clusters", file=sys.stderr, flush=True)
     ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.sector, ev.row, ev.y, ev.z)]

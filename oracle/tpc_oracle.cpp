@@ -110,7 +110,10 @@ bool predict(State<T>& st, T dx, T b, T smax) {
   const T c1 = tsqrt(T(1) - s1 * s1);
   const T N = s + s1;
   const T D = c0 + c1;
-  const T t = N / D;
+  const T iD = T(1) / D;
+  const T ic0 = T(1) / c0;
+  const T ic1 = T(1) / c1;
+  const T t = N * iD;
   const T dl = tabs(dx) * tsqrt(T(1) + t * t);
   const T u = T(0.5) * bq * dl;
   const T u2 = u * u;
@@ -118,17 +121,17 @@ bool predict(State<T>& st, T dx, T b, T smax) {
   if (dx < T(0)) ds = -ds;
 
   // Jacobian d(y1, z1, s1)/d(s, T, Q); the other entries are those of the
-  // identity.  dz/dQ is the leading-order term.
-  const T D2 = D * D;
-  const T sc0 = s / c0;
-  const T sc1 = s1 / c1;
-  const T jys = dx * (T(2) * D + N * (sc0 + sc1)) / D2;
-  const T jyq = b * dx * dx * (D + N * sc1) / D2;
-  const T jzs = tl * dx * N / (c0 * c1 * D);
+  // identity.  dz/dQ is the leading-order term T b s_m dx^2 / (2 c_m^3) with
+  // s_m = N/2 and the mid-angle cosine c_m taken as D/2 (equal to leading
+  // order), i.e. 2 T b N dx^2 / D^3.
+  const T iD2 = iD * iD;
+  const T sc0 = s * ic0;
+  const T sc1 = s1 * ic1;
+  const T jys = dx * (T(2) * D + N * (sc0 + sc1)) * iD2;
+  const T jyq = b * dx * dx * (D + N * sc1) * iD2;
+  const T jzs = tl * dx * N * (ic0 * ic1 * iD);
   const T jzt = ds;
-  const T sm = T(0.5) * N;
-  const T cm = tsqrt(T(1) - sm * sm);
-  const T jzq = tl * b * sm * dx * dx / (T(2) * cm * cm * cm);
+  const T jzq = T(2) * tl * b * N * dx * dx * (iD2 * iD);
   const T jsq = b * dx;
 
   p[0] = p[0] + dx * t;

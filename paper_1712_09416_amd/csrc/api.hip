@@ -70,11 +70,11 @@ __global__ void k_links_out(Slot S, int e, int32_t* up, int32_t* dn, int32_t* up
   const int64_t ev0 = S.ev_off[e];
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t p = b + blockIdx.x * blockDim.x + threadIdx.x; p < t; p += stride) {
-    const int64_t id = (int64_t)S.hid[p] - ev0;
-    const int32_t l[4] = {S.up[p], S.dn[p], S.upc[p], S.dnc[p]};
+    const int64_t id = (int64_t)S.hit[p].id - ev0;
+    const int32_t l[4] = {S.up[p], S.dn[p], S.hit[p].upc, S.dnc[p]};
     int32_t* o[4] = {up, dn, upc, dnc};
     for (int k = 0; k < 4; ++k)
-      o[k][id] = l[k] >= 0 ? (int32_t)((int64_t)S.hid[l[k]] - ev0) : -1;
+      o[k][id] = l[k] >= 0 ? (int32_t)((int64_t)S.hit[l[k]].id - ev0) : -1;
   }
 }
 
@@ -122,33 +122,33 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   s.ty = c.take<float>(N);
   s.tz = c.take<float>(N);
   s.tid = c.take<uint32_t>(N);
-  s.hy = c.take<float>(N);
-  s.hz = c.take<float>(N);
-  s.hid = c.take<uint32_t>(N);
+  s.hit = c.take<Hit>(N);
   s.up = c.take<int32_t>(N);
   s.dn = c.take<int32_t>(N);
-  s.upc = c.take<int32_t>(N);
   s.dnc = c.take<int32_t>(N);
   s.tl_base = c.take<uint32_t>(S + 1);
   s.tk_base = c.take<uint32_t>(S + 1);
-  s.n_start = c.take<uint32_t>(S);
-  s.n_track = c.take<uint32_t>(S);
-  s.flat_tl = c.take<uint32_t>(S + 1);
-  s.flat_tk = c.take<uint32_t>(S + 1);
+  s.row_nstart = c.take<uint32_t>(SR + 1);
+  s.range_cnt = c.take<uint32_t>(4);
   s.start_hit = c.take<int32_t>(cap_tl);
+  s.start_sr = c.take<int32_t>(cap_tl);
   s.tl_hits = c.take<int32_t>(cap_tl * kRows);
   s.tl_info = c.take<int32_t>(cap_tl * 4);
   s.tl_weight = c.take<uint32_t>(cap_tl);
   s.tl_state = c.take<float>(cap_tl * 5);
+  s.tl_sel = c.take<uint32_t>(cap_tl + 1);
   s.weight = c.take<uint32_t>(N);
   s.tk_tracklet = c.take<int32_t>(cap_tk);
+  s.tk_own = c.take<int32_t>(cap_tk * kRows);
+  s.tk_own_row = c.take<uint8_t>(cap_tk * kRows);
+  s.tk_nown = c.take<int32_t>(cap_tk);
   s.tk_info = c.take<int32_t>(cap_tk * 4);
   s.tk_par = c.take<double>(cap_tk * 5);
   s.tk_cov = c.take<double>(cap_tk * 15);
   s.tk_chi2 = c.take<double>(cap_tk);
   s.tmap = c.take<int32_t>(N);
   s.scan_a = c.take<uint32_t>(N + 1);
-  s.scan_b = c.take<uint32_t>(std::max<int64_t>(N + 1, cap_tk + 1) / kScanTile + 4);
+  s.scan_b = c.take<uint32_t>(std::max<int64_t>(std::max<int64_t>(N, SR), cap_tl) / kScanTile + 4);
   s.out_count = c.take<uint32_t>(2);
   s.out_ntk = c.take<uint32_t>(cap_tk + 1);
   s.out_order = c.take<int32_t>(cap_tk);
@@ -241,35 +241,45 @@ int build_grid(tpc_ctx* ctx, SlotHost& h) {
   return TPC_OK;
 }
 
+// Exclusive scan in place of data[0, n) (n = *n_dev if given, else n_bound,
+// which bounds it); the total goes to total_out and, with write_end, to
+// data[n].
+void scan_u32(hipStream_t st, uint32_t* data, const uint32_t* n_dev, int64_t n_bound,
+              uint32_t* partial, uint32_t* total_out, bool write_end = true) {
+  const int nb = (int)std::max<int64_t>(1, (n_bound + kScanTile - 1) / kScanTile);
+  k_scan_tiles<<<nb, 256, 0, st>>>(data, n_dev, n_bound, partial);
+  k_scan_partials<<<1, 1024, 0, st>>>(partial, nb, data, n_dev, n_bound, total_out,
+                                      write_end ? 1 : 0);
+  k_scan_apply<<<nb, 256, 0, st>>>(data, n_dev, n_bound, partial, data);
+}
+
+
+
 int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns) {
   Slot& s = h.d;
   hipStream_t st = ctx->stream;
-  // work estimate for the persistent grids (the exact counts live on the device)
-  const int64_t est = std::max<int64_t>(1, h.n / 3 * ns / s.n_sectors);
-  const int nb = grid_stride_blocks(est, 64, 4096);
+  // host bounds for the persistent grids (exact counts live on the device)
+  const int64_t tl_bound = std::min<int64_t>(s.cap_tl, h.n / 3 + ns);
+  const int nb_lane = std::max(8, grid_stride_blocks(tl_bound, 64, 4096) / 8 * 8);
+  const int nb_wave = grid_stride_blocks(tl_bound * 64, 256, 8192);
   k_neighbours<<<dim3(kRows, ns), 256, 0, st>>>(s, ctx->k, g0);
   mark(ctx, 2);
-  k_clean_start<<<dim3(kRows, ns), 256, 0, st>>>(s, g0);
-  k_flatten<<<1, 1024, 0, st>>>(s.n_start, s.flat_tl, g0, ns);
+  k_clean_rows<<<dim3(kRows, ns), 256, 0, st>>>(s, g0);
+  scan_u32(st, s.row_nstart + (size_t)g0 * kRows, nullptr, (int64_t)ns * kRows, s.scan_b,
+           s.range_cnt + 0, false);
+  k_start_write<<<dim3(kRows, ns), 256, 0, st>>>(s, g0);
   mark(ctx, 3);
-  k_tracklets<<<nb, 64, 0, st>>>(s, ctx->k, g0, ns);
+  k_tracklets<<<nb_lane, 64, 0, st>>>(s, ctx->k, g0);
   mark(ctx, 4);
-  k_weights<<<nb, 64, 0, st>>>(s, g0, ns);
-  k_select<<<nb, 64, 0, st>>>(s, ctx->k, g0, ns);
-  k_flatten<<<1, 1024, 0, st>>>(s.n_track, s.flat_tk, g0, ns);
+  k_weights<<<nb_wave, 256, 0, st>>>(s, g0);
+  k_select<<<nb_wave, 256, 0, st>>>(s, ctx->k, g0);
+  scan_u32(st, s.tl_sel, s.range_cnt + 0, tl_bound, s.scan_b, s.range_cnt + 1, false);
+  k_track_write<<<nb_wave, 256, 0, st>>>(s, g0);
   mark(ctx, 5);
-  k_refit<<<nb, 64, 0, st>>>(s, ctx->k, g0, ns);
+  k_refit<<<grid_stride_blocks(std::max<int64_t>(1, tl_bound / 4), 64, 4096), 64, 0, st>>>(s, ctx->k, g0);
   mark(ctx, 6);
   TPC_LAUNCHED();
   return TPC_OK;
-}
-
-void scan_u32(hipStream_t st, uint32_t* data, const uint32_t* n_dev, int64_t n_bound,
-              uint32_t* partial, uint32_t* total_out) {
-  const int nb = (int)std::max<int64_t>(1, (n_bound + kScanTile - 1) / kScanTile);
-  k_scan_tiles<<<nb, 256, 0, st>>>(data, n_dev, n_bound, partial);
-  k_scan_partials<<<1, 1024, 0, st>>>(partial, nb, data, n_dev, n_bound, total_out);
-  k_scan_apply<<<nb, 256, 0, st>>>(data, n_dev, n_bound, partial, data);
 }
 
 int finalize(tpc_ctx* ctx, SlotHost& h) {

@@ -6,21 +6,101 @@
 
 namespace tpc {
 
-// Visit the sorted hits of row `sr` that can lie inside
-// [yc - w, yc + w] x [zc - w, zc + w] (a superset: every bin the window
-// touches, with a small margin so that rounding cannot hide a hit).
-template <class Fn>
-__device__ __forceinline__ void for_window(const Slot& S, int sr, float yc, float zc, float wy,
-                                           float wz, Fn&& fn) {
-  const RowBins b = S.bins[sr];
+constexpr int kNfRowCap = 1024;   // hits of a neighbour row staged in LDS
+constexpr int kNfCand = 16;       // up-row candidates kept per hit
+constexpr int kNfThreads = 256;
+
+// Visit the hits of one row that can lie inside [yc - wy, yc + wy] x
+// [zc - wz, zc + wz]: every bin the window touches (plus a small margin so
+// rounding cannot hide a hit); the caller applies the exact window test.
+// `bins` is indexed by the row's bin number and holds hit positions in the
+// numbering of whatever `fn` receives.
+template <class BinPtr, class Fn>
+__device__ __forceinline__ void for_window(const RowBins& b, BinPtr bins, float yc, float zc,
+                                           float wy, float wz, Fn&& fn) {
   const float eps = 1e-3f;
   const int iy0 = bin_y(b, yc - wy - eps), iy1 = bin_y(b, yc + wy + eps);
   const int iz0 = bin_z(b, zc - wz - eps), iz1 = bin_z(b, zc + wz + eps);
   for (int iz = iz0; iz <= iz1; ++iz) {
-    const int first = b.base + iz * b.ny;
-    const uint32_t p0 = S.bin_off[first + iy0];
-    const uint32_t p1 = S.bin_off[first + iy1 + 1];
+    const int first = iz * b.ny;
+    const uint32_t p0 = bins[first + iy0];
+    const uint32_t p1 = bins[first + iy1 + 1];
     for (uint32_t p = p0; p < p1; ++p) fn(p);
+  }
+}
+
+// Best (down, up) pair of one hit.  hd/bd (hu/bu): hits and bin offsets of
+// row r-1 (r+1) in a common numbering; add_d/add_u turn that numbering into
+// sorted-hit indices.
+template <class HitPtr, class BinPtr>
+__device__ __forceinline__ void best_pair(const DevConst& K, const Hit hh, int row,
+                                          const RowBins& Bd, HitPtr hd, BinPtr bd, uint32_t add_d,
+                                          const RowBins& Bu, HitPtr hu, BinPtr bu, uint32_t add_u,
+                                          uint32_t* cand, int32_t& out_up, int32_t& out_dn) {
+  // cand[k * kNfThreads]: this thread's k-th candidate (thread-minor layout,
+  // so a wave's accesses fall in distinct LDS banks)
+  const float xr = K.row_x[row];
+  const float rho_d = K.row_x[row - 1] / xr;
+  const float rho_u = K.row_x[row + 1] / xr;
+  const float f = (xr - K.row_x[row - 1]) / (K.row_x[row + 1] - K.row_x[row - 1]);
+  const float W = K.nf_w;
+  const float yh = hh.y, zh = hh.z;
+  const float ypd = yh * rho_d, zpd = zh * rho_d;
+  const float ypu = yh * rho_u, zpu = zh * rho_u;
+  const float sy = sigma_y(K, zh), sz = sigma_z(K, zh);
+  const float wy = 1.0f / (1.5f * (sy * sy));
+  const float wz = 1.0f / (1.5f * (sz * sz));
+  // up-row candidates inside the exact window
+  int nu = 0;
+  bool overflow = false;
+  for_window(Bu, bu, ypu, zpu, W, W, [&](uint32_t u) {
+    const Hit x = hu[u];
+    if (!(fabsf(x.y - ypu) <= W && fabsf(x.z - zpu) <= W)) return;
+    if (nu < kNfCand) cand[nu * kNfThreads] = u;
+    else overflow = true;
+    ++nu;
+  });
+  out_up = -1;
+  out_dn = -1;
+  if (nu == 0) return;
+  bool have = false;
+  float best = 0.0f;
+  uint32_t bid_d = 0, bid_u = 0;
+  int32_t bd_i = -1, bu_i = -1;
+  auto pair = [&](uint32_t d, const Hit& xd, uint32_t u, const Hit& xu) {
+    const float dy = xd.y + (xu.y - xd.y) * f - yh;
+    const float dz = xd.z + (xu.z - xd.z) * f - zh;
+    const float m = dy * dy * wy + dz * dz * wz;
+    const bool better =
+        !have || m < best || (m == best && (xd.id < bid_d || (xd.id == bid_d && xu.id < bid_u)));
+    if (better) {
+      have = true;
+      best = m;
+      bid_d = xd.id;
+      bid_u = xu.id;
+      bd_i = (int32_t)(d + add_d);
+      bu_i = (int32_t)(u + add_u);
+    }
+  };
+  for_window(Bd, bd, ypd, zpd, W, W, [&](uint32_t d) {
+    const Hit xd = hd[d];
+    if (!(fabsf(xd.y - ypd) <= W && fabsf(xd.z - zpd) <= W)) return;
+    if (!overflow) {
+      for (int k = 0; k < nu; ++k) {
+        const uint32_t u = cand[k * kNfThreads];
+        pair(d, xd, u, hu[u]);
+      }
+    } else {
+      for_window(Bu, bu, ypu, zpu, W, W, [&](uint32_t u) {
+        const Hit xu = hu[u];
+        if (!(fabsf(xu.y - ypu) <= W && fabsf(xu.z - zpu) <= W)) return;
+        pair(d, xd, u, xu);
+      });
+    }
+  });
+  if (have && best <= K.nf_mmax) {
+    out_up = bu_i;
+    out_dn = bd_i;
   }
 }
 
@@ -29,16 +109,19 @@ __device__ __forceinline__ void for_window(const Slot& S, int sr, float yc, floa
 // |y - y_h x_r'/x_r| <= W, |z - z_h x_r'/x_r| <= W whose straight line passes
 // closest to h, measured by m = dy^2 / (1.5 sy^2) + dz^2 / (1.5 sz^2);
 // ties go to the smaller (id_d, id_u); the pair is kept if m <= m_max.
-// Rows 0 and 158 get no links.  Also clears the per-sector counters.
-__global__ void __launch_bounds__(256) k_neighbours(Slot S, DevConst K, int g0) {
+// Rows r-1 and r+1 (hits and bin offsets) are staged in LDS when they hold
+// at most kNfRowCap hits; otherwise read from global memory.  Rows 0 and 158
+// get no links.
+__global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, int g0) {
+  __shared__ Hit sh_d[kNfRowCap];
+  __shared__ Hit sh_u[kNfRowCap];
+  __shared__ uint32_t sb_d[kNfRowCap + 1];
+  __shared__ uint32_t sb_u[kNfRowCap + 1];
+  __shared__ uint32_t cand[kNfCand * kNfThreads];
   const int row = blockIdx.x;
   const int g = g0 + blockIdx.y;
   const int sr = g * kRows + row;
   const uint32_t h0 = S.row_off[sr], h1 = S.row_off[sr + 1];
-  if (row == 0 && threadIdx.x == 0) {
-    S.n_start[g] = 0;
-    S.n_track[g] = 0;
-  }
   if (row == 0 || row == kRows - 1) {
     for (uint32_t h = h0 + threadIdx.x; h < h1; h += blockDim.x) {
       S.up[h] = -1;
@@ -46,129 +129,110 @@ __global__ void __launch_bounds__(256) k_neighbours(Slot S, DevConst K, int g0) 
     }
     return;
   }
-  const float xr = K.row_x[row];
-  const float rho_d = K.row_x[row - 1] / xr;
-  const float rho_u = K.row_x[row + 1] / xr;
-  const float f = (xr - K.row_x[row - 1]) / (K.row_x[row + 1] - K.row_x[row - 1]);
-  const float W = K.nf_w;
-  for (uint32_t h = h0 + threadIdx.x; h < h1; h += blockDim.x) {
-    const float yh = S.hy[h], zh = S.hz[h];
-    const float ypd = yh * rho_d, zpd = zh * rho_d;
-    const float ypu = yh * rho_u, zpu = zh * rho_u;
-    const float sy = sigma_y(K, zh), sz = sigma_z(K, zh);
-    const float wy = 1.0f / (1.5f * (sy * sy));
-    const float wz = 1.0f / (1.5f * (sz * sz));
-    bool have = false;
-    float best = 0.0f;
-    uint32_t bid_d = 0, bid_u = 0;
-    int32_t bd = -1, bu = -1;
-    for_window(S, sr - 1, ypd, zpd, W, W, [&](uint32_t d) {
-      const float yd = S.hy[d], zd = S.hz[d];
-      if (!(fabsf(yd - ypd) <= W && fabsf(zd - zpd) <= W)) return;
-      const uint32_t idd = S.hid[d];
-      for_window(S, sr + 1, ypu, zpu, W, W, [&](uint32_t u) {
-        const float yu = S.hy[u], zu = S.hz[u];
-        if (!(fabsf(yu - ypu) <= W && fabsf(zu - zpu) <= W)) return;
-        const uint32_t idu = S.hid[u];
-        const float dy = yd + (yu - yd) * f - yh;
-        const float dz = zd + (zu - zd) * f - zh;
-        const float m = dy * dy * wy + dz * dz * wz;
-        const bool better = !have || m < best ||
-                            (m == best && (idd < bid_d || (idd == bid_d && idu < bid_u)));
-        if (better) {
-          have = true;
-          best = m;
-          bid_d = idd;
-          bid_u = idu;
-          bd = (int32_t)d;
-          bu = (int32_t)u;
-        }
-      });
-    });
-    const bool ok = have && best <= K.nf_mmax;
-    S.up[h] = ok ? bu : -1;
-    S.dn[h] = ok ? bd : -1;
+  if (h0 == h1) return;
+  const uint32_t od = S.row_off[sr - 1], nd = h0 - od;
+  const uint32_t ou = h1, nu = S.row_off[sr + 2] - h1;
+  const RowBins Bd = S.bins[sr - 1], Bu = S.bins[sr + 1];
+  const int nbd = Bd.ny * Bd.nz, nbu = Bu.ny * Bu.nz;
+  uint32_t* my = cand + threadIdx.x;
+  if (nd <= (uint32_t)kNfRowCap && nu <= (uint32_t)kNfRowCap) {
+    for (uint32_t j = threadIdx.x; j < nd; j += blockDim.x) sh_d[j] = S.hit[od + j];
+    for (uint32_t j = threadIdx.x; j < nu; j += blockDim.x) sh_u[j] = S.hit[ou + j];
+    for (int j = threadIdx.x; j <= nbd; j += blockDim.x) sb_d[j] = S.bin_off[Bd.base + j] - od;
+    for (int j = threadIdx.x; j <= nbu; j += blockDim.x) sb_u[j] = S.bin_off[Bu.base + j] - ou;
+    __syncthreads();
+    for (uint32_t h = h0 + threadIdx.x; h < h1; h += blockDim.x) {
+      int32_t up, dn;
+      best_pair(K, S.hit[h], row, Bd, (const Hit*)sh_d, (const uint32_t*)sb_d, od, Bu,
+                (const Hit*)sh_u, (const uint32_t*)sb_u, ou, my, up, dn);
+      S.up[h] = up;
+      S.dn[h] = dn;
+    }
+  } else {
+    for (uint32_t h = h0 + threadIdx.x; h < h1; h += blockDim.x) {
+      int32_t up, dn;
+      best_pair(K, S.hit[h], row, Bd, (const Hit*)S.hit, (const uint32_t*)(S.bin_off + Bd.base), 0u,
+                Bu, (const Hit*)S.hit, (const uint32_t*)(S.bin_off + Bu.base), 0u, my, up, dn);
+      S.up[h] = up;
+      S.dn[h] = dn;
+    }
   }
 }
 
-// a4: keep a link only if it is mutual (reading the links of a3 only), and
-// collect the start hits: first hit of a cleaned chain of >= 3 hits.  Start
-// hits go to the sector's region with a wave-aggregated atomic.  Also
-// clears the hit weights used by the tracklet selection.
-__global__ void __launch_bounds__(256) k_clean_start(Slot S, int g0) {
+// Start of a cleaned chain of >= 3 hits, from the links of a3 only.
+__device__ __forceinline__ bool is_start(const Slot& S, uint32_t h, int32_t& uc, int32_t& dc) {
+  const int32_t u = S.up[h], d = S.dn[h];
+  uc = (u >= 0 && S.dn[u] == (int32_t)h) ? u : -1;
+  dc = (d >= 0 && S.up[d] == (int32_t)h) ? d : -1;
+  if (uc < 0 || dc >= 0) return false;
+  const int32_t uu = S.up[uc];
+  return uu >= 0 && S.dn[uu] == uc;
+}
+
+// a4: keep a link only if it is mutual; count the start hits of each row.
+// Also clears the hit weights used by the tracklet selection.
+__global__ void __launch_bounds__(256) k_clean_rows(Slot S, int g0) {
+  __shared__ uint32_t count;
   const int row = blockIdx.x;
   const int g = g0 + blockIdx.y;
   const int sr = g * kRows + row;
   const uint32_t h0 = S.row_off[sr], h1 = S.row_off[sr + 1];
-  const uint32_t cap = S.tl_base[g + 1] - S.tl_base[g];
+  if (threadIdx.x == 0) count = 0;
+  __syncthreads();
   for (uint32_t base = h0; base < h1; base += blockDim.x) {
     const uint32_t h = base + threadIdx.x;
     bool start = false;
     if (h < h1) {
-      const int32_t u = S.up[h], d = S.dn[h];
-      const int32_t uc = (u >= 0 && S.dn[u] == (int32_t)h) ? u : -1;
-      const int32_t dc = (d >= 0 && S.up[d] == (int32_t)h) ? d : -1;
-      S.upc[h] = uc;
+      int32_t uc, dc;
+      start = is_start(S, h, uc, dc);
+      S.hit[h].upc = uc;
       S.dnc[h] = dc;
       S.weight[h] = 0u;
-      if (uc >= 0 && dc < 0) {
-        const int32_t uu = S.up[uc];
-        start = uu >= 0 && S.dn[uu] == uc;
-      }
     }
     const unsigned long long m = __ballot(start);
-    if (m) {
-      const int lane = threadIdx.x & 63;
-      const int leader = __ffsll((long long)m) - 1;
-      uint32_t first = 0;
-      if (lane == leader) first = atomicAdd(&S.n_start[g], (uint32_t)__popcll(m));
-      first = __shfl(first, leader, 64);
-      if (start) {
-        const uint32_t k = first + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-        if (k < cap) S.start_hit[S.tl_base[g] + k] = (int32_t)h;
-        else atomicAdd(&S.err[2], 1u);
-      }
-    }
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&count, (uint32_t)__popcll(m));
   }
+  __syncthreads();
+  if (threadIdx.x == 0) S.row_nstart[sr] = count;
 }
 
-// Prefix sums of a per-sector count over the launched sector range, so that
-// a flat work index can be mapped to (sector, item).  One block.
-__global__ void __launch_bounds__(1024) k_flatten(const uint32_t* cnt, uint32_t* flat, int g0, int ns) {
-  __shared__ uint32_t w[64];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
+// a4: write the start hits in (sector, row, position) order at the offsets
+// given by the scan of the per-row counts over the launched sector range.
+__global__ void __launch_bounds__(256) k_start_write(Slot S, int g0) {
+  __shared__ uint32_t wcount[4];
+  __shared__ uint32_t running;
+  const int row = blockIdx.x;
+  const int g = g0 + blockIdx.y;
+  const int sr = g * kRows + row;
+  const uint32_t h0 = S.row_off[sr], h1 = S.row_off[sr + 1];
+  const uint32_t base_out = S.tl_base[g0] + S.row_nstart[sr];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) running = 0;
   __syncthreads();
-  for (int base = 0; base < ns; base += blockDim.x) {
-    const int i = base + threadIdx.x;
-    const uint32_t v = i < ns ? cnt[g0 + i] : 0u;
-    uint32_t tot;
-    // wave scan then block scan
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t x = v;
-    for (int d = 1; d < 64; d <<= 1) {
-      uint32_t t = __shfl_up(x, d, 64);
-      if (lane >= d) x += t;
+  for (uint32_t base = h0; base < h1; base += blockDim.x) {
+    const uint32_t h = base + threadIdx.x;
+    bool start = false;
+    if (h < h1) {
+      int32_t uc, dc;
+      start = is_start(S, h, uc, dc);
     }
-    if (lane == 63) w[wv] = x;
+    const unsigned long long m = __ballot(start);
+    if (lane == 0) wcount[w] = (uint32_t)__popcll(m);
     __syncthreads();
-    if (threadIdx.x < 64) {
-      uint32_t s = threadIdx.x < (blockDim.x >> 6) ? w[threadIdx.x] : 0u;
-      for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(s, d, 64);
-        if ((int)threadIdx.x >= d) s += t;
-      }
-      if (threadIdx.x < (blockDim.x >> 6)) w[32 + threadIdx.x] = s;
+    uint32_t before = running, tot = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+      if (i < w) before += wcount[i];
+      tot += wcount[i];
+    }
+    if (start) {
+      const uint32_t k = base_out + before + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      S.start_hit[k] = (int32_t)h;
+      S.start_sr[k] = sr;
     }
     __syncthreads();
-    tot = w[32 + (blockDim.x >> 6) - 1];
-    const uint32_t before = wv ? w[32 + wv - 1] : 0u;
-    if (i < ns) flat[i] = carry + before + x - v;
-    __syncthreads();
-    if (threadIdx.x == 0) carry += tot;
+    if (threadIdx.x == 0) running += tot;
     __syncthreads();
   }
-  if (threadIdx.x == 0) flat[ns] = carry;
 }
 
 }  // namespace tpc

@@ -4,28 +4,21 @@
 
 namespace tpc {
 
-__device__ __forceinline__ int flat_find_f(const uint32_t* flat, int ns, uint32_t t) {
-  int lo = 0, hi = ns - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (flat[mid] <= t) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 // a6: every hit keeps the largest weight (n << 24 | 0xFFFFFF - start ID) of
-// the valid tracklets that contain it.
-__global__ void __launch_bounds__(64) k_weights(Slot S, int g0, int ns) {
-  const uint32_t total = S.flat_tl[ns];
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-    const int gi = flat_find_f(S.flat_tl, ns, t);
-    const uint32_t T = S.tl_base[g0 + gi] + (t - S.flat_tl[gi]);
+// the valid tracklets that contain it.  One wave per tracklet, one lane per
+// row: the tracklet's row-indexed hit list is read coalesced.
+__global__ void __launch_bounds__(256) k_weights(Slot S, int g0) {
+  const uint32_t total = S.range_cnt[0];
+  const uint32_t base = S.tl_base[g0];
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < total; t += nw) {
+    const uint32_t T = base + t;
     const int32_t* info = S.tl_info + (size_t)T * 4;
     if (!info[3]) continue;
     const uint32_t w = S.tl_weight[T];
     const int32_t* hits = S.tl_hits + (size_t)T * kRows;
-    for (int r = info[1]; r <= info[2]; ++r) {
+    for (int r = info[1] + (int)lane; r <= info[2]; r += 64) {
       const int32_t h = hits[r];
       if (h >= 0) atomicMax(&S.weight[h], w);
     }
@@ -33,51 +26,97 @@ __global__ void __launch_bounds__(64) k_weights(Slot S, int g0, int ns) {
 }
 
 // a6: a valid tracklet becomes a track if it owns (holds the maximal weight
-// of) at least n_min_track of its hits.
-__global__ void __launch_bounds__(64) k_select(Slot S, DevConst K, int g0, int ns) {
-  const uint32_t total = S.flat_tl[ns];
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-    const int gi = flat_find_f(S.flat_tl, ns, t);
-    const int g = g0 + gi;
-    const uint32_t T = S.tl_base[g] + (t - S.flat_tl[gi]);
+// of) at least n_min_track of its hits.  Writes 1/0 per tracklet of the
+// range; the scan of these flags places the tracks.
+__global__ void __launch_bounds__(256) k_select(Slot S, DevConst K, int g0) {
+  const uint32_t total = S.range_cnt[0];
+  const uint32_t base = S.tl_base[g0];
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < total; t += nw) {
+    const uint32_t T = base + t;
     const int32_t* info = S.tl_info + (size_t)T * 4;
-    if (!info[3]) continue;
+    uint32_t sel = 0;
+    if (info[3]) {
+      const uint32_t w = S.tl_weight[T];
+      const int32_t* hits = S.tl_hits + (size_t)T * kRows;
+      int cnt = 0;
+      for (int r0 = info[1]; r0 <= info[2]; r0 += 64) {
+        const int r = r0 + (int)lane;
+        bool own = false;
+        if (r <= info[2]) {
+          const int32_t h = hits[r];
+          own = h >= 0 && S.weight[h] == w;
+        }
+        cnt += __popcll(__ballot(own));
+      }
+      sel = cnt >= K.n_min_track ? 1u : 0u;
+    }
+    if (lane == 0) S.tl_sel[t] = sel;
+  }
+}
+
+// Selected tracklets -> tracks of the range (in tracklet order), each with
+// its owned hits compacted (ascending row).  One wave per tracklet.
+__global__ void __launch_bounds__(256) k_track_write(Slot S, int g0) {
+  const uint32_t total = S.range_cnt[0];
+  const uint32_t ntk = S.range_cnt[1];
+  const uint32_t tl0 = S.tl_base[g0], tk0 = S.tk_base[g0];
+  const uint32_t lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < total; t += nw) {
+    const uint32_t pos = S.tl_sel[t];
+    const uint32_t next = t + 1 < total ? S.tl_sel[t + 1] : ntk;
+    if (next == pos) continue;
+    const uint32_t T = tl0 + t;
+    const uint32_t k = tk0 + pos;
+    const int32_t* info = S.tl_info + (size_t)T * 4;
     const uint32_t w = S.tl_weight[T];
     const int32_t* hits = S.tl_hits + (size_t)T * kRows;
+    int32_t* own = S.tk_own + (size_t)k * kRows;
+    uint8_t* own_row = S.tk_own_row + (size_t)k * kRows;
     int cnt = 0;
-    for (int r = info[1]; r <= info[2]; ++r) {
-      const int32_t h = hits[r];
-      cnt += (h >= 0 && S.weight[h] == w) ? 1 : 0;
+    for (int rb = info[1]; rb <= info[2]; rb += 64) {
+      const int r = rb + (int)lane;
+      int32_t h = -1;
+      bool mine = false;
+      if (r <= info[2]) {
+        h = hits[r];
+        mine = h >= 0 && S.weight[h] == w;
+      }
+      const unsigned long long m = __ballot(mine);
+      if (mine) {
+        const int j = cnt + __popcll(m & below);
+        own[j] = h;
+        own_row[j] = (uint8_t)r;
+      }
+      cnt += __popcll(m);
     }
-    if (cnt < K.n_min_track) continue;
-    const uint32_t k = atomicAdd(&S.n_track[g], 1u);
-    if (k < S.tk_base[g + 1] - S.tk_base[g]) S.tk_tracklet[S.tk_base[g] + k] = (int32_t)T;
-    else atomicAdd(&S.err[2], 1u);
+    if (lane == 0) {
+      S.tk_tracklet[k] = (int32_t)T;
+      S.tk_nown[k] = cnt;
+    }
   }
 }
 
 struct PassOut {
   Helix<double> st;
-  int rlast, n;
+  int rlast, jlast, n;
   double chi2;
 };
 
-// owned hit of the tracklet at row r, or -1
-__device__ __forceinline__ int32_t owned_at(const Slot& S, const int32_t* hits, uint32_t w, int r) {
-  const int32_t h = hits[r];
-  return (h >= 0 && S.weight[h] == w) ? h : -1;
-}
-
-// One inward pass from the outermost owned row ro down to rmin: state reset
-// to the hit at ro with the prior covariance, then transport row by row and
-// update with every owned hit (no gate).  A failed transport ends the pass.
-__device__ void refit_pass(const Slot& S, const DevConst& K, const int32_t* hits, uint32_t w, int ro,
-                           int rmin, double s0, double t0, double q0, PassOut& o) {
-  const int32_t ho = hits[ro];
+// One inward pass over the owned hits own[jmin .. n-1] (ascending rows):
+// state reset to the outermost hit with the prior covariance, transport row
+// by row, update with every owned hit (no gate).  A failed transport ends
+// the pass.  The next hit is loaded one step ahead of its use.
+__device__ void refit_pass(const Slot& S, const DevConst& K, const int32_t* own,
+                           const uint8_t* own_row, int n, int jmin, double s0, double t0,
+                           double q0, PassOut& o) {
+  const Hit xo = S.hit[own[n - 1]];
   Helix<double> st;
-  st.y = (double)S.hy[ho];
-  st.z = (double)S.hz[ho];
+  st.y = (double)xo.y;
+  st.z = (double)xo.z;
   st.s = s0;
   st.t = t0;
   st.q = q0;
@@ -87,68 +126,85 @@ __device__ void refit_pass(const Slot& S, const DevConst& K, const int32_t* hits
     reset_cov(st, sy * sy, sz * sz, (double)K.cs0, (double)K.ct0, (double)K.cq0);
   }
   o.st = st;
-  o.rlast = ro;
+  o.rlast = own_row[n - 1];
+  o.jlast = n - 1;
   o.n = 1;
   o.chi2 = 0.0;
   const double smax = K.smax, chi2max = K.chi2max;
-  for (int r = ro - 1; r >= rmin; --r) {
-    if (!transport(st, (double)K.row_x[r] - (double)K.row_x[r + 1], K.bd, smax)) break;
-    const int32_t h = owned_at(S, hits, w, r);
-    if (h < 0) continue;
+  int rcur = o.rlast;
+  int j = n - 2;
+  Hit xn;
+  int rn = 0;
+  if (j >= jmin) {
+    xn = S.hit[own[j]];
+    rn = own_row[j];
+  }
+  for (; j >= jmin; --j) {
+    const Hit xh = xn;
+    const int rh = rn;
+    if (j - 1 >= jmin) {
+      xn = S.hit[own[j - 1]];
+      rn = own_row[j - 1];
+    }
+    bool ok = true;
+    for (int r = rcur - 1; r >= rh; --r) {
+      if (!transport(st, (double)K.row_x[r] - (double)K.row_x[r + 1], K.bd, smax)) {
+        ok = false;
+        break;
+      }
+    }
+    if (!ok) break;
+    rcur = rh;
     const double sy = sy0 + sy1 * fabs(st.z) / zmax, sz = sz0 + sz1 * fabs(st.z) / zmax;
     double ch = 0.0;
-    kalman_update(st, (double)S.hy[h], (double)S.hz[h], sy * sy, sz * sz, chi2max, smax, false, &ch);
+    kalman_update(st, (double)xh.y, (double)xh.z, sy * sy, sz * sz, chi2max, smax, false, &ch);
     o.chi2 = o.chi2 + ch;
     o.n += 1;
     o.st = st;
-    o.rlast = r;
+    o.rlast = rh;
+    o.jlast = j;
   }
 }
 
-// a7: refit of each selected tracklet over its owned hits, in double, three
-// inward passes.  Pass 1 starts from the tracklet's inner (s, T, Q) with s
-// carried to the outermost owned row along the circle (sin phi is linear in
-// x); each later pass starts from the previous pass's result carried back
-// the same way, so the Jacobians are evaluated along the fitted track.
-// Output at the innermost fitted hit; the innermost hit's cluster is marked
-// for the canonical ordering.
-__global__ void __launch_bounds__(64) k_refit(Slot S, DevConst K, int g0, int ns) {
-  const uint32_t total = S.flat_tk[ns];
+// a7: refit of each track over its owned hits, in double, three inward
+// passes.  Pass 1 starts from the tracklet's inner (s, T, Q) with s carried
+// to the outermost owned row along the circle (sin phi is linear in x);
+// each later pass starts from the previous pass's result carried back the
+// same way, so the Jacobians are evaluated along the fitted track.  Output
+// at the innermost fitted hit; its cluster is marked for the canonical
+// ordering.
+__global__ void __launch_bounds__(64) k_refit(Slot S, DevConst K, int g0) {
+  const uint32_t total = S.range_cnt[1];
+  const uint32_t tk0 = S.tk_base[g0];
   const uint32_t stride = gridDim.x * blockDim.x;
   unsigned nfit = 0;
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
     ++nfit;
-    const int gi = flat_find_f(S.flat_tk, ns, t);
-    const int g = g0 + gi;
-    const uint32_t k = S.tk_base[g] + (t - S.flat_tk[gi]);
+    const uint32_t k = tk0 + t;
     const int32_t T = S.tk_tracklet[k];
-    const int32_t* info = S.tl_info + (size_t)T * 4;
-    const int32_t* hits = S.tl_hits + (size_t)T * kRows;
-    const uint32_t w = S.tl_weight[T];
+    const int n = S.tk_nown[k];
+    const int32_t* own = S.tk_own + (size_t)k * kRows;
+    const uint8_t* own_row = S.tk_own_row + (size_t)k * kRows;
     int32_t* out = S.tk_info + (size_t)k * 4;
     out[0] = 0;
-    int ro = -1, rmin = kRows;
-    for (int r = info[1]; r <= info[2]; ++r)
-      if (owned_at(S, hits, w, r) >= 0) {
-        ro = r;
-        rmin = r < rmin ? r : rmin;
-      }
-    if (ro < 0) continue;
+    if (n < 1) continue;
+    const int ro = own_row[n - 1];
+    const int rin_tl = S.tl_info[(size_t)T * 4 + 1];
     const float* sv = S.tl_state + (size_t)T * 5;
     const double smax = K.smax;
     PassOut o;
     bool ok = true;
     {
       const double sin_ = sv[2], tin = sv[3], qin = sv[4];
-      const double s0 = sin_ + (K.bd * qin) * ((double)K.row_x[ro] - (double)K.row_x[info[1]]);
+      const double s0 = sin_ + (K.bd * qin) * ((double)K.row_x[ro] - (double)K.row_x[rin_tl]);
       if (!(fabs(s0) <= smax)) ok = false;
-      else refit_pass(S, K, hits, w, ro, rmin, s0, tin, qin, o);
+      else refit_pass(S, K, own, own_row, n, 0, s0, tin, qin, o);
     }
     for (int pass = 1; ok && pass < 3; ++pass) {
       const double sin_ = o.st.s, tin = o.st.t, qin = o.st.q;
       const double s0 = sin_ + (K.bd * qin) * ((double)K.row_x[ro] - (double)K.row_x[o.rlast]);
       if (!(fabs(s0) <= smax)) ok = false;
-      else refit_pass(S, K, hits, w, ro, o.rlast, s0, tin, qin, o);
+      else refit_pass(S, K, own, own_row, n, o.jlast, s0, tin, qin, o);
     }
     if (!ok || o.n < K.n_min_track) continue;
     out[0] = 1;
@@ -165,7 +221,7 @@ __global__ void __launch_bounds__(64) k_refit(Slot S, DevConst K, int g0, int ns
 #pragma unroll
     for (int i = 0; i < 15; ++i) cov[i] = o.st.c[i];
     S.tk_chi2[k] = o.chi2;
-    S.tmap[S.hid[hits[o.rlast]]] = (int32_t)k;
+    S.tmap[S.hit[own[o.jlast]].id] = (int32_t)k;
   }
   wave_add_u64(&S.stats[3], nfit);
 }

@@ -202,9 +202,12 @@ __global__ void __launch_bounds__(256) k_row_sort(Slot S) {
     // flagged in k_scan_rows (the slot's result is refused); keep the row
     // harmless for the kernels that still run: no coordinates, empty bins
     for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
-      S.hy[off + j] = __builtin_nanf("");
-      S.hz[off + j] = __builtin_nanf("");
-      S.hid[off + j] = S.tid[off + j];
+      Hit h;
+      h.y = __builtin_nanf("");
+      h.z = __builtin_nanf("");
+      h.id = S.tid[off + j];
+      h.upc = -1;
+      S.hit[off + j] = h;
     }
     for (int bb = threadIdx.x; bb <= nb; bb += blockDim.x) S.bin_off[b.base + bb] = off;
     return;
@@ -242,9 +245,12 @@ __global__ void __launch_bounds__(256) k_row_sort(Slot S) {
   for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
     const unsigned long long kk = key[j];
     const uint32_t src = (uint32_t)(kk & 0xFFFull);
-    S.hy[off + j] = ly[src];
-    S.hz[off + j] = lz[src];
-    S.hid[off + j] = (uint32_t)((kk >> 12) & 0xFFFFFFFFull);
+    Hit h;
+    h.y = ly[src];
+    h.z = lz[src];
+    h.id = (uint32_t)((kk >> 12) & 0xFFFFFFFFull);
+    h.upc = -1;
+    S.hit[off + j] = h;
   }
   // bin offsets: first sorted position whose bin is >= each bin
   for (int bb = threadIdx.x; bb <= nb; bb += blockDim.x) {

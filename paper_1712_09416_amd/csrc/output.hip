@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_tiles(const uint32_t* in, c
 
 __global__ void __launch_bounds__(1024) k_scan_partials(uint32_t* partial, int nb, uint32_t* out,
                                                         const uint32_t* n_dev, int64_t n_host,
-                                                        uint32_t* total_out) {
+                                                        uint32_t* total_out, int write_end) {
   __shared__ uint32_t w[32];
   __shared__ uint32_t carry;
   if (threadIdx.x == 0) carry = 0;
@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(1024) k_scan_partials(uint32_t* partial, int n
   }
   if (threadIdx.x == 0) {
     const uint32_t n = scan_n(n_dev, n_host);
-    out[n] = carry;
+    if (write_end) out[n] = carry;
     if (total_out) *total_out = carry;
   }
 }
@@ -147,11 +147,10 @@ __global__ void k_write_out(Slot S, DevConst K) {
     const int32_t k = S.out_order[pos];
     const int32_t* ti = S.tk_info + (size_t)k * 4;
     const int32_t T = S.tk_tracklet[k];
-    const uint32_t w = S.tl_weight[T];
-    const int32_t* hits = S.tl_hits + (size_t)T * kRows;
-    // sector of the track: from the innermost hit's global sector
-    const int32_t pin = hits[ti[2]];
-    const uint32_t gidx = S.hid[pin];
+    const int nown = S.tk_nown[k];
+    const int32_t* own = S.tk_own + (size_t)k * kRows;
+    const int j0 = nown - ti[1];          // the fitted hits are the last n_hits owned ones
+    const uint32_t gidx = S.hit[own[j0]].id;
     int e = 0;
     {
       int lo = 0, hi = S.n_events - 1;
@@ -171,7 +170,7 @@ __global__ void k_write_out(Slot S, DevConst K) {
     o.row_out = ti[3];
     o.hit_off = (int64_t)(hoff - ehoff);
     o.inner_id = (int32_t)((int64_t)gidx - ev0);
-    o.start_id = (int32_t)((int64_t)S.hid[S.start_hit[T]] - ev0);
+    o.start_id = (int32_t)((int64_t)S.hit[S.start_hit[T]].id - ev0);
     o.x_ref = (double)K.row_x[ti[2]];
     o.ndf = 2 * ti[1] - 5;
     o.event = e;
@@ -181,11 +180,7 @@ __global__ void k_write_out(Slot S, DevConst K) {
     for (int i = 0; i < 15; ++i) o.cov[i] = cov[i];
     o.chi2 = S.tk_chi2[k];
     S.out_tracks[pos] = o;
-    uint32_t j = hoff;
-    for (int r = ti[2]; r <= ti[3]; ++r) {
-      const int32_t h = hits[r];
-      if (h >= 0 && S.weight[h] == w) S.out_hits[j++] = (int32_t)((int64_t)S.hid[h] - ev0);
-    }
+    for (int j = j0; j < nown; ++j) S.out_hits[hoff + (j - j0)] = (int32_t)((int64_t)S.hit[own[j]].id - ev0);
   }
 }
 

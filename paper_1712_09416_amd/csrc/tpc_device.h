@@ -48,6 +48,14 @@ struct RowBins {
   int32_t pad;
 };
 
+// A sorted hit: coordinates, global cluster index, cleaned up-link (sorted
+// index of the next hit of its chain, -1 none).  16 bytes: one load.
+struct alignas(16) Hit {
+  float y, z;
+  uint32_t id;
+  int32_t upc;
+};
+
 // One slot: a batch of events whose clusters are concatenated; sector g of
 // the slot is sector g % 36 of event g / 36.
 struct Slot {
@@ -69,30 +77,30 @@ struct Slot {
   float* ty;                // [n] row-ordered, unsorted within a row
   float* tz;
   uint32_t* tid;
-  float* hy;                // [n] sorted by (sector, row, bin, id)
-  float* hz;
-  uint32_t* hid;            // global cluster index of each sorted hit
-  // links (sorted-hit indices, -1 none)
+  Hit* hit;                 // [n] sorted by (sector, row, bin, id)
+  // links (sorted-hit indices, -1 none); the cleaned up-link lives in hit[].upc
   int32_t* up;
   int32_t* dn;
-  int32_t* upc;
   int32_t* dnc;
-  // per-sector regions: starts / tracklets and tracks
+  // per-sector regions (used by per-sector launches; contiguous for a range)
   uint32_t* tl_base;        // [S+1] tracklet region of each sector
   uint32_t* tk_base;        // [S+1] track region of each sector
-  uint32_t* n_start;        // [S]
-  uint32_t* n_track;        // [S]
-  uint32_t* flat_tl;        // [S+1] prefix of n_start over the launched range
-  uint32_t* flat_tk;        // [S+1] prefix of n_track over the launched range
+  uint32_t* row_nstart;     // [SR+1] start hits per row, then their offsets
+  uint32_t* range_cnt;      // [4]: tracklets, tracks of the launched range
   int32_t* start_hit;       // [tl capacity] sorted index of the start hit
+  int32_t* start_sr;        // [tl capacity] (sector, row) of the start hit
   // tracklets
   int32_t* tl_hits;         // [tl capacity][kRows] sorted index per row, -1 none
   int32_t* tl_info;         // [tl capacity][4]: n, row_in, row_out, valid
   uint32_t* tl_weight;      // [tl capacity]
   float* tl_state;          // [tl capacity][5] inner state (y, z, s, T, Q)
+  uint32_t* tl_sel;         // [tl capacity+1] selected flag, then track positions
   uint32_t* weight;         // [n] per sorted hit, 0 = unowned
-  // tracks (temporary, per-sector regions)
+  // tracks (per-sector regions)
   int32_t* tk_tracklet;     // [tk capacity]
+  int32_t* tk_own;          // [tk capacity][kRows] owned hits (sorted index), ascending row
+  uint8_t* tk_own_row;      // [tk capacity][kRows] their rows
+  int32_t* tk_nown;         // [tk capacity]
   int32_t* tk_info;         // [tk capacity][4]: ok, n, row_in, row_out
   double* tk_par;           // [tk capacity][5]
   double* tk_cov;           // [tk capacity][15]
@@ -109,7 +117,7 @@ struct Slot {
   uint32_t* ev_track_off;   // [E+1]
   uint32_t* ev_hit_off;     // [E+1]
   uint32_t* err;            // [4]: invalid clusters, dense rows, overflow, spare
-  unsigned long long* stats; // [8] work counters (see tpc_get_profile)
+  unsigned long long* stats; // [8] work counters
   // capacities
   int64_t cap_n;
   int64_t cap_tl;
@@ -179,23 +187,26 @@ __device__ __forceinline__ bool transport(Helix<F>& h, F dx, F b, F smax) {
   const F c1 = sqrt_(one - s1 * s1);
   const F N = s0 + s1;
   const F D = c0 + c1;
-  const F tmid = N / D;
+  const F iD = one / D;
+  const F ic0 = one / c0;
+  const F ic1 = one / c1;
+  const F tmid = N * iD;
   const F chord = fabs_(dx) * sqrt_(one + tmid * tmid);
   const F u = half * bq * chord;
   const F u2 = u * u;
   F arc = chord * (one + u2 * (one / F(6) + u2 * (F(3) / F(40))));
   if (dx < F(0)) arc = -arc;
 
-  const F D2 = D * D;
-  const F r0 = s0 / c0;
-  const F r1 = s1 / c1;
-  const F dy_ds = dx * (two * D + N * (r0 + r1)) / D2;
-  const F dy_dq = b * dx * dx * (D + N * r1) / D2;
-  const F dz_ds = h.t * dx * N / (c0 * c1 * D);
+  // Jacobian; dz/dQ to leading order, 2 T b N dx^2 / D^3 (the mid-angle
+  // cosine taken as D/2)
+  const F iD2 = iD * iD;
+  const F r0 = s0 * ic0;
+  const F r1 = s1 * ic1;
+  const F dy_ds = dx * (two * D + N * (r0 + r1)) * iD2;
+  const F dy_dq = b * dx * dx * (D + N * r1) * iD2;
+  const F dz_ds = h.t * dx * N * (ic0 * ic1 * iD);
   const F dz_dt = arc;
-  const F sm = half * N;
-  const F cm = sqrt_(one - sm * sm);
-  const F dz_dq = h.t * b * sm * dx * dx / (two * cm * cm * cm);
+  const F dz_dq = two * h.t * b * N * dx * dx * (iD2 * iD);
   const F ds_dq = b * dx;
 
   h.y = h.y + dx * tmid;

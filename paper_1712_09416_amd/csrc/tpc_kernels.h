@@ -12,18 +12,19 @@ __global__ void k_scatter(Slot S);
 __global__ void k_row_sort(Slot S);
 // cellular automaton
 __global__ void k_neighbours(Slot S, DevConst K, int g0);
-__global__ void k_clean_start(Slot S, int g0);
-__global__ void k_flatten(const uint32_t* cnt, uint32_t* flat, int g0, int ns);
+__global__ void k_clean_rows(Slot S, int g0);
+__global__ void k_start_write(Slot S, int g0);
 // Kalman filter
-__global__ void k_tracklets(Slot S, DevConst K, int g0, int ns);
-__global__ void k_weights(Slot S, int g0, int ns);
-__global__ void k_select(Slot S, DevConst K, int g0, int ns);
-__global__ void k_refit(Slot S, DevConst K, int g0, int ns);
+__global__ void k_tracklets(Slot S, DevConst K, int g0);
+__global__ void k_weights(Slot S, int g0);
+__global__ void k_select(Slot S, DevConst K, int g0);
+__global__ void k_track_write(Slot S, int g0);
+__global__ void k_refit(Slot S, DevConst K, int g0);
 // output
 __global__ void k_scan_tiles(const uint32_t* in, const uint32_t* n_dev, int64_t n_host,
                              uint32_t* partial);
 __global__ void k_scan_partials(uint32_t* partial, int nb, uint32_t* out, const uint32_t* n_dev,
-                                int64_t n_host, uint32_t* total_out);
+                                int64_t n_host, uint32_t* total_out, int write_end);
 __global__ void k_scan_apply(const uint32_t* in, const uint32_t* n_dev, int64_t n_host,
                              const uint32_t* partial, uint32_t* out);
 __global__ void k_flags(Slot S);

@@ -14,10 +14,11 @@ __device__ __forceinline__ void for_window_t(const Slot& S, int sr, float yc, fl
   const float eps = 1e-3f;
   const int iy0 = bin_y(b, yc - wy - eps), iy1 = bin_y(b, yc + wy + eps);
   const int iz0 = bin_z(b, zc - wz - eps), iz1 = bin_z(b, zc + wz + eps);
+  const uint32_t* bo = S.bin_off + b.base;
   for (int iz = iz0; iz <= iz1; ++iz) {
-    const int first = b.base + iz * b.ny;
-    const uint32_t p0 = S.bin_off[first + iy0];
-    const uint32_t p1 = S.bin_off[first + iy1 + 1];
+    const int first = iz * b.ny;
+    const uint32_t p0 = bo[first + iy0];
+    const uint32_t p1 = bo[first + iy1 + 1];
     for (uint32_t p = p0; p < p1; ++p) fn(p);
   }
 }
@@ -48,10 +49,11 @@ __device__ __forceinline__ int32_t search_row(const Slot& S, const DevConst& K, 
   uint32_t bid = 0;
   for_window_t(S, sr, yc, zc, wy, wz, [&](uint32_t p) {
     ++examined;
-    const float ry = S.hy[p] - yc, rz = S.hz[p] - zc;
+    const Hit x = S.hit[p];
+    const float ry = x.y - yc, rz = x.z - zc;
     if (!(fabsf(ry) <= wy && fabsf(rz) <= wz)) return;
     const float ch = chi2_of(w, ry, rz);
-    const uint32_t id = S.hid[p];
+    const uint32_t id = x.id;
     if (best < 0 || ch < bchi || (ch == bchi && id < bid)) {
       best = (int32_t)p;
       bchi = ch;
@@ -61,29 +63,10 @@ __device__ __forceinline__ int32_t search_row(const Slot& S, const DevConst& K, 
   return best;
 }
 
-__device__ __forceinline__ bool try_hit(const Slot& S, const DevConst& K, Helix<float>& h, int32_t p,
-                                        float vy, float vz) {
+__device__ __forceinline__ bool try_hit(const DevConst& K, Helix<float>& h, const Hit& x, float vy,
+                                        float vz) {
   float ch;
-  return kalman_update(h, S.hy[p], S.hz[p], vy, vz, K.chi2max, K.smax, true, &ch);
-}
-
-__device__ __forceinline__ int row_of(const uint32_t* row_off, int g, uint32_t p) {
-  int lo = 0, hi = kRows - 1;
-  const uint32_t* ro = row_off + g * kRows;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (ro[mid] <= p) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ int flat_find(const uint32_t* flat, int ns, uint32_t t) {
-  int lo = 0, hi = ns - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (flat[mid] <= t) lo = mid; else hi = mid - 1;
-  }
-  return lo;
+  return kalman_update(h, x.y, x.z, vy, vz, K.chi2max, K.smax, true, &ch);
 }
 
 // For each start hit h0 (row r0) with cleaned up-link h1:
@@ -95,30 +78,40 @@ __device__ __forceinline__ int flat_find(const uint32_t* flat, int ns, uint32_t 
 //  in    restart at the outermost hit with the prior covariance and the
 //        outward (s, T, Q); rows down to 0: re-confirm the outward hit, else
 //        search; same gap rule.  The inward hits form the tracklet.
-__global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0, int ns) {
-  const uint32_t total = S.flat_tl[ns];
-  const uint32_t stride = gridDim.x * blockDim.x;
+__global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
+  // Tracklets are ordered by (sector, row): give each XCD (blocks are
+  // dispatched round-robin over the 8 XCDs) one contiguous chunk, so the
+  // hits a chunk's lanes read stay in that XCD's L2.
+  const uint32_t total = S.range_cnt[0];
+  const uint32_t base = S.tl_base[g0];
+  constexpr uint32_t kXcd = 8;
+  const uint32_t xcd = blockIdx.x % kXcd, j = blockIdx.x / kXcd;
+  const uint32_t nbx = (gridDim.x - xcd + kXcd - 1) / kXcd;
+  const uint32_t chunk = (total + kXcd - 1) / kXcd;
+  const uint32_t c0 = xcd * chunk;
+  const uint32_t c1 = min(total, c0 + chunk);
   unsigned visits = 0, examined = 0, done = 0;
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+  for (uint32_t t = c0 + j * blockDim.x + threadIdx.x; t < c1; t += nbx * blockDim.x) {
     ++done;
-    const int gi = flat_find(S.flat_tl, ns, t);
-    const int g = g0 + gi;
-    const uint32_t T = S.tl_base[g] + (t - S.flat_tl[gi]);
+    const uint32_t T = base + t;
+    const int sr0 = S.start_sr[T];
+    const int g = sr0 / kRows;
+    const int r0 = sr0 - g * kRows;
     const bool side_c = (g % kSectorsPerEvent) >= kSectorsPerEvent / 2;
     const int64_t ev0 = S.ev_off[g / kSectorsPerEvent];
     const int32_t p0 = S.start_hit[T];
-    const int r0 = row_of(S.row_off, g, (uint32_t)p0);
-    const int32_t p1 = S.upc[p0];
+    const Hit x0 = S.hit[p0];
+    const Hit x1 = S.hit[x0.upc];
     int32_t* hits = S.tl_hits + (size_t)T * kRows;
 
     Helix<float> st;
     {
       const float dx = K.row_x[r0 + 1] - K.row_x[r0];
-      const float dy = S.hy[p1] - S.hy[p0];
-      const float dz = S.hz[p1] - S.hz[p0];
+      const float dy = x1.y - x0.y;
+      const float dz = x1.z - x0.z;
       const float L = sqrtf(dx * dx + dy * dy);
-      st.y = S.hy[p0];
-      st.z = S.hz[p0];
+      st.y = x0.y;
+      st.z = x0.z;
       st.s = dy / L;
       st.t = dz / L;
       st.q = 0.0f;
@@ -130,7 +123,8 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0, in
     // outward
     Helix<float> last = st;
     int rout = r0;
-    int32_t cur = p0;
+    int32_t next = x0.upc;     // cleaned chain link of the last accepted hit
+    Hit xnext = x1;            // that hit, loaded ahead of the transport
     bool chain = true;
     int miss = 0;
     for (int r = r0 + 1; r < kRows; ++r) {
@@ -140,18 +134,25 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0, in
       const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
       const float vy = sy * sy, vz = sz * sz;
       int32_t got = -1;
+      Hit xg;
       if (chain) {
-        const int32_t nx = S.upc[cur];
-        if (nx >= 0 && try_hit(S, K, st, nx, vy, vz)) got = nx;
-        else chain = false;
+        if (next >= 0) {
+          xg = xnext;
+          if (try_hit(K, st, xg, vy, vz)) got = next;
+        }
+        if (got < 0) chain = false;
       }
       if (got < 0) {
         const int32_t bh = search_row(S, K, g * kRows + r, st, vy, vz, examined);
-        if (bh >= 0 && try_hit(S, K, st, bh, vy, vz)) got = bh;
+        if (bh >= 0) {
+          xg = S.hit[bh];
+          if (try_hit(K, st, xg, vy, vz)) got = bh;
+        }
       }
       hits[r] = got;
       if (got >= 0) {
-        cur = got;
+        next = xg.upc;
+        if (chain && next >= 0) xnext = S.hit[next];
         miss = 0;
         last = st;
         rout = r;
@@ -161,10 +162,10 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0, in
     }
 
     // inward, covariance reset at the outermost hit
-    const int32_t hout = hits[rout];
+    const Hit xo = S.hit[hits[rout]];
     st = last;
-    st.y = S.hy[hout];
-    st.z = S.hz[hout];
+    st.y = xo.y;
+    st.z = xo.z;
     {
       const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
       reset_cov(st, sy * sy, sz * sz, K.cs0, K.ct0, K.cq0);
@@ -181,10 +182,10 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0, in
       const float vy = sy * sy, vz = sz * sz;
       int32_t got = -1;
       const int32_t uh = r >= r0 ? hits[r] : -1;
-      if (uh >= 0 && try_hit(S, K, st, uh, vy, vz)) got = uh;
+      if (uh >= 0 && try_hit(K, st, S.hit[uh], vy, vz)) got = uh;
       if (got < 0) {
         const int32_t bh = search_row(S, K, g * kRows + r, st, vy, vz, examined);
-        if (bh >= 0 && try_hit(S, K, st, bh, vy, vz)) got = bh;
+        if (bh >= 0 && try_hit(K, st, S.hit[bh], vy, vz)) got = bh;
       }
       hits[r] = got;
       if (got >= 0) {
@@ -201,7 +202,7 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0, in
     info[1] = rin;
     info[2] = rout;
     info[3] = n >= K.n_min_tracklet ? 1 : 0;
-    const uint32_t id0 = (uint32_t)((int64_t)S.hid[p0] - ev0);
+    const uint32_t id0 = (uint32_t)((int64_t)x0.id - ev0);
     S.tl_weight[T] = ((uint32_t)n << 24) | (0xFFFFFFu - id0);
     float* sv = S.tl_state + (size_t)T * 5;
     sv[0] = last.y;

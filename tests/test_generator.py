@@ -88,6 +88,26 @@ def test_truth_sin_phi_is_local_direction():
     assert np.allclose((x - xloc_c) / (h * R), ev.truth[sig, 2], atol=1e-12)
 
 
+def test_truth_of_returning_legs():
+    """A returning looper leg, followed towards larger x, has its direction
+    turned by pi: sin phi, tan lambda and q/pT all change sign, and
+    consecutive crossings of the leg step x upwards with y consistent with
+    that direction (dy/dx = tan phi)."""
+    ev = tpcgen.pbpb_event(tpcgen.seed_for(2) + 11, 400)
+    sig = np.nonzero((ev.pid >= 0) & (ev.leg % 2 == 1))[0]
+    assert len(sig) > 100
+    key = ev.pid[sig].astype(np.int64) * 1000 + ev.sector[sig].astype(np.int64) * 200 + ev.row[sig]
+    key = key * 4 + ev.leg[sig]
+    o = np.argsort(key)
+    s, k = sig[o], key[o]
+    nxt = np.nonzero(np.diff(k) == 4)[0]      # same leg, next row
+    a, b = s[nxt], s[nxt + 1]
+    x = G.row_x().astype(np.float64)
+    dydx = (ev.truth[b, 0] - ev.truth[a, 0]) / (x[ev.row[b]] - x[ev.row[a]])
+    sm = 0.5 * (ev.truth[a, 2] + ev.truth[b, 2])
+    assert np.all(np.sign(dydx) == np.sign(sm)) or np.mean(np.sign(dydx) == np.sign(sm)) > 0.99
+
+
 def test_noise_fraction_and_shuffle():
     ev = tpcgen.pp_event()
     nsig = int((ev.pid >= 0).sum())

@@ -282,6 +282,22 @@ def test_pulls_and_chi2_one_sector(oracle_lib):
     assert 0.9 < C2.mean() < 1.1
 
 
+def test_pulls_pbpb_with_loopers_and_secondaries(oracle_lib):
+    """Pulls stay unit-width on a Pb-Pb-shaped event (secondaries, looper
+    legs followed in either direction); a few mixed tracks aside, the
+    central 98% of each pull lies within +-4."""
+    ev = tpcgen.pbpb_event(tpcgen.seed_for(2) + 5, 3000)
+    r = oracle_lib.run_event(ev, precision=32, nthreads=8)
+    p, c2 = Q.pulls(ev, r.tracks, r.hits)
+    assert len(p) > 5000
+    lo, hi = np.percentile(p, [1, 99], axis=0)
+    assert np.all(lo > -4) and np.all(hi < 4), (lo, hi)
+    core = np.abs(p) < 5
+    rms = np.sqrt([(p[core[:, i], i] ** 2).mean() for i in range(5)])
+    assert np.all((rms > 0.85) & (rms < 1.2)), rms
+    assert 0.85 < np.median(c2) < 1.15
+
+
 @pytest.mark.parametrize("make", [tpcgen.one_sector_event, tpcgen.pp_event])
 def test_float_run_matches_double_replay(oracle_lib, make):
     """The float run's track parameters and covariances equal the double

@@ -10,7 +10,7 @@ cluster list is shuffled, so the cluster ID (input index) carries no order.
 Per cluster the generator also records the truth: particle index (-1 for
 noise), the (sector, leg) it belongs to and the exact local track state at the
 crossing, written as the tracker sees the leg when it follows it towards
-larger x (a returning looper leg shows up with T and Q negated).
+larger x (a returning looper leg shows up with sin phi, T and Q negated).
 
 Nothing here is tracker arithmetic: the generator uses trigonometry on the
 global helix, while the tracker propagates a local state row by row.
@@ -208,7 +208,8 @@ def _crossings(p, sectors_allowed, x_rows):
             out["row"].append(rows[sel])
             out["y"].append(yloc[sel])
             out["z"].append(zz[sel])
-            out["s"].append(v[sel])
+            # a returning leg followed towards larger x has direction phi + pi
+            out["s"].append(v[sel] * sgn)
             out["T"].append(T[pi] * sgn)
             out["Q"].append(Q[pi] * sgn)
             out["leg"].append(2 * turn + np.where(outward, 0, 1))
