@@ -36,12 +36,153 @@ def tracklet_bytes(cnt: dict) -> int:
             + BYTES_PER_WINDOW_HIT * cnt["window_hits"])
 
 
+class Ev:
+    """Cluster arrays of a generated event (from tpcgen.parallel)."""
+
+    def __init__(self, d):
+        self.sector, self.row, self.y, self.z = d["sector"], d["row"], d["y"], d["z"]
+        self.sigma = d["sigma"]
+        self.name = d["name"]
+        self.n = int(len(self.y))
+        self.seed = None
+
+    def geometry(self):
+        from tpcgen import geometry as G
+        return G.geometry_dict(self.sigma)
+
+
+def serve_pool_specs():
+    """Distinct events the serving stream draws from: pp-like, peripheral
+    (2000 primaries, Pb-Pb shape) and central."""
+    import tpcgen
+    specs = [("pp", (tpcgen.seed_for(4, e),)) for e in range(24)]
+    specs += [("pbpb", (tpcgen.seed_for(4, 100 + e), 2000)) for e in range(8)]
+    specs += [("pbpb", (tpcgen.seed_for(4, 200 + e), 15000)) for e in range(2)]
+    return specs
+
+
+def bench_batch(evs, geo, dev, steps: int) -> dict:
+    """64 events of uneven size (Pb-Pb shape, multiplicity log-uniform
+    50-15000): tracked together in one slot (one launch per step over all
+    2304 sectors), replayed from a HIP graph; compared with the same slot
+    without the graph, with one event at a time (fused launches) and with
+    the plain per-sector launch sequence."""
+    import numpy as np
+    import torch
+    from paper_1712_09416_amd import Tracker
+    evs = [Ev(d) for d in evs]
+    offs = np.concatenate([[0], np.cumsum([e.n for e in evs])]).astype(np.int64)
+    total = int(offs[-1])
+    cat = [torch.from_numpy(np.concatenate([getattr(e, k) for e in evs])).to(dev)
+           for k in ("sector", "row", "y", "z")]
+    trk = Tracker(geo, max_events=len(evs), max_clusters=total)
+    st = trk.stream
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    trk.load_batch(0, offs, *cat)
+    trk.track_event(0)
+    ntracks = sum(len(trk.get_tracks(0, e)[0]) for e in range(len(evs)))
+    trk.load_batch(0, offs, *cat)
+    trk.capture(0)
+    trk.launch(0)
+    ms_graph = timed(lambda: trk.launch(0), steps)
+
+    def eager():
+        trk.load_batch(0, offs, *cat)
+        trk.track_event(0)
+    eager()
+    ms_eager = timed(eager, steps)
+    slices = [[c[offs[e]:offs[e + 1]] for c in cat] for e in range(len(evs))]
+
+    def per_event():
+        for sl in slices:
+            trk.load(0, *sl)
+            trk.track_event(0)
+    per_event()
+    ms_events = timed(per_event, 1)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for sl in slices:
+        trk.load(0, *sl)
+        for s in range(36):
+            trk.track_sector(0, s)
+        trk.device_results(0)
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - p0) * 1e3
+    trk.close()
+    rate = lambda ms: total / (ms * 1e-3)  # noqa: E731
+    return {"events": len(evs), "clusters": total, "sectors": 36 * len(evs), "tracks": ntracks,
+            "graph_ms": ms_graph, "graph_clusters_per_s": rate(ms_graph),
+            "one_launch_per_step_ms": ms_eager, "one_launch_per_step_clusters_per_s": rate(ms_eager),
+            "per_event_ms": ms_events, "per_event_clusters_per_s": rate(ms_events),
+            "plain_ms": ms_plain, "plain_clusters_per_s": rate(ms_plain)}
+
+
+def bench_serve(pool, geo, n_req: int) -> dict:
+    """Poisson stream of events (70% pp, 25% peripheral, 5% central, drawn
+    from a pool of distinct events), served with continuous batching over 4
+    streams vs the plain one-event-at-a-time path.  Rates: 0.7 x the plain
+    capacity (both modes), and 0.7 x the continuous-batching capacity."""
+    import numpy as np
+    from paper_1712_09416_amd.serve import Server, Request, poisson_arrivals
+    evs = [Ev(d) for d in pool]
+    kinds = {"pp": [e for e in evs if e.name.startswith("pp")],
+             "peripheral": [e for e in evs if e.name == "pbpb_2000"],
+             "central": [e for e in evs if e.name == "pbpb_15000"]}
+    rng = np.random.default_rng(1712094164)
+    warm = 30
+    u = rng.uniform(size=n_req + warm)
+    kind = np.where(u < 0.70, "pp", np.where(u < 0.95, "peripheral", "central"))
+    picks = []
+    counters = {k: 0 for k in kinds}
+    for k in kind:
+        picks.append(kinds[k][counters[k] % len(kinds[k])])
+        counters[k] += 1
+    cap = max(e.n for e in evs) + 1024
+
+    def requests(times):
+        return [Request(float(t), e.sector, e.row, e.y, e.z, tag=e.name) for t, e in zip(times, picks)]
+
+    def capacity(plain):
+        srv = Server(geo, n_streams=4, max_events=8, cap_clusters=cap, plain=plain)
+        srv.run(requests(np.zeros(len(picks[:40])))[:40])          # warm-up
+        st = srv.run(requests(np.zeros(len(picks))))
+        srv.close()
+        return st.n_requests / st.wall_s
+
+    def serve(plain, rate):
+        srv = Server(geo, n_streams=4, max_events=8, cap_clusters=cap, plain=plain)
+        srv.run(requests(np.zeros(40))[:40])
+        st = srv.run(requests(poisson_arrivals(len(picks), rate, seed=7)), warmup=warm)
+        srv.close()
+        return st.summary()
+
+    c_plain = capacity(True)
+    c_cb = capacity(False)
+    r1 = 0.7 * c_plain
+    return {"mix": "70% pp / 25% peripheral (2000 primaries) / 5% central, pool of 34 distinct events",
+            "capacity_events_per_s": {"plain": c_plain, "continuous_batching": c_cb},
+            "at_0.7_plain_capacity": {"rate_events_per_s": r1, "plain": serve(True, r1),
+                                      "continuous_batching": serve(False, r1)},
+            "at_0.7_cb_capacity": {"rate_events_per_s": 0.7 * c_cb,
+                                   "continuous_batching": serve(False, 0.7 * c_cb)}}
+
+
 def cpu_baseline(ev, threads: int) -> dict:
     """The oracle (float decisions, double refit) on the same event."""
     from oracle import oracle
     oracle.build(force=False)
     t = time.perf_counter()
-    r = oracle.run_event(ev, precision=32, nthreads=threads)
+    r = oracle.run(ev.sector, ev.row, ev.y, ev.z, ev.geometry(), precision=32, nthreads=threads)
     dt = time.perf_counter() - t
     return {"value": ev.n / dt, "unit": "clusters/s", "cores": threads, "kind": "oracle",
             "sample": f"whole central event ({ev.n} clusters, 36 sectors, one sector per "
@@ -58,6 +199,11 @@ def main() -> int:
                     help="steps of the per-sector (plain) launch sequence, for comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
+    ap.add_argument("--batch-events", type=int, default=64,
+                    help="events of the batched workload (0: skip it)")
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests of the serving workload (0: skip it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the tracker "
@@ -65,8 +211,20 @@ def main() -> int:
         return 2
 
     import numpy as np
-    import torch
     import tpcgen
+    from tpcgen import parallel
+
+    # every synthetic event is generated before the GPU is touched
+    mult = tpcgen.batch_multiplicities(64)[: args.batch_events]
+    specs = [("central", ())]
+    specs += [("batch", (e, int(m))) for e, m in enumerate(mult)]
+    serve_specs = serve_pool_specs() if args.serve_requests > 0 else []
+    gen = parallel.generate(specs + serve_specs)
+    central = gen[0]
+    batch_evs = gen[1:1 + len(mult)]
+    serve_pool = gen[1 + len(mult):]
+
+    import torch
     from paper_1712_09416_amd import Tracker
 
     dev = torch.device("cuda:0")
@@ -77,7 +235,7 @@ def main() -> int:
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    ev = tpcgen.central_event()
+    ev = Ev(central)
     print(f"bench: central event {ev.n} clusters", file=sys.stderr, flush=True)
     ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.sector, ev.row, ev.y, ev.z)]
     trk = Tracker(ev.geometry(), max_clusters=ev.n)
@@ -91,31 +249,37 @@ def main() -> int:
         step()
     torch.cuda.synchronize()
 
+    # timed region: K steps back to back on the tracker's stream
+    st = trk.stream                   # every kernel of the tracker runs there
+    ev_steps = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for e0, e1 in ev_steps:
+        e0.record(st)
+        step()
+        e1.record(st)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - w0) * 1e3
+    lat = [e0.elapsed_time(e1) for e0, e1 in ev_steps]
+    total_ms = ev_steps[0][0].elapsed_time(ev_steps[-1][1])
+
+    # per-stage times and work counters: separate profiled steps
     trk.set_profiling(True)
     stage_ms = None
     counters = None
-    lat = []
-    t_all0 = torch.cuda.Event(enable_timing=True)
-    t_all1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_all0.record()
-    for _ in range(args.steps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
+    n_prof = max(3, min(args.steps, 10))
+    for _ in range(n_prof):
         step()
-        e1.record()
         ms, cnt = trk.profile()       # waits for the step
-        lat.append(e0.elapsed_time(e1))
         stage_ms = {k: (stage_ms or {}).get(k, 0.0) + v for k, v in ms.items()}
         counters = cnt
-    t_all1.record()
-    torch.cuda.synchronize()
-    total_ms = t_all0.elapsed_time(t_all1)
     trk.set_profiling(False)
-    stage_ms = {k: v / args.steps for k, v in stage_ms.items()}
+    stage_ms = {k: v / n_prof for k, v in stage_ms.items()}
     tracks, hits = trk.get_tracks(0)
-    ms_per_step = total_ms / args.steps
+    # whole-job rate from the host clock around the synchronised region (the
+    # GPU-event span is reported beside it)
+    ms_per_step = wall_ms / args.steps
     value = ev.n / (ms_per_step * 1e-3)
 
     # plain: the same event with the per-sector launch sequence
@@ -145,6 +309,7 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "gpu_ms_per_step": total_ms / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -152,7 +317,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"central Pb-Pb-shaped event, 36 sectors x 159 rows, {ev.n} clusters",
                    "mode": "fused (one launch per step over all sectors)",
-                   "refit": "f64", "seed": ev.seed},
+                   "refit": "f64", "seed": tpcgen.seed_for(2)},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "stage_ms": stage_ms,
@@ -162,10 +327,16 @@ def main() -> int:
         "plain": plain,
         "roofline": roof,
     }
+    trk.close()
+    if len(batch_evs):
+        out["batch"] = bench_batch(batch_evs, ev.geometry(), dev, args.batch_steps)
+        print(f"bench: batch {out['batch']}", file=sys.stderr, flush=True)
+    if args.serve_requests > 0:
+        out["serve"] = bench_serve(serve_pool, ev.geometry(), args.serve_requests)
+        print(f"bench: serve {out['serve']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(ev, threads)
-    trk.close()
     print(json.dumps(out), flush=True)
     return 0
 

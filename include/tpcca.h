@@ -193,6 +193,26 @@ int tpc_get_links(tpc_ctx* ctx, int slot, int event, int32_t* up, int32_t* dn, i
 int tpc_kf_step_f32(tpc_ctx* ctx, float* state, const float* dx, const float* meas,
                     float* result, int64_t n);
 
+/* Record into a HIP graph, without running it, the whole sequence
+ * tpc_track_event would enqueue for the slot as currently staged (grid,
+ * finding, fitting, ordering; kernels only, no memset or copy nodes).  The
+ * graph is kept by the context, one per slot, and bakes in the slot's
+ * staged shape: input pointers, cluster count and event offsets.
+ * Requires a non-default stream.  Errors: TPC_EINVAL, TPC_ESTATE (slot not
+ * staged), TPC_EDEVICE (capture failed). */
+int tpc_graph_capture(tpc_ctx* ctx, int slot);
+
+/* Launch the slot's graph on the context stream (asynchronous); the slot is
+ * then tracked as after tpc_track_event.  The slot must be staged with the
+ * same shape as at capture (e.g. TPC_HOST copies of new clusters into the
+ * slot's own buffers, or the same device arrays refilled in place).
+ * Errors: TPC_EINVAL, TPC_ESTATE (no graph, or the staged shape changed). */
+int tpc_graph_launch(tpc_ctx* ctx, int slot);
+
+/* TPC_OK if all work enqueued so far for the slot (staging, tracking) has
+ * finished, TPC_EBUSY if not; never waits.  Errors: TPC_EINVAL. */
+int tpc_poll(tpc_ctx* ctx, int slot);
+
 /* Stage timing.  With profiling on, tpc_track_event records HIP events on
  * the context stream around its steps; tpc_get_profile waits for the stream
  * and returns, for the last tracked slot, the milliseconds of each step

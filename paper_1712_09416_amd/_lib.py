@@ -17,8 +17,9 @@ ERROR_NAMES = {0: "TPC_OK", -1: "TPC_EINVAL", -2: "TPC_ENOMEM", -3: "TPC_EOVERFL
 
 EXPORTS = ("tpc_params_default", "tpc_workspace_bytes", "tpc_init_geometry", "tpc_load_clusters",
            "tpc_load_batch", "tpc_track_sector", "tpc_track_event", "tpc_get_tracks",
-           "tpc_device_results", "tpc_get_links", "tpc_kf_step_f32", "tpc_set_profiling",
-           "tpc_get_profile", "tpc_last_error", "tpc_destroy")
+           "tpc_device_results", "tpc_get_links", "tpc_kf_step_f32", "tpc_graph_capture",
+           "tpc_graph_launch", "tpc_poll", "tpc_set_profiling", "tpc_get_profile",
+           "tpc_last_error", "tpc_destroy")
 STAGES = ("grid", "neighbours", "clean_starts", "tracklets", "weights_select", "refit", "output")
 
 
@@ -79,6 +80,9 @@ def load() -> ctypes.CDLL:
     L.tpc_device_results.argtypes = [P, I, P, P, P, P, P]
     L.tpc_get_links.argtypes = [P, I, I, P, P, P, P]
     L.tpc_kf_step_f32.argtypes = [P, P, P, P, P, I64]
+    L.tpc_graph_capture.argtypes = [P, I]
+    L.tpc_graph_launch.argtypes = [P, I]
+    L.tpc_poll.argtypes = [P, I]
     L.tpc_set_profiling.argtypes = [P, I]
     L.tpc_get_profile.argtypes = [P, P, P]
     L.tpc_last_error.restype = ctypes.c_char_p

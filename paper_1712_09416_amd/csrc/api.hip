@@ -14,6 +14,7 @@ using namespace tpc;
 namespace {
 
 constexpr int kScanTile = 1024;
+constexpr int64_t kCountChunkHost = 16384;   // clusters per block of k_count
 
 struct SlotHost {
   Slot d{};
@@ -21,6 +22,10 @@ struct SlotHost {
   int64_t n = 0;
   int n_events = 0;
   std::vector<int64_t> ev_off;
+  hipEvent_t done = nullptr;          // recorded after the slot's last enqueued work
+  hipGraphExec_t graph = nullptr;     // captured tracking sequence
+  std::vector<int64_t> graph_ev_off;  // staged shape the graph was captured with
+  const void* graph_in[4] = {};
   uint8_t* own_sector = nullptr;
   uint8_t* own_row = nullptr;
   float* own_y = nullptr;
@@ -117,6 +122,7 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   s.row_cnt = c.take<uint32_t>(SR);
   s.row_off = c.take<uint32_t>(SR + 1);
   s.bins = c.take<RowBins>(SR);
+  s.row_bin = c.take<uint32_t>(SR + 1);
   s.bin_off = c.take<uint32_t>(N + SR + 1);
   s.rank = c.take<uint32_t>(N);
   s.ty = c.take<float>(N);
@@ -130,6 +136,7 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   s.tk_base = c.take<uint32_t>(S + 1);
   s.row_nstart = c.take<uint32_t>(SR + 1);
   s.range_cnt = c.take<uint32_t>(4);
+  s.big_rows = c.take<uint32_t>(N / 1024 + 1);
   s.start_hit = c.take<int32_t>(cap_tl);
   s.start_sr = c.take<int32_t>(cap_tl);
   s.tl_hits = c.take<int32_t>(cap_tl * kRows);
@@ -192,6 +199,7 @@ struct tpc_ctx {
   std::string err;
   bool prof = false;
   bool prof_valid = false;
+  bool capturing = false;
   int prof_slot = -1;
   hipEvent_t ev[TPC_N_STAGES + 1] = {};
   int fail(int code, const std::string& m) {
@@ -217,28 +225,18 @@ struct tpc_ctx {
 namespace {
 
 void mark(tpc_ctx* ctx, int i) {
-  if (ctx->prof) (void)hipEventRecord(ctx->ev[i], ctx->stream);
+  if (ctx->prof && !ctx->capturing) (void)hipEventRecord(ctx->ev[i], ctx->stream);
+}
+
+int record_done(tpc_ctx* ctx, SlotHost& h) {
+  if (!h.done) TPC_HIP(hipEventCreateWithFlags(&h.done, hipEventDisableTiming));
+  TPC_HIP(hipEventRecord(h.done, ctx->stream));
+  return TPC_OK;
 }
 
 int grid_stride_blocks(int64_t n, int threads, int cap = 4096) {
   const int64_t b = (n + threads - 1) / threads;
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
-}
-
-int build_grid(tpc_ctx* ctx, SlotHost& h) {
-  Slot& s = h.d;
-  hipStream_t st = ctx->stream;
-  const int64_t SR = (int64_t)s.n_sectors * kRows;
-  k_zero_u32<<<grid_stride_blocks(SR, 256), 256, 0, st>>>(s.row_cnt, SR);
-  k_zero_u32<<<1, 64, 0, st>>>(s.err, 4);
-  k_zero_u32<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t*>(s.stats), 16);
-  k_count<<<grid_stride_blocks(h.n, 256), 256, 0, st>>>(s);
-  k_scan_rows<<<1, 1024, 0, st>>>(s, ctx->k);
-  k_scatter<<<grid_stride_blocks(h.n, 256), 256, 0, st>>>(s);
-  k_row_sort<<<(unsigned)SR, 256, 0, st>>>(s);
-  TPC_LAUNCHED();
-  h.state = 2;
-  return TPC_OK;
 }
 
 // Exclusive scan in place of data[0, n) (n = *n_dev if given, else n_bound,
@@ -255,12 +253,37 @@ void scan_u32(hipStream_t st, uint32_t* data, const uint32_t* n_dev, int64_t n_b
 
 
 
+int build_grid(tpc_ctx* ctx, SlotHost& h) {
+  Slot& s = h.d;
+  hipStream_t st = ctx->stream;
+  const int64_t SR = (int64_t)s.n_sectors * kRows;
+  k_zero_u32<<<grid_stride_blocks(SR, 256), 256, 0, st>>>(s.row_cnt, SR);
+  k_zero_u32<<<1, 64, 0, st>>>(s.err, 4);
+  k_zero_u32<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t*>(s.stats), 16);
+  int64_t max_ev = 1;
+  for (int e = 0; e < h.n_events; ++e) max_ev = std::max<int64_t>(max_ev, h.ev_off[e + 1] - h.ev_off[e]);
+  const unsigned chunks = (unsigned)((max_ev + kCountChunkHost - 1) / kCountChunkHost);
+  k_count<<<dim3(chunks, h.n_events), 256, 0, st>>>(s);
+  k_row_layout<<<grid_stride_blocks(SR, 256), 256, 0, st>>>(s, ctx->k);
+  scan_u32(st, s.row_off, nullptr, SR, s.scan_b, nullptr);
+  scan_u32(st, s.row_bin, nullptr, SR, s.scan_b, nullptr);
+  k_row_finish<<<grid_stride_blocks(SR, 256), 256, 0, st>>>(s);
+  scan_u32(st, s.tl_base, nullptr, s.n_sectors, s.scan_b, nullptr);
+  scan_u32(st, s.tk_base, nullptr, s.n_sectors, s.scan_b, nullptr);
+  k_scatter<<<grid_stride_blocks(h.n, 256), 256, 0, st>>>(s);
+  k_row_sort_small<<<(unsigned)SR, 256, 0, st>>>(s);
+  k_row_sort_large<<<64, 256, 0, st>>>(s);
+  TPC_LAUNCHED();
+  h.state = 2;
+  return TPC_OK;
+}
+
 int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns) {
   Slot& s = h.d;
   hipStream_t st = ctx->stream;
   // host bounds for the persistent grids (exact counts live on the device)
   const int64_t tl_bound = std::min<int64_t>(s.cap_tl, h.n / 3 + ns);
-  const int nb_lane = std::max(8, grid_stride_blocks(tl_bound, 64, 4096) / 8 * 8);
+  const int nb_lane = std::max(8, grid_stride_blocks(tl_bound, 64, 16384) / 8 * 8);
   const int nb_wave = grid_stride_blocks(tl_bound * 64, 256, 8192);
   k_neighbours<<<dim3(kRows, ns), 256, 0, st>>>(s, ctx->k, g0);
   mark(ctx, 2);
@@ -271,7 +294,6 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns) {
   mark(ctx, 3);
   k_tracklets<<<nb_lane, 64, 0, st>>>(s, ctx->k, g0);
   mark(ctx, 4);
-  k_weights<<<nb_wave, 256, 0, st>>>(s, g0);
   k_select<<<nb_wave, 256, 0, st>>>(s, ctx->k, g0);
   scan_u32(st, s.tl_sel, s.range_cnt + 0, tl_bound, s.scan_b, s.range_cnt + 1, false);
   k_track_write<<<nb_wave, 256, 0, st>>>(s, g0);
@@ -341,7 +363,7 @@ int stage(tpc_ctx* ctx, int slot, int n_events, const int64_t* offs, const uint8
   TPC_HIP(hipMemcpyAsync(s.ev_off, h.ev_off.data(), (n_events + 1) * sizeof(int64_t),
                          hipMemcpyHostToDevice, st));
   h.state = 1;
-  return TPC_OK;
+  return record_done(ctx, h);
 }
 
 }  // namespace
@@ -486,7 +508,7 @@ int tpc_track_sector(tpc_ctx* ctx, int slot, int sector) {
   const int rc = track_range(ctx, h, sector, 1);
   if (rc) return rc;
   h.state = 3;
-  return TPC_OK;
+  return record_done(ctx, h);
 }
 
 int tpc_track_event(tpc_ctx* ctx, int slot) {
@@ -506,7 +528,72 @@ int tpc_track_event(tpc_ctx* ctx, int slot) {
   if (rc) return rc;
   ctx->prof_valid = ctx->prof;
   ctx->prof_slot = slot;
+  return record_done(ctx, h);
+}
+
+int tpc_graph_capture(tpc_ctx* ctx, int slot) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  SlotHost& h = ctx->slots[slot];
+  if (h.state < 1) return ctx->fail(TPC_ESTATE, "slot not staged");
+  if (!ctx->stream) return ctx->fail(TPC_EINVAL, "graph capture needs a non-default stream");
+  if (h.graph) {
+    TPC_HIP(hipGraphExecDestroy(h.graph));
+    h.graph = nullptr;
+  }
+  const int state0 = h.state;
+  h.state = 1;                       // capture the grid build too
+  ctx->capturing = true;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+  int rc = TPC_OK;
+  if (e == hipSuccess) {
+    rc = build_grid(ctx, h);
+    if (!rc) rc = track_range(ctx, h, 0, h.d.n_sectors);
+    if (!rc) rc = finalize(ctx, h);
+    e = hipStreamEndCapture(ctx->stream, &g);
+  }
+  ctx->capturing = false;
+  h.state = state0;
+  if (rc) return rc;
+  if (e != hipSuccess) return ctx->fail(TPC_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&h.graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h.graph = nullptr;
+    return ctx->fail(TPC_EDEVICE, std::string("instantiate: ") + hipGetErrorString(e));
+  }
+  h.graph_ev_off = h.ev_off;
+  h.graph_in[0] = h.d.sector;
+  h.graph_in[1] = h.d.row;
+  h.graph_in[2] = h.d.y;
+  h.graph_in[3] = h.d.z;
   return TPC_OK;
+}
+
+int tpc_graph_launch(tpc_ctx* ctx, int slot) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  SlotHost& h = ctx->slots[slot];
+  if (!h.graph) return ctx->fail(TPC_ESTATE, "no graph captured for the slot");
+  if (h.state < 1) return ctx->fail(TPC_ESTATE, "slot not staged");
+  if (h.ev_off != h.graph_ev_off || h.graph_in[0] != h.d.sector || h.graph_in[1] != h.d.row ||
+      h.graph_in[2] != h.d.y || h.graph_in[3] != h.d.z)
+    return ctx->fail(TPC_ESTATE, "slot staged with another shape than at capture");
+  TPC_HIP(hipGraphLaunch(h.graph, ctx->stream));
+  h.state = 4;
+  return record_done(ctx, h);
+}
+
+int tpc_poll(tpc_ctx* ctx, int slot) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  SlotHost& h = ctx->slots[slot];
+  if (!h.done) return TPC_OK;
+  const hipError_t e = hipEventQuery(h.done);
+  if (e == hipSuccess) return TPC_OK;
+  if (e == hipErrorNotReady) return TPC_EBUSY;
+  return ctx->fail(TPC_EDEVICE, std::string("poll: ") + hipGetErrorString(e));
 }
 
 int tpc_set_profiling(tpc_ctx* ctx, int enable) {
@@ -637,6 +724,10 @@ int tpc_destroy(tpc_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (int i = 0; i <= TPC_N_STAGES; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  for (SlotHost& h : ctx->slots) {
+    if (h.graph) (void)hipGraphExecDestroy(h.graph);
+    if (h.done) (void)hipEventDestroy(h.done);
+  }
   delete ctx;
   return TPC_OK;
 }

@@ -6,8 +6,6 @@
 
 namespace tpc {
 
-constexpr int kNfRowCap = 1024;   // hits of a neighbour row staged in LDS
-constexpr int kNfCand = 16;       // up-row candidates kept per hit
 constexpr int kNfThreads = 256;
 
 // Visit the hits of one row that can lie inside [yc - wy, yc + wy] x
@@ -29,94 +27,85 @@ __device__ __forceinline__ void for_window(const RowBins& b, BinPtr bins, float 
   }
 }
 
-// Best (down, up) pair of one hit.  hd/bd (hu/bu): hits and bin offsets of
-// row r-1 (r+1) in a common numbering; add_d/add_u turn that numbering into
-// sorted-hit indices.
-template <class HitPtr, class BinPtr>
-__device__ __forceinline__ void best_pair(const DevConst& K, const Hit hh, int row,
-                                          const RowBins& Bd, HitPtr hd, BinPtr bd, uint32_t add_d,
-                                          const RowBins& Bu, HitPtr hu, BinPtr bu, uint32_t add_u,
-                                          uint32_t* cand, int32_t& out_up, int32_t& out_dn) {
-  // cand[k * kNfThreads]: this thread's k-th candidate (thread-minor layout,
-  // so a wave's accesses fall in distinct LDS banks)
+// A neighbour row seen through global memory (Hit records, absolute bin
+// offsets); `add` turns the numbering into sorted-hit indices.
+struct RowGlobal {
+  const Hit* hit;
+  const uint32_t* bins;
+  uint32_t add;
+  __device__ float2 yz(uint32_t p) const {
+    const Hit x = hit[p];
+    return make_float2(x.y, x.z);
+  }
+  __device__ uint32_t id(uint32_t p) const { return hit[p].id; }
+};
+__device__ __forceinline__ float nf_metric(float yd, float zd, float yu, float zu, float yh, float zh,
+                                           float f, float wy, float wz) {
+  const float dy = yd + (yu - yd) * f - yh;
+  const float dz = zd + (zu - zd) * f - zh;
+  return dy * dy * wy + dz * dz * wz;
+}
+
+// Best (down, up) pair of one hit by a nested scan of the two windows.
+template <class RD, class RU>
+__device__ void nested_pair(const DevConst& K, float yh, float zh, int row, const RowBins& Bd,
+                            const RD& rd, const RowBins& Bu, const RU& ru, int32_t& out_up,
+                            int32_t& out_dn) {
   const float xr = K.row_x[row];
   const float rho_d = K.row_x[row - 1] / xr;
   const float rho_u = K.row_x[row + 1] / xr;
   const float f = (xr - K.row_x[row - 1]) / (K.row_x[row + 1] - K.row_x[row - 1]);
   const float W = K.nf_w;
-  const float yh = hh.y, zh = hh.z;
   const float ypd = yh * rho_d, zpd = zh * rho_d;
   const float ypu = yh * rho_u, zpu = zh * rho_u;
   const float sy = sigma_y(K, zh), sz = sigma_z(K, zh);
   const float wy = 1.0f / (1.5f * (sy * sy));
   const float wz = 1.0f / (1.5f * (sz * sz));
-  // up-row candidates inside the exact window
-  int nu = 0;
-  bool overflow = false;
-  for_window(Bu, bu, ypu, zpu, W, W, [&](uint32_t u) {
-    const Hit x = hu[u];
-    if (!(fabsf(x.y - ypu) <= W && fabsf(x.z - zpu) <= W)) return;
-    if (nu < kNfCand) cand[nu * kNfThreads] = u;
-    else overflow = true;
-    ++nu;
-  });
-  out_up = -1;
-  out_dn = -1;
-  if (nu == 0) return;
   bool have = false;
   float best = 0.0f;
   uint32_t bid_d = 0, bid_u = 0;
   int32_t bd_i = -1, bu_i = -1;
-  auto pair = [&](uint32_t d, const Hit& xd, uint32_t u, const Hit& xu) {
-    const float dy = xd.y + (xu.y - xd.y) * f - yh;
-    const float dz = xd.z + (xu.z - xd.z) * f - zh;
-    const float m = dy * dy * wy + dz * dz * wz;
-    const bool better =
-        !have || m < best || (m == best && (xd.id < bid_d || (xd.id == bid_d && xu.id < bid_u)));
-    if (better) {
-      have = true;
-      best = m;
-      bid_d = xd.id;
-      bid_u = xu.id;
-      bd_i = (int32_t)(d + add_d);
-      bu_i = (int32_t)(u + add_u);
-    }
-  };
-  for_window(Bd, bd, ypd, zpd, W, W, [&](uint32_t d) {
-    const Hit xd = hd[d];
-    if (!(fabsf(xd.y - ypd) <= W && fabsf(xd.z - zpd) <= W)) return;
-    if (!overflow) {
-      for (int k = 0; k < nu; ++k) {
-        const uint32_t u = cand[k * kNfThreads];
-        pair(d, xd, u, hu[u]);
+  for_window(Bd, rd.bins, ypd, zpd, W, W, [&](uint32_t d) {
+    const float2 a = rd.yz(d);
+    if (!(fabsf(a.x - ypd) <= W && fabsf(a.y - zpd) <= W)) return;
+    const uint32_t idd = rd.id(d);
+    for_window(Bu, ru.bins, ypu, zpu, W, W, [&](uint32_t u) {
+      const float2 b = ru.yz(u);
+      if (!(fabsf(b.x - ypu) <= W && fabsf(b.y - zpu) <= W)) return;
+      const uint32_t idu = ru.id(u);
+      const float m = nf_metric(a.x, a.y, b.x, b.y, yh, zh, f, wy, wz);
+      const bool better =
+          !have || m < best || (m == best && (idd < bid_d || (idd == bid_d && idu < bid_u)));
+      if (better) {
+        have = true;
+        best = m;
+        bid_d = idd;
+        bid_u = idu;
+        bd_i = (int32_t)(d + rd.add);
+        bu_i = (int32_t)(u + ru.add);
       }
-    } else {
-      for_window(Bu, bu, ypu, zpu, W, W, [&](uint32_t u) {
-        const Hit xu = hu[u];
-        if (!(fabsf(xu.y - ypu) <= W && fabsf(xu.z - zpu) <= W)) return;
-        pair(d, xd, u, xu);
-      });
-    }
+    });
   });
-  if (have && best <= K.nf_mmax) {
-    out_up = bu_i;
-    out_dn = bd_i;
-  }
+  const bool ok = have && best <= K.nf_mmax;
+  out_up = ok ? bu_i : -1;
+  out_dn = ok ? bd_i : -1;
 }
+
+constexpr int kNfCand = 32;      // up-row candidates kept per hit before a nested scan
 
 // a3: one block per (sector, row).  For each hit h of row r (1..157), the
 // pair (d in row r-1, u in row r+1) inside the origin-pointing windows
 // |y - y_h x_r'/x_r| <= W, |z - z_h x_r'/x_r| <= W whose straight line passes
 // closest to h, measured by m = dy^2 / (1.5 sy^2) + dz^2 / (1.5 sz^2);
 // ties go to the smaller (id_d, id_u); the pair is kept if m <= m_max.
-// Rows r-1 and r+1 (hits and bin offsets) are staged in LDS when they hold
-// at most kNfRowCap hits; otherwise read from global memory.  Rows 0 and 158
-// get no links.
+// Rows 0 and 158 get no links.
+// One lane per hit; the up-row candidates are listed once (LDS,
+// thread-minor so a wave's accesses fall in distinct banks) and paired with
+// every down-row candidate; a hit with more than kNfCand up candidates takes
+// a nested scan.  The neighbour rows are read through the caches rather than
+// staged: the small LDS footprint keeps enough waves resident to hide the
+// load latency (measured faster than staging both rows in LDS).
 __global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, int g0) {
-  __shared__ Hit sh_d[kNfRowCap];
-  __shared__ Hit sh_u[kNfRowCap];
-  __shared__ uint32_t sb_d[kNfRowCap + 1];
-  __shared__ uint32_t sb_u[kNfRowCap + 1];
   __shared__ uint32_t cand[kNfCand * kNfThreads];
   const int row = blockIdx.x;
   const int g = g0 + blockIdx.y;
@@ -129,33 +118,62 @@ __global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, i
     }
     return;
   }
-  if (h0 == h1) return;
-  const uint32_t od = S.row_off[sr - 1], nd = h0 - od;
-  const uint32_t ou = h1, nu = S.row_off[sr + 2] - h1;
   const RowBins Bd = S.bins[sr - 1], Bu = S.bins[sr + 1];
-  const int nbd = Bd.ny * Bd.nz, nbu = Bu.ny * Bu.nz;
+  const RowGlobal rd{S.hit, S.bin_off + Bd.base, 0u}, ru{S.hit, S.bin_off + Bu.base, 0u};
+  const float xr = K.row_x[row];
+  const float rho_d = K.row_x[row - 1] / xr;
+  const float rho_u = K.row_x[row + 1] / xr;
+  const float f = (xr - K.row_x[row - 1]) / (K.row_x[row + 1] - K.row_x[row - 1]);
+  const float W = K.nf_w;
   uint32_t* my = cand + threadIdx.x;
-  if (nd <= (uint32_t)kNfRowCap && nu <= (uint32_t)kNfRowCap) {
-    for (uint32_t j = threadIdx.x; j < nd; j += blockDim.x) sh_d[j] = S.hit[od + j];
-    for (uint32_t j = threadIdx.x; j < nu; j += blockDim.x) sh_u[j] = S.hit[ou + j];
-    for (int j = threadIdx.x; j <= nbd; j += blockDim.x) sb_d[j] = S.bin_off[Bd.base + j] - od;
-    for (int j = threadIdx.x; j <= nbu; j += blockDim.x) sb_u[j] = S.bin_off[Bu.base + j] - ou;
-    __syncthreads();
-    for (uint32_t h = h0 + threadIdx.x; h < h1; h += blockDim.x) {
-      int32_t up, dn;
-      best_pair(K, S.hit[h], row, Bd, (const Hit*)sh_d, (const uint32_t*)sb_d, od, Bu,
-                (const Hit*)sh_u, (const uint32_t*)sb_u, ou, my, up, dn);
-      S.up[h] = up;
-      S.dn[h] = dn;
+  for (uint32_t h = h0 + threadIdx.x; h < h1; h += blockDim.x) {
+    const Hit x = S.hit[h];
+    const float yh = x.y, zh = x.z;
+    const float ypu = yh * rho_u, zpu = zh * rho_u;
+    int nu = 0;
+    for_window(Bu, ru.bins, ypu, zpu, W, W, [&](uint32_t u) {
+      const float2 c = ru.yz(u);
+      if (!(fabsf(c.x - ypu) <= W && fabsf(c.y - zpu) <= W)) return;
+      if (nu < kNfCand) my[nu * kNfThreads] = u;
+      ++nu;
+    });
+    int32_t up = -1, dn = -1;
+    if (nu > kNfCand) {
+      nested_pair(K, yh, zh, row, Bd, rd, Bu, ru, up, dn);
+    } else if (nu > 0) {
+      const float ypd = yh * rho_d, zpd = zh * rho_d;
+      const float sy = sigma_y(K, zh), sz = sigma_z(K, zh);
+      const float wy = 1.0f / (1.5f * (sy * sy));
+      const float wz = 1.0f / (1.5f * (sz * sz));
+      bool have = false;
+      float best = 0.0f;
+      uint32_t bid_d = 0, bid_u = 0;
+      for_window(Bd, rd.bins, ypd, zpd, W, W, [&](uint32_t d) {
+        const Hit xd = S.hit[d];
+        if (!(fabsf(xd.y - ypd) <= W && fabsf(xd.z - zpd) <= W)) return;
+        for (int k = 0; k < nu; ++k) {
+          const uint32_t u = my[k * kNfThreads];
+          const Hit xu = S.hit[u];
+          const float m = nf_metric(xd.y, xd.z, xu.y, xu.z, yh, zh, f, wy, wz);
+          const bool better =
+              !have || m < best || (m == best && (xd.id < bid_d || (xd.id == bid_d && xu.id < bid_u)));
+          if (better) {
+            have = true;
+            best = m;
+            bid_d = xd.id;
+            bid_u = xu.id;
+            dn = (int32_t)d;
+            up = (int32_t)u;
+          }
+        }
+      });
+      if (!(have && best <= K.nf_mmax)) {
+        up = -1;
+        dn = -1;
+      }
     }
-  } else {
-    for (uint32_t h = h0 + threadIdx.x; h < h1; h += blockDim.x) {
-      int32_t up, dn;
-      best_pair(K, S.hit[h], row, Bd, (const Hit*)S.hit, (const uint32_t*)(S.bin_off + Bd.base), 0u,
-                Bu, (const Hit*)S.hit, (const uint32_t*)(S.bin_off + Bu.base), 0u, my, up, dn);
-      S.up[h] = up;
-      S.dn[h] = dn;
-    }
+    S.up[h] = up;
+    S.dn[h] = dn;
   }
 }
 

@@ -4,27 +4,6 @@
 
 namespace tpc {
 
-// a6: every hit keeps the largest weight (n << 24 | 0xFFFFFF - start ID) of
-// the valid tracklets that contain it.  One wave per tracklet, one lane per
-// row: the tracklet's row-indexed hit list is read coalesced.
-__global__ void __launch_bounds__(256) k_weights(Slot S, int g0) {
-  const uint32_t total = S.range_cnt[0];
-  const uint32_t base = S.tl_base[g0];
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
-  for (uint32_t t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < total; t += nw) {
-    const uint32_t T = base + t;
-    const int32_t* info = S.tl_info + (size_t)T * 4;
-    if (!info[3]) continue;
-    const uint32_t w = S.tl_weight[T];
-    const int32_t* hits = S.tl_hits + (size_t)T * kRows;
-    for (int r = info[1] + (int)lane; r <= info[2]; r += 64) {
-      const int32_t h = hits[r];
-      if (h >= 0) atomicMax(&S.weight[h], w);
-    }
-  }
-}
-
 // a6: a valid tracklet becomes a track if it owns (holds the maximal weight
 // of) at least n_min_track of its hits.  Writes 1/0 per tracklet of the
 // range; the scan of these flags places the tracks.
@@ -110,7 +89,7 @@ struct PassOut {
 // state reset to the outermost hit with the prior covariance, transport row
 // by row, update with every owned hit (no gate).  A failed transport ends
 // the pass.  The next hit is loaded one step ahead of its use.
-__device__ void refit_pass(const Slot& S, const DevConst& K, const int32_t* own,
+__device__ __forceinline__ void refit_pass(const Slot& S, const DevConst& K, const int32_t* own,
                            const uint8_t* own_row, int n, int jmin, double s0, double t0,
                            double q0, PassOut& o) {
   const Hit xo = S.hit[own[n - 1]];
@@ -131,38 +110,32 @@ __device__ void refit_pass(const Slot& S, const DevConst& K, const int32_t* own,
   o.n = 1;
   o.chi2 = 0.0;
   const double smax = K.smax, chi2max = K.chi2max;
-  int rcur = o.rlast;
+  // row-synchronous walk (every lane moves one row per iteration); the next
+  // owned hit is loaded one hit ahead
   int j = n - 2;
+  int rn = j >= jmin ? (int)own_row[j] : -1;
   Hit xn;
-  int rn = 0;
-  if (j >= jmin) {
-    xn = S.hit[own[j]];
-    rn = own_row[j];
-  }
-  for (; j >= jmin; --j) {
+  if (j >= jmin) xn = S.hit[own[j]];
+  const int rstop = j >= jmin ? (int)own_row[jmin] : o.rlast;
+  for (int r = o.rlast - 1; r >= rstop; --r) {
+    if (!transport(st, (double)K.row_x[r] - (double)K.row_x[r + 1], K.bd, smax)) break;
+    if (r != rn) continue;
     const Hit xh = xn;
-    const int rh = rn;
-    if (j - 1 >= jmin) {
-      xn = S.hit[own[j - 1]];
-      rn = own_row[j - 1];
-    }
-    bool ok = true;
-    for (int r = rcur - 1; r >= rh; --r) {
-      if (!transport(st, (double)K.row_x[r] - (double)K.row_x[r + 1], K.bd, smax)) {
-        ok = false;
-        break;
-      }
-    }
-    if (!ok) break;
-    rcur = rh;
     const double sy = sy0 + sy1 * fabs(st.z) / zmax, sz = sz0 + sz1 * fabs(st.z) / zmax;
     double ch = 0.0;
     kalman_update(st, (double)xh.y, (double)xh.z, sy * sy, sz * sz, chi2max, smax, false, &ch);
     o.chi2 = o.chi2 + ch;
     o.n += 1;
     o.st = st;
-    o.rlast = rh;
+    o.rlast = r;
     o.jlast = j;
+    --j;
+    if (j >= jmin) {
+      rn = own_row[j];
+      xn = S.hit[own[j]];
+    } else {
+      rn = -1;
+    }
   }
 }
 

@@ -22,10 +22,23 @@ __device__ __forceinline__ int event_of(const int64_t* ev_off, int n_events, int
 }
 
 // a1: validate, count clusters per (sector, row) and give each its rank
-// inside the row (order of arrival; the sort below makes it canonical).
-__global__ void k_count(Slot S) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n; i += stride) {
+// inside the row (arrival order; the row sort below makes it canonical).
+// One block per chunk of kCountChunk clusters of one event (blockIdx.y):
+// ranks are taken in an LDS histogram of the event's rows, then one global
+// atomic per row and block reserves the block's range.
+constexpr int kCountChunk = 16384;
+constexpr int kEventRows = kSectorsPerEvent * kRows;
+
+__global__ void __launch_bounds__(256) k_count(Slot S) {
+  __shared__ uint32_t hist[kEventRows];
+  const int e = blockIdx.y;
+  const int64_t e0 = S.ev_off[e], e1 = S.ev_off[e + 1];
+  const int64_t i0 = e0 + (int64_t)blockIdx.x * kCountChunk;
+  if (i0 >= e1) return;
+  const int64_t i1 = min(e1, i0 + (int64_t)kCountChunk);
+  for (int r = threadIdx.x; r < kEventRows; r += blockDim.x) hist[r] = 0u;
+  __syncthreads();
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     S.tmap[i] = -1;
     const int sec = S.sector[i];
     const int row = S.row[i];
@@ -35,38 +48,20 @@ __global__ void k_count(Slot S) {
       S.rank[i] = kNoHit;
       continue;
     }
-    const int e = event_of(S.ev_off, S.n_events, i);
-    const int sr = (e * kSectorsPerEvent + sec) * kRows + row;
-    S.rank[i] = atomicAdd(&S.row_cnt[sr], 1u);
-  }
-}
-
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds_w, uint32_t* total) {
-  // 1024 threads, wave64: scan in waves, then over the 16 wave sums
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t t = __shfl_up(x, d, 64);
-    if (lane >= d) x += t;
-  }
-  if (lane == 63) lds_w[w] = x;
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const int nw = blockDim.x >> 6;
-    uint32_t s = threadIdx.x < nw ? lds_w[threadIdx.x] : 0u;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      uint32_t t = __shfl_up(s, d, 64);
-      if ((int)threadIdx.x >= d) s += t;
-    }
-    if (threadIdx.x < nw) lds_w[32 + threadIdx.x] = s;
+    S.rank[i] = atomicAdd(&hist[sec * kRows + row], 1u);
   }
   __syncthreads();
-  const uint32_t before = w ? lds_w[32 + w - 1] : 0u;
-  *total = lds_w[32 + (blockDim.x >> 6) - 1];
+  uint32_t* cnt = S.row_cnt + (size_t)e * kEventRows;
+  for (int r = threadIdx.x; r < kEventRows; r += blockDim.x) {
+    const uint32_t c = hist[r];
+    hist[r] = c ? atomicAdd(&cnt[r], c) : 0u;
+  }
   __syncthreads();
-  return before + x - v;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const uint32_t rk = S.rank[i];
+    if (rk == kNoHit) continue;
+    S.rank[i] = rk + hist[S.sector[i] * kRows + S.row[i]];
+  }
 }
 
 // Bin layout of one row with n hits: ~bin_target hits per bin, edges at
@@ -100,73 +95,36 @@ __device__ RowBins make_bins(const DevConst& K, int row, bool side_c, uint32_t n
   return b;
 }
 
-// a2 (one block): row offsets, bin layout and bin bases of every row, and the
-// per-sector regions for start hits / tracklets (<= n_g/3 + 1: chains of >= 3
-// hits are disjoint) and tracks (<= n_g/10 + 1: tracks own >= 10 hits).
-__global__ void __launch_bounds__(1024) k_scan_rows(Slot S, DevConst K) {
-  __shared__ uint32_t wsum[64];
-  __shared__ uint32_t carry_rows, carry_bins;
+// a2: per row, the bin layout (from the row's count) and the two counts
+// the scans turn into offsets: clusters -> row_off, bins -> row_bin.
+__global__ void k_row_layout(Slot S, DevConst K) {
   const int SR = S.n_sectors * kRows;
-  if (threadIdx.x == 0) { carry_rows = 0; carry_bins = 0; }
-  __syncthreads();
-  for (int base = 0; base < SR; base += blockDim.x) {
-    const int sr = base + threadIdx.x;
-    const uint32_t cnt = sr < SR ? S.row_cnt[sr] : 0u;
-    RowBins b;
-    uint32_t nb = 0;
-    if (sr < SR) {
-      const int g = sr / kRows, row = sr % kRows;
-      b = make_bins(K, row, (g % kSectorsPerEvent) >= kSectorsPerEvent / 2, cnt);
-      nb = (uint32_t)(b.ny * b.nz);
-      if (cnt > (uint32_t)kMaxRowHits) atomicAdd(&S.err[1], 1u);
-    }
-    uint32_t tot_r, tot_b;
-    const uint32_t off_r = block_exclusive_scan(cnt, wsum, &tot_r);
-    const uint32_t off_b = block_exclusive_scan(nb, wsum, &tot_b);
-    if (sr < SR) {
-      S.row_off[sr] = carry_rows + off_r;
-      b.base = (int32_t)(carry_bins + off_b);
-      S.bins[sr] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      carry_rows += tot_r;
-      carry_bins += tot_b;
-    }
-    __syncthreads();
+  const int stride = gridDim.x * blockDim.x;
+  for (int sr = blockIdx.x * blockDim.x + threadIdx.x; sr < SR; sr += stride) {
+    const uint32_t cnt = S.row_cnt[sr];
+    const int g = sr / kRows, row = sr - (sr / kRows) * kRows;
+    const RowBins b = make_bins(K, row, (g % kSectorsPerEvent) >= kSectorsPerEvent / 2, cnt);
+    if (cnt > (uint32_t)kMaxRowHits) atomicAdd(&S.err[1], 1u);
+    S.bins[sr] = b;
+    S.row_off[sr] = cnt;
+    S.row_bin[sr] = (uint32_t)(b.ny * b.nz);
   }
-  if (threadIdx.x == 0) {
-    S.row_off[SR] = carry_rows;
-    S.bin_off[carry_bins] = carry_rows;
-  }
-  __syncthreads();
-  // per-sector regions
-  __shared__ uint32_t carry_tl, carry_tk;
-  if (threadIdx.x == 0) { carry_tl = 0; carry_tk = 0; }
-  __syncthreads();
-  for (int base = 0; base < S.n_sectors; base += blockDim.x) {
-    const int g = base + threadIdx.x;
-    uint32_t a = 0, c = 0;
-    if (g < S.n_sectors) {
-      const uint32_t ng = S.row_off[(g + 1) * kRows] - S.row_off[g * kRows];
-      a = ng / 3 + 1;
-      c = ng / 10 + 1;
-    }
-    uint32_t ta, tc;
-    const uint32_t oa = block_exclusive_scan(a, wsum, &ta);
-    const uint32_t oc = block_exclusive_scan(c, wsum, &tc);
-    if (g < S.n_sectors) {
-      S.tl_base[g] = carry_tl + oa;
-      S.tk_base[g] = carry_tk + oc;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) { carry_tl += ta; carry_tk += tc; }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    S.tl_base[S.n_sectors] = carry_tl;
-    S.tk_base[S.n_sectors] = carry_tk;
-    if ((int64_t)carry_tl > S.cap_tl || (int64_t)carry_tk > S.cap_tk) atomicAdd(&S.err[2], 1u);
+}
+
+// a2 (after the scans): bin bases of the rows, and the per-sector regions
+// for start hits / tracklets (<= n_g/3 + 1: chains of >= 3 hits are
+// disjoint) and tracks (<= n_g/10 + 1: tracks own >= 10 hits), as counts
+// for the next scans.
+__global__ void k_row_finish(Slot S) {
+  const int SR = S.n_sectors * kRows;
+  const int stride = gridDim.x * blockDim.x;
+  const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t0 == 0) S.range_cnt[2] = 0;   // rows over 1024 hits, listed by the row sort
+  for (int sr = t0; sr < SR; sr += stride) S.bins[sr].base = (int32_t)S.row_bin[sr];
+  for (int g = t0; g < S.n_sectors; g += stride) {
+    const uint32_t ng = S.row_off[(g + 1) * kRows] - S.row_off[g * kRows];
+    S.tl_base[g] = ng / 3 + 1;
+    S.tk_base[g] = ng / 10 + 1;
   }
 }
 
@@ -185,21 +143,31 @@ __global__ void k_scatter(Slot S) {
   }
 }
 
-// a2: one block per (sector, row): sort the row's hits by (bin, cluster
-// index) with a bitonic sort of 64-bit keys in LDS, write them in that order
-// and fill the row's bin offsets.
-// key = bin << 44 | cluster index << 12 | position in the row
-__global__ void __launch_bounds__(256) k_row_sort(Slot S) {
-  __shared__ unsigned long long key[kMaxRowHits];
-  __shared__ float ly[kMaxRowHits];
-  __shared__ float lz[kMaxRowHits];
-  const int sr = blockIdx.x;
+// a2: one block per (sector, row): order the row's hits by (bin, cluster
+// index) — counting sort by bin in LDS, then an insertion sort by index
+// inside each bin (bins hold ~2 hits) — write them as Hit records and fill
+// the row's bin offsets.  CAP is the largest row the instance handles; the
+// instance for rows up to kMaxRowHits also handles the over-full rows.
+template <int CAP>
+__device__ __forceinline__ void row_sort(Slot& S, int sr, bool small) {
+  __shared__ float ly[CAP];
+  __shared__ float lz[CAP];
+  __shared__ uint32_t lid[CAP];
+  __shared__ uint16_t lbin[CAP];
+  __shared__ uint16_t lrank[CAP];
+  __shared__ uint16_t perm[CAP];
+  __shared__ uint32_t hist[CAP + 1];
+  __shared__ uint32_t wsum[4];
   const uint32_t off = S.row_off[sr];
   const uint32_t n = S.row_off[sr + 1] - off;
+  if (small && n > (uint32_t)CAP) {          // left to the large instance
+    if (threadIdx.x == 0) S.big_rows[atomicAdd(&S.range_cnt[2], 1u)] = sr;
+    return;
+  }
   const RowBins b = S.bins[sr];
   const int nb = b.ny * b.nz;
   if (n > (uint32_t)kMaxRowHits) {
-    // flagged in k_scan_rows (the slot's result is refused); keep the row
+    // flagged in k_row_layout (the slot's result is refused); keep the row
     // harmless for the kernels that still run: no coordinates, empty bins
     for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
       Hit h;
@@ -212,55 +180,78 @@ __global__ void __launch_bounds__(256) k_row_sort(Slot S) {
     for (int bb = threadIdx.x; bb <= nb; bb += blockDim.x) S.bin_off[b.base + bb] = off;
     return;
   }
-  uint32_t P = 1;
-  while (P < n) P <<= 1;
-  for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) {
-    if (j < n) {
-      const float y = S.ty[off + j], z = S.tz[off + j];
-      ly[j] = y;
-      lz[j] = z;
-      const uint32_t bin = (uint32_t)(bin_z(b, z) * b.ny + bin_y(b, y));
-      key[j] = ((unsigned long long)bin << 44) | ((unsigned long long)S.tid[off + j] << 12) | j;
-    } else {
-      key[j] = ~0ull;
+  for (int bb = threadIdx.x; bb <= nb; bb += blockDim.x) hist[bb] = 0u;
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
+    const float y = S.ty[off + j], z = S.tz[off + j];
+    ly[j] = y;
+    lz[j] = z;
+    lid[j] = S.tid[off + j];
+    const uint32_t bin = (uint32_t)(bin_z(b, z) * b.ny + bin_y(b, y));
+    lbin[j] = (uint16_t)bin;
+    lrank[j] = (uint16_t)atomicAdd(&hist[bin], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of hist[0, nb) (each thread a contiguous stretch)
+  {
+    const int per = (nb + blockDim.x - 1) / blockDim.x;
+    const int a = threadIdx.x * per, z = min(nb, a + per);
+    uint32_t sum = 0;
+    for (int k = a; k < z; ++k) sum += hist[k];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = sum;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t t = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += t;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    for (int i = 0; i < w; ++i) run += wsum[i];
+    for (int k = a; k < z; ++k) {
+      const uint32_t c = hist[k];
+      hist[k] = run;
+      run += c;
+    }
+    if (threadIdx.x == 0) hist[nb] = n;
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) perm[hist[lbin[j]] + lrank[j]] = (uint16_t)j;
+  __syncthreads();
+  for (int bb = threadIdx.x; bb < nb; bb += blockDim.x) {
+    const uint32_t p0 = hist[bb], p1 = hist[bb + 1];
+    for (uint32_t i = p0 + 1; i < p1; ++i) {
+      const uint16_t v = perm[i];
+      const uint32_t key = lid[v];
+      uint32_t k = i;
+      while (k > p0 && lid[perm[k - 1]] > key) {
+        perm[k] = perm[k - 1];
+        --k;
+      }
+      perm[k] = v;
     }
   }
   __syncthreads();
-  for (uint32_t k = 2; k <= P; k <<= 1) {
-    for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-      for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
-        const uint32_t l = i ^ jj;
-        if (l > i) {
-          const unsigned long long a = key[i], c = key[l];
-          const bool up = (i & k) == 0;
-          if ((a > c) == up) {
-            key[i] = c;
-            key[l] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
   for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
-    const unsigned long long kk = key[j];
-    const uint32_t src = (uint32_t)(kk & 0xFFFull);
+    const uint16_t src = perm[j];
     Hit h;
     h.y = ly[src];
     h.z = lz[src];
-    h.id = (uint32_t)((kk >> 12) & 0xFFFFFFFFull);
+    h.id = lid[src];
     h.upc = -1;
     S.hit[off + j] = h;
   }
-  // bin offsets: first sorted position whose bin is >= each bin
-  for (int bb = threadIdx.x; bb <= nb; bb += blockDim.x) {
-    uint32_t lo = 0, hi = n;
-    const unsigned long long t = (unsigned long long)bb << 44;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (key[mid] < t) lo = mid + 1; else hi = mid;
-    }
-    S.bin_off[b.base + bb] = off + lo;
+  for (int bb = threadIdx.x; bb <= nb; bb += blockDim.x) S.bin_off[b.base + bb] = off + hist[bb];
+}
+
+// every row; rows over 1024 hits are listed for the large instance
+__global__ void __launch_bounds__(256) k_row_sort_small(Slot S) { row_sort<1024>(S, blockIdx.x, true); }
+// the listed rows (1025..4096 hits, and the over-full ones)
+__global__ void __launch_bounds__(256) k_row_sort_large(Slot S) {
+  const uint32_t nbig = S.range_cnt[2];
+  for (uint32_t i = blockIdx.x; i < nbig; i += gridDim.x) {
+    row_sort<kMaxRowHits>(S, (int)S.big_rows[i], false);
+    __syncthreads();
   }
 }
 

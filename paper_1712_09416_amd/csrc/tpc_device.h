@@ -15,7 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/tpcca.h"
+#include "tpcca.h"
 
 namespace tpc {
 
@@ -72,6 +72,7 @@ struct Slot {
   uint32_t* row_cnt;        // [SR]
   uint32_t* row_off;        // [SR+1] first sorted hit of each (sector, row)
   RowBins* bins;            // [SR]
+  uint32_t* row_bin;        // [SR+1] bins per row, then the rows' first bin
   uint32_t* bin_off;        // [n + SR + 1]
   uint32_t* rank;           // [n]
   float* ty;                // [n] row-ordered, unsorted within a row
@@ -86,7 +87,8 @@ struct Slot {
   uint32_t* tl_base;        // [S+1] tracklet region of each sector
   uint32_t* tk_base;        // [S+1] track region of each sector
   uint32_t* row_nstart;     // [SR+1] start hits per row, then their offsets
-  uint32_t* range_cnt;      // [4]: tracklets, tracks of the launched range
+  uint32_t* range_cnt;      // [4]: tracklets, tracks of the launched range; rows > 1024 hits
+  uint32_t* big_rows;       // [n / 1024 + 1] (sector, row) of the rows over 1024 hits
   int32_t* start_hit;       // [tl capacity] sorted index of the start hit
   int32_t* start_sr;        // [tl capacity] (sector, row) of the start hit
   // tracklets

@@ -7,16 +7,17 @@ namespace tpc {
 
 // stage + grid
 __global__ void k_count(Slot S);
-__global__ void k_scan_rows(Slot S, DevConst K);
+__global__ void k_row_layout(Slot S, DevConst K);
+__global__ void k_row_finish(Slot S);
 __global__ void k_scatter(Slot S);
-__global__ void k_row_sort(Slot S);
+__global__ void k_row_sort_small(Slot S);
+__global__ void k_row_sort_large(Slot S);
 // cellular automaton
 __global__ void k_neighbours(Slot S, DevConst K, int g0);
 __global__ void k_clean_rows(Slot S, int g0);
 __global__ void k_start_write(Slot S, int g0);
 // Kalman filter
 __global__ void k_tracklets(Slot S, DevConst K, int g0);
-__global__ void k_weights(Slot S, int g0);
 __global__ void k_select(Slot S, DevConst K, int g0);
 __global__ void k_track_write(Slot S, int g0);
 __global__ void k_refit(Slot S, DevConst K, int g0);

@@ -8,9 +8,8 @@
 namespace tpc {
 
 template <class Fn>
-__device__ __forceinline__ void for_window_t(const Slot& S, int sr, float yc, float zc, float wy,
-                                             float wz, Fn&& fn) {
-  const RowBins b = S.bins[sr];
+__device__ __forceinline__ void for_window_t(const Slot& S, const RowBins& b, float yc, float zc,
+                                             float wy, float wz, Fn&& fn) {
   const float eps = 1e-3f;
   const int iy0 = bin_y(b, yc - wy - eps), iy1 = bin_y(b, yc + wy + eps);
   const int iz0 = bin_z(b, zc - wz - eps), iz1 = bin_z(b, zc + wz + eps);
@@ -35,7 +34,7 @@ __device__ __forceinline__ bool inside(const DevConst& K, const Helix<float>& h,
 // Best hit of row sr for the predicted state: inside
 // |r_y| <= min(k sqrt(S_yy), w_max), |r_z| <= min(k sqrt(S_zz), w_max),
 // smallest chi2, ties to the smaller cluster ID.  -1 if none.
-__device__ __forceinline__ int32_t search_row(const Slot& S, const DevConst& K, int sr,
+__device__ __forceinline__ int32_t search_row(const Slot& S, const DevConst& K, const RowBins& rb,
                                               const Helix<float>& h, float vy, float vz,
                                               unsigned& examined) {
   const Resid<float> w = resid_weights(h, vy, vz);
@@ -47,7 +46,7 @@ __device__ __forceinline__ int32_t search_row(const Slot& S, const DevConst& K, 
   int32_t best = -1;
   float bchi = 0.0f;
   uint32_t bid = 0;
-  for_window_t(S, sr, yc, zc, wy, wz, [&](uint32_t p) {
+  for_window_t(S, rb, yc, zc, wy, wz, [&](uint32_t p) {
     ++examined;
     const Hit x = S.hit[p];
     const float ry = x.y - yc, rz = x.z - zc;
@@ -129,6 +128,7 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
     int miss = 0;
     for (int r = r0 + 1; r < kRows; ++r) {
       ++visits;
+      const RowBins rb = S.bins[g * kRows + r];   // independent of the state: issued early
       if (!transport(st, K.row_x[r] - K.row_x[r - 1], K.b, K.smax)) break;
       if (!inside(K, st, r, side_c)) break;
       const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
         if (got < 0) chain = false;
       }
       if (got < 0) {
-        const int32_t bh = search_row(S, K, g * kRows + r, st, vy, vz, examined);
+        const int32_t bh = search_row(S, K, rb, st, vy, vz, examined);
         if (bh >= 0) {
           xg = S.hit[bh];
           if (try_hit(K, st, xg, vy, vz)) got = bh;
@@ -174,17 +174,29 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
     int rin = rout;
     last = st;
     miss = 0;
+    // the outward hit of the next row down, loaded one step ahead
+    int32_t uh_next = rout - 1 >= r0 && rout >= 1 ? hits[rout - 1] : -1;
+    Hit xu_next;
+    if (uh_next >= 0) xu_next = S.hit[uh_next];
     for (int r = rout - 1; r >= 0; --r) {
       ++visits;
+      const RowBins rb = S.bins[g * kRows + r];
+      const int32_t uh = uh_next;
+      const Hit xu = xu_next;
+      if (r - 1 >= r0) {
+        uh_next = hits[r - 1];
+        if (uh_next >= 0) xu_next = S.hit[uh_next];
+      } else {
+        uh_next = -1;
+      }
       if (!transport(st, K.row_x[r] - K.row_x[r + 1], K.b, K.smax)) break;
       if (!inside(K, st, r, side_c)) break;
       const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
       const float vy = sy * sy, vz = sz * sz;
       int32_t got = -1;
-      const int32_t uh = r >= r0 ? hits[r] : -1;
-      if (uh >= 0 && try_hit(K, st, S.hit[uh], vy, vz)) got = uh;
+      if (uh >= 0 && try_hit(K, st, xu, vy, vz)) got = uh;
       if (got < 0) {
-        const int32_t bh = search_row(S, K, g * kRows + r, st, vy, vz, examined);
+        const int32_t bh = search_row(S, K, rb, st, vy, vz, examined);
         if (bh >= 0 && try_hit(K, st, S.hit[bh], vy, vz)) got = bh;
       }
       hits[r] = got;
@@ -198,12 +210,23 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
       }
     }
     int32_t* info = S.tl_info + (size_t)T * 4;
+    const bool valid = n >= K.n_min_tracklet;
     info[0] = n;
     info[1] = rin;
     info[2] = rout;
-    info[3] = n >= K.n_min_tracklet ? 1 : 0;
+    info[3] = valid ? 1 : 0;
     const uint32_t id0 = (uint32_t)((int64_t)x0.id - ev0);
-    S.tl_weight[T] = ((uint32_t)n << 24) | (0xFFFFFFu - id0);
+    const uint32_t w = ((uint32_t)n << 24) | (0xFFFFFFu - id0);
+    S.tl_weight[T] = w;
+    // a6 (ownership): every hit of a valid tracklet keeps the largest weight
+    // of the tracklets holding it; issued here, without waiting for results,
+    // so the atomics overlap the other lanes' Kalman steps
+    if (valid) {
+      for (int r = rin; r <= rout; ++r) {
+        const int32_t h = hits[r];
+        if (h >= 0) atomicMax(&S.weight[h], w);
+      }
+    }
     float* sv = S.tl_state + (size_t)T * 5;
     sv[0] = last.y;
     sv[1] = last.z;

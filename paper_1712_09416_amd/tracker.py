@@ -56,7 +56,8 @@ class Tracker:
         if nbytes == 0:
             raise ValueError("invalid tracker parameters")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (graph capture needs a non-default stream)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.ctx = ctypes.c_void_p()
         rc = self.L.tpc_init_geometry(ctypes.byref(self.ctx), ctypes.byref(self.geometry),
                                       ctypes.byref(self.params), self.workspace.data_ptr(),
@@ -70,6 +71,8 @@ class Tracker:
         numpy arrays are copied to the device asynchronously."""
         dev = isinstance(y, torch.Tensor) and y.is_cuda
         arrs = self._prep(sector, row, y, z, dev)
+        if dev:
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self._keep[slot] = arrs
         flags = _lib.TPC_DEVICE if dev else _lib.TPC_HOST
         n = int(arrs[2].shape[0])
@@ -82,6 +85,8 @@ class Tracker:
         arrs = self._prep(sector, row, y, z, dev)
         offs = np.ascontiguousarray(offsets, np.int64)
         self._keep[slot] = arrs + (offs,)
+        if dev:
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
         flags = _lib.TPC_DEVICE if dev else _lib.TPC_HOST
         check(self.L.tpc_load_batch(self.ctx, slot, len(offs) - 1, offs.ctypes.data, _ptr(arrs[0]),
                                     _ptr(arrs[1]), _ptr(arrs[2]), _ptr(arrs[3]), None, flags),
@@ -101,6 +106,22 @@ class Tracker:
 
     def track_sector(self, slot: int, sector: int):
         check(self.L.tpc_track_sector(self.ctx, slot, sector), self.ctx)
+
+    def capture(self, slot: int = 0):
+        """Record the slot's tracking sequence into a HIP graph."""
+        check(self.L.tpc_graph_capture(self.ctx, slot), self.ctx)
+
+    def launch(self, slot: int = 0):
+        """Replay the slot's graph (asynchronous)."""
+        check(self.L.tpc_graph_launch(self.ctx, slot), self.ctx)
+
+    def poll(self, slot: int = 0) -> bool:
+        """True when all work enqueued for the slot has finished."""
+        rc = self.L.tpc_poll(self.ctx, slot)
+        if rc == _lib.TPC_EBUSY:
+            return False
+        check(rc, self.ctx)
+        return True
 
     # -- results ---------------------------------------------------------------
     def get_tracks(self, slot: int = 0, event: int = 0):

@@ -264,3 +264,55 @@ def test_repeat_runs_identical(dev):
     b = gpu_run(ev, dev, links=False)
     assert np.array_equal(a[1], b[1])
     assert np.array_equal(a[0], b[0])
+
+
+def test_graph_replays_match_eager(dev):
+    """The captured tracking graph, replayed several times with other eager
+    work in between, gives the eager result every time; a slot re-staged with
+    another shape is refused."""
+    from paper_1712_09416_amd import Tracker, TpcError
+    ev = tpcgen.pbpb_event(tpcgen.seed_for(2) + 90, 1500)
+    trk = Tracker(ev.geometry(), max_clusters=ev.n + 100)
+    ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.sector, ev.row, ev.y, ev.z)]
+    trk.load(0, *ins)
+    trk.track_event(0)
+    ref_t, ref_h = trk.get_tracks(0)
+    trk.load(0, *ins)
+    trk.capture(0)
+    for k in range(4):
+        junk = torch.randn(1 << 20, device=dev).sum().item()       # eager work between replays
+        assert np.isfinite(junk)
+        trk.launch(0)
+        t, h = trk.get_tracks(0)
+        assert np.array_equal(h, ref_h), k
+        assert np.array_equal(t, ref_t), k
+        trk.load(0, *ins)
+    other = [a[:-10].contiguous() for a in ins]
+    trk.load(0, *other)
+    with pytest.raises(TpcError):
+        trk.launch(0)
+    trk.close()
+
+
+def test_serving_results_equal_alone(dev):
+    """Requests served with continuous batching over several streams (and
+    with the plain one-at-a-time path) give each event exactly its
+    single-event result."""
+    from paper_1712_09416_amd.serve import Server, Request, poisson_arrivals
+    pool = [tpcgen.pbpb_event(tpcgen.seed_for(4, e), m) for e, m in enumerate([60, 300, 900, 150])]
+    geo = pool[0].geometry()
+    alone = [gpu_run(ev, dev, links=False, geometry=geo)[:2] for ev in pool]
+    arr = poisson_arrivals(40, 2000.0, seed=5)
+    reqs = [Request(float(arr[i]), pool[i % 4].sector, pool[i % 4].row, pool[i % 4].y,
+                    pool[i % 4].z, tag=str(i % 4)) for i in range(40)]
+    for plain in (False, True):
+        srv = Server(geo, n_streams=3, max_events=4, cap_clusters=600_000, plain=plain)
+        st = srv.run(reqs, collect=True)
+        srv.close()
+        say(f"serving plain={plain}: {st.summary()}")
+        assert st.n_requests == 40
+        for i, (t, h) in enumerate(st.results):
+            rt, rh = alone[i % 4]
+            assert np.array_equal(h, rh), (plain, i)
+            for k in ("n_hits", "inner_id", "hit_off", "par", "cov", "chi2", "sector"):
+                assert np.array_equal(t[k], rt[k]), (plain, i, k)
