@@ -64,9 +64,10 @@ def serve_pool_specs():
 def bench_batch(evs, geo, dev, steps: int) -> dict:
     """64 events of uneven size (Pb-Pb shape, multiplicity log-uniform
     50-15000): tracked together in one slot (one launch per step over all
-    2304 sectors), replayed from a HIP graph; compared with the same slot
-    without the graph, with one event at a time (fused launches) and with
-    the plain per-sector launch sequence."""
+    2304 sectors), replayed from a HIP graph, with the grid knobs autotuned
+    on the batch; compared with the same slot without the graph, with one
+    event at a time (fused launches) and with the plain per-sector launch
+    sequence."""
     import numpy as np
     import torch
     from paper_1712_09416_amd import Tracker
@@ -75,7 +76,12 @@ def bench_batch(evs, geo, dev, steps: int) -> dict:
     total = int(offs[-1])
     cat = [torch.from_numpy(np.concatenate([getattr(e, k) for e in evs])).to(dev)
            for k in ("sector", "row", "y", "z")]
-    trk = Tracker(geo, max_events=len(evs), max_clusters=total)
+    # grid knobs tuned on this batch (the tuner checks the tracks do not change)
+    from paper_1712_09416_amd.autotune import autotune
+    tune = autotune(geo, offs, *cat, reps=3)
+    bt, be = tune["best"]
+    print(f"bench: batch autotune {tune}", file=sys.stderr, flush=True)
+    trk = Tracker(geo, max_events=len(evs), max_clusters=total, bin_target=bt, bin_min_edge=be)
     st = trk.stream
 
     def timed(fn, reps):
@@ -124,7 +130,9 @@ def bench_batch(evs, geo, dev, steps: int) -> dict:
             "graph_ms": ms_graph, "graph_clusters_per_s": rate(ms_graph),
             "one_launch_per_step_ms": ms_eager, "one_launch_per_step_clusters_per_s": rate(ms_eager),
             "per_event_ms": ms_events, "per_event_clusters_per_s": rate(ms_events),
-            "plain_ms": ms_plain, "plain_clusters_per_s": rate(ms_plain)}
+            "plain_ms": ms_plain, "plain_clusters_per_s": rate(ms_plain),
+            "autotune": {"best": {"bin_target": bt, "bin_min_edge": be},
+                         "graph_ms": {f"{t:g}/{e:g}": v for (t, e), v in tune["ms"].items()}}}
 
 
 def bench_serve(pool, geo, n_req: int) -> dict:
@@ -164,10 +172,14 @@ def bench_serve(pool, geo, n_req: int) -> dict:
         srv.run(requests(np.zeros(40))[:40])
         st = srv.run(requests(poisson_arrivals(len(picks), rate, seed=7)), warmup=warm)
         srv.close()
-        return st.summary()
+        out = st.summary()
+        print(f"bench: serve plain={plain} rate {rate:.1f}/s: {out}", file=sys.stderr, flush=True)
+        return out
 
     c_plain = capacity(True)
+    print(f"bench: serve plain capacity {c_plain:.1f} events/s", file=sys.stderr, flush=True)
     c_cb = capacity(False)
+    print(f"bench: serve batching capacity {c_cb:.1f} events/s", file=sys.stderr, flush=True)
     r1 = 0.7 * c_plain
     return {"mix": "70% pp / 25% peripheral (2000 primaries) / 5% central, pool of 34 distinct events",
             "capacity_events_per_s": {"plain": c_plain, "continuous_batching": c_cb},
@@ -192,13 +204,15 @@ def cpu_baseline(ev, threads: int) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=3,
                     help="steps of the per-sector (plain) launch sequence, for comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
+    ap.add_argument("--e2e-steps", type=int, default=20,
+                    help="end-to-end steps (host clusters in, host tracks out)")
     ap.add_argument("--batch-events", type=int, default=64,
                     help="events of the batched workload (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -228,13 +242,22 @@ def main() -> int:
     from paper_1712_09416_amd import Tracker
 
     dev = torch.device("cuda:0")
-    if args.copy_calibration:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+    # a plain 1 GiB device copy: the practical bandwidth ceiling on this GPU,
+    # and the reference kernel for scaling the HBM byte counters
+    a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_copy = 1 if args.copy_calibration else 10
+    torch.cuda.synchronize()
+    c0.record()
+    for _ in range(n_copy):
+        b.copy_(a)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * a.numel() * n_copy / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del a, b
     ev = Ev(central)
     print(f"bench: central event {ev.n} clusters", file=sys.stderr, flush=True)
     ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.sector, ev.row, ev.y, ev.z)]
@@ -263,6 +286,19 @@ def main() -> int:
     wall_ms = (time.perf_counter() - w0) * 1e3
     lat = [e0.elapsed_time(e1) for e0, e1 in ev_steps]
     total_ms = ev_steps[0][0].elapsed_time(ev_steps[-1][1])
+
+    # end to end: clusters in pinned host memory -> tracks in host memory
+    e2e = []
+    if args.e2e_steps > 0:
+        pin = [torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+               for a in (ev.sector, ev.row, ev.y, ev.z)]
+        for k in range(args.e2e_steps + 2):
+            t0 = time.perf_counter()
+            trk.load(0, *pin)
+            trk.track_event(0)
+            trk.get_tracks(0)
+            if k >= 2:
+                e2e.append((time.perf_counter() - t0) * 1e3)
 
     # per-stage times and work counters: separate profiled steps
     trk.set_profiling(True)
@@ -294,12 +330,22 @@ def main() -> int:
             trk.get_tracks(0)
         plain_ms = (time.perf_counter() - p0) * 1e3 / args.plain_steps
         plain = {"ms_per_event": plain_ms, "clusters_per_s": ev.n / (plain_ms * 1e-3)}
+        # the same per-sector sequences spread over 4 streams (concurrent sectors)
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            trk.load(0, *ins)
+            trk.track_event_streams(0, 4)
+            trk.get_tracks(0)
+        ms4 = (time.perf_counter() - p0) * 1e3 / args.plain_steps
+        plain["streams4_ms_per_event"] = ms4
+        plain["streams4_clusters_per_s"] = ev.n / (ms4 * 1e-3)
 
     t_tl = stage_ms["tracklets"] * 1e-3
     ach = tracklet_bytes(counters) / t_tl / 1e9
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "k_tracklets",
-            "launch_ms": stage_ms["tracklets"]}
+            "launch_ms": stage_ms["tracklets"], "copy_kernel_gbs": copy_gbs}
 
     out = {
         "metric": METRIC,
@@ -325,9 +371,14 @@ def main() -> int:
         "tracks": int(len(tracks)),
         "track_hits": int(len(hits)),
         "plain": plain,
+        "end_to_end": ({"what": "pinned host clusters -> H2D -> tracking -> tracks in host memory",
+                        "p50_ms": float(np.percentile(e2e, 50)),
+                        "p99_ms": float(np.percentile(e2e, 99)),
+                        "clusters_per_s": ev.n / (float(np.mean(e2e)) * 1e-3)} if e2e else None),
         "roofline": roof,
     }
     trk.close()
+    print(f"bench: central {ms_per_step:.3f} ms/step, stages {stage_ms}", file=sys.stderr, flush=True)
     if len(batch_evs):
         out["batch"] = bench_batch(batch_evs, ev.geometry(), dev, args.batch_steps)
         print(f"bench: batch {out['batch']}", file=sys.stderr, flush=True)

@@ -158,6 +158,19 @@ int tpc_track_sector(tpc_ctx* ctx, int slot, int sector);
  * tpc_get_tracks.  Errors: TPC_EINVAL, TPC_ESTATE. */
 int tpc_track_event(tpc_ctx* ctx, int slot);
 
+/* Track every sector of the slot with the per-sector launch sequence of
+ * tpc_track_sector, sector g on the library's own stream g mod n_streams
+ * (1 <= n_streams <= 8; streams at default priority, created on first use),
+ * after the grid is built on the context stream; the context stream waits
+ * for all of them before the canonical ordering.  The paper's concurrent
+ * kernels of independent sectors (Section 4.2), kept as an alternative to
+ * the one-launch-per-step path: the tracks are identical to
+ * tpc_track_event's.  Each stream has its own counters and scan space, so
+ * sectors in flight together share no scratch.  Asynchronous.  Errors:
+ * TPC_EINVAL, TPC_ESTATE (slot not staged or already tracked, or called
+ * during graph capture), TPC_EDEVICE. */
+int tpc_track_event_streams(tpc_ctx* ctx, int slot, int n_streams);
+
 /* Wait for the slot and copy the tracks of one event of it (event = 0 for
  * tpc_load_clusters) into caller host memory: out[max_tracks],
  * hit_ids[max_hits] (cluster IDs, each track's hits ascending by row).

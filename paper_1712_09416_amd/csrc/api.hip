@@ -171,6 +171,35 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   s.cap_e = E;
 }
 
+// Per-stream copies of the only buffers that the per-sector launch sequence
+// shares between sectors (start/track counters, scan partials, selection
+// flags), so sectors on different streams never touch the same bytes.
+constexpr int kMaxLanes = 8;
+struct Lane {
+  hipStream_t st = nullptr;
+  hipEvent_t done = nullptr;
+  uint32_t* range_cnt = nullptr;
+  uint32_t* scan_b = nullptr;
+  uint32_t* tl_sel = nullptr;
+};
+
+void carve_lanes(Carver& c, const tpc_params& p, Lane* lanes) {
+  const int64_t N = p.max_clusters;
+  const int64_t S = (int64_t)p.max_events * kSectorsPerEvent;
+  const int64_t SR = S * kRows;
+  const int64_t cap_tl = N / 3 + S;
+  for (int i = 0; i < kMaxLanes; ++i) {
+    uint32_t* a = c.take<uint32_t>(4);
+    uint32_t* b = c.take<uint32_t>(std::max<int64_t>(std::max<int64_t>(N, SR), cap_tl) / kScanTile + 4);
+    uint32_t* t = c.take<uint32_t>(cap_tl + 1);
+    if (lanes) {
+      lanes[i].range_cnt = a;
+      lanes[i].scan_b = b;
+      lanes[i].tl_sel = t;
+    }
+  }
+}
+
 bool params_ok(const tpc_params* p) {
   if (!p) return false;
   if (!(p->max_slots >= 1 && p->max_slots <= 1024)) return false;
@@ -202,6 +231,8 @@ struct tpc_ctx {
   bool capturing = false;
   int prof_slot = -1;
   hipEvent_t ev[TPC_N_STAGES + 1] = {};
+  Lane lanes[kMaxLanes];
+  hipEvent_t fork = nullptr;
   int fail(int code, const std::string& m) {
     err = m;
     return code;
@@ -278,28 +309,35 @@ int build_grid(tpc_ctx* ctx, SlotHost& h) {
   return TPC_OK;
 }
 
-int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns) {
-  Slot& s = h.d;
+int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nullptr) {
+  Slot s = h.d;
   hipStream_t st = ctx->stream;
+  if (lane) {
+    s.range_cnt = lane->range_cnt;
+    s.scan_b = lane->scan_b;
+    s.tl_sel = lane->tl_sel;
+    st = lane->st;
+  }
+  const bool marks = lane == nullptr;
   // host bounds for the persistent grids (exact counts live on the device)
   const int64_t tl_bound = std::min<int64_t>(s.cap_tl, h.n / 3 + ns);
   const int nb_lane = std::max(8, grid_stride_blocks(tl_bound, 64, 16384) / 8 * 8);
   const int nb_wave = grid_stride_blocks(tl_bound * 64, 256, 8192);
   k_neighbours<<<dim3(kRows, ns), 256, 0, st>>>(s, ctx->k, g0);
-  mark(ctx, 2);
+  if (marks) mark(ctx, 2);
   k_clean_rows<<<dim3(kRows, ns), 256, 0, st>>>(s, g0);
   scan_u32(st, s.row_nstart + (size_t)g0 * kRows, nullptr, (int64_t)ns * kRows, s.scan_b,
            s.range_cnt + 0, false);
   k_start_write<<<dim3(kRows, ns), 256, 0, st>>>(s, g0);
-  mark(ctx, 3);
+  if (marks) mark(ctx, 3);
   k_tracklets<<<nb_lane, 64, 0, st>>>(s, ctx->k, g0);
-  mark(ctx, 4);
+  if (marks) mark(ctx, 4);
   k_select<<<nb_wave, 256, 0, st>>>(s, ctx->k, g0);
   scan_u32(st, s.tl_sel, s.range_cnt + 0, tl_bound, s.scan_b, s.range_cnt + 1, false);
   k_track_write<<<nb_wave, 256, 0, st>>>(s, g0);
-  mark(ctx, 5);
+  if (marks) mark(ctx, 5);
   k_refit<<<grid_stride_blocks(std::max<int64_t>(1, tl_bound / 4), 64, 4096), 64, 0, st>>>(s, ctx->k, g0);
-  mark(ctx, 6);
+  if (marks) mark(ctx, 6);
   TPC_LAUNCHED();
   return TPC_OK;
 }
@@ -402,6 +440,7 @@ size_t tpc_workspace_bytes(const tpc_params* p) {
     Slot s{};
     carve_slot(c, *p, s, nullptr);
   }
+  carve_lanes(c, *p, nullptr);
   return c.off + 256;
 }
 
@@ -475,6 +514,7 @@ int tpc_init_geometry(tpc_ctx** out, const tpc_geometry* g, const tpc_params* p,
   Carver c{ctx->ws, 0, false};
   ctx->slots.resize(p->max_slots);
   for (int i = 0; i < p->max_slots; ++i) carve_slot(c, *p, ctx->slots[i].d, &ctx->slots[i]);
+  carve_lanes(c, *p, ctx->lanes);
   *out = ctx;
   return TPC_OK;
 }
@@ -528,6 +568,39 @@ int tpc_track_event(tpc_ctx* ctx, int slot) {
   if (rc) return rc;
   ctx->prof_valid = ctx->prof;
   ctx->prof_slot = slot;
+  return record_done(ctx, h);
+}
+
+int tpc_track_event_streams(tpc_ctx* ctx, int slot, int n_streams) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  if (n_streams < 1 || n_streams > kMaxLanes)
+    return ctx->fail(TPC_EINVAL, "n_streams must be 1..8");
+  if (ctx->capturing) return ctx->fail(TPC_ESTATE, "not available under capture");
+  SlotHost& h = ctx->slots[slot];
+  if (h.state < 1 || h.state >= 3) return ctx->fail(TPC_ESTATE, "slot not staged or already tracked");
+  for (int i = 0; i < n_streams; ++i) {
+    Lane& l = ctx->lanes[i];
+    if (!l.st) TPC_HIP(hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking));
+    if (!l.done) TPC_HIP(hipEventCreateWithFlags(&l.done, hipEventDisableTiming));
+  }
+  if (!ctx->fork) TPC_HIP(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+  if (h.state < 2) {
+    const int rc = build_grid(ctx, h);
+    if (rc) return rc;
+  }
+  TPC_HIP(hipEventRecord(ctx->fork, ctx->stream));
+  for (int i = 0; i < n_streams; ++i) TPC_HIP(hipStreamWaitEvent(ctx->lanes[i].st, ctx->fork, 0));
+  for (int g = 0; g < h.d.n_sectors; ++g) {
+    const int rc = track_range(ctx, h, g, 1, &ctx->lanes[g % n_streams]);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < n_streams; ++i) {
+    TPC_HIP(hipEventRecord(ctx->lanes[i].done, ctx->lanes[i].st));
+    TPC_HIP(hipStreamWaitEvent(ctx->stream, ctx->lanes[i].done, 0));
+  }
+  const int rc = finalize(ctx, h);
+  if (rc) return rc;
   return record_done(ctx, h);
 }
 
@@ -724,6 +797,14 @@ int tpc_destroy(tpc_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (int i = 0; i <= TPC_N_STAGES; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  for (Lane& l : ctx->lanes) {
+    if (l.st) {
+      (void)hipStreamSynchronize(l.st);
+      (void)hipStreamDestroy(l.st);
+    }
+    if (l.done) (void)hipEventDestroy(l.done);
+  }
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   for (SlotHost& h : ctx->slots) {
     if (h.graph) (void)hipGraphExecDestroy(h.graph);
     if (h.done) (void)hipEventDestroy(h.done);

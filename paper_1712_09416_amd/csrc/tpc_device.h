@@ -140,6 +140,46 @@ __device__ __forceinline__ int bin_z(const RowBins& b, float z) {
   return f >= 0.0f ? (int)fminf(f, (float)(b.nz - 1)) : 0;
 }
 
+// Hits of one row that can lie inside [yc - wy, yc + wy] x [zc - wz, zc + wz]:
+// every bin the window touches, plus a small margin so rounding cannot hide
+// a hit; the caller applies the exact window test.  `bo` is the row's bin
+// offset table (sorted-hit positions).  The bin ranges of up to four z rows
+// are read together, then each range's hits four at a time, so a query
+// waits for a few memory round trips rather than one per hit.  fn(p, hit)
+// runs in ascending p within a range, ranges in ascending z.
+template <class Fn>
+__device__ __forceinline__ void for_window_hits(const RowBins& b, const uint32_t* bo, const Hit* hit,
+                                                float yc, float zc, float wy, float wz, Fn&& fn) {
+  const float eps = 1e-3f;
+  const int iy0 = bin_y(b, yc - wy - eps), iy1 = bin_y(b, yc + wy + eps);
+  const int iz0 = bin_z(b, zc - wz - eps), iz1 = bin_z(b, zc + wz + eps);
+  for (int izb = iz0; izb <= iz1; izb += 4) {
+    uint32_t lo[4], hi[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      lo[k] = 0u;
+      hi[k] = 0u;
+      if (izb + k <= iz1) {
+        const int first = (izb + k) * b.ny;
+        lo[k] = bo[first + iy0];
+        hi[k] = bo[first + iy1 + 1];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      for (uint32_t p = lo[k]; p < hi[k]; p += 4) {
+        Hit x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (p + u < hi[k]) x[u] = hit[p + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (p + u < hi[k]) fn(p + u, x[u]);
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ float sigma_y(const DevConst& k, float z) {
   return k.sy0 + k.sy1 * fabsf(z) / k.z_max;
 }

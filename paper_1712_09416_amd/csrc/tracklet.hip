@@ -7,21 +7,6 @@
 
 namespace tpc {
 
-template <class Fn>
-__device__ __forceinline__ void for_window_t(const Slot& S, const RowBins& b, float yc, float zc,
-                                             float wy, float wz, Fn&& fn) {
-  const float eps = 1e-3f;
-  const int iy0 = bin_y(b, yc - wy - eps), iy1 = bin_y(b, yc + wy + eps);
-  const int iz0 = bin_z(b, zc - wz - eps), iz1 = bin_z(b, zc + wz + eps);
-  const uint32_t* bo = S.bin_off + b.base;
-  for (int iz = iz0; iz <= iz1; ++iz) {
-    const int first = iz * b.ny;
-    const uint32_t p0 = bo[first + iy0];
-    const uint32_t p1 = bo[first + iy1 + 1];
-    for (uint32_t p = p0; p < p1; ++p) fn(p);
-  }
-}
-
 // Stop rules after a transport to row r: left the sector sideways, crossed
 // the membrane, or left the drift volume.
 __device__ __forceinline__ bool inside(const DevConst& K, const Helix<float>& h, int r, bool side_c) {
@@ -33,10 +18,11 @@ __device__ __forceinline__ bool inside(const DevConst& K, const Helix<float>& h,
 
 // Best hit of row sr for the predicted state: inside
 // |r_y| <= min(k sqrt(S_yy), w_max), |r_z| <= min(k sqrt(S_zz), w_max),
-// smallest chi2, ties to the smaller cluster ID.  -1 if none.
+// smallest chi2, ties to the smaller cluster ID.  -1 if none; the hit record
+// is returned in `out`.
 __device__ __forceinline__ int32_t search_row(const Slot& S, const DevConst& K, const RowBins& rb,
                                               const Helix<float>& h, float vy, float vz,
-                                              unsigned& examined) {
+                                              unsigned& examined, Hit& out) {
   const Resid<float> w = resid_weights(h, vy, vz);
   float wy = K.kwin * sqrtf(w.s00);
   if (wy > K.wmax) wy = K.wmax;
@@ -46,9 +32,8 @@ __device__ __forceinline__ int32_t search_row(const Slot& S, const DevConst& K, 
   int32_t best = -1;
   float bchi = 0.0f;
   uint32_t bid = 0;
-  for_window_t(S, rb, yc, zc, wy, wz, [&](uint32_t p) {
+  for_window_hits(rb, S.bin_off + rb.base, S.hit, yc, zc, wy, wz, [&](uint32_t p, const Hit& x) {
     ++examined;
-    const Hit x = S.hit[p];
     const float ry = x.y - yc, rz = x.z - zc;
     if (!(fabsf(ry) <= wy && fabsf(rz) <= wz)) return;
     const float ch = chi2_of(w, ry, rz);
@@ -57,6 +42,7 @@ __device__ __forceinline__ int32_t search_row(const Slot& S, const DevConst& K, 
       best = (int32_t)p;
       bchi = ch;
       bid = id;
+      out = x;
     }
   });
   return best;
@@ -143,11 +129,8 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
         if (got < 0) chain = false;
       }
       if (got < 0) {
-        const int32_t bh = search_row(S, K, rb, st, vy, vz, examined);
-        if (bh >= 0) {
-          xg = S.hit[bh];
-          if (try_hit(K, st, xg, vy, vz)) got = bh;
-        }
+        const int32_t bh = search_row(S, K, rb, st, vy, vz, examined, xg);
+        if (bh >= 0 && try_hit(K, st, xg, vy, vz)) got = bh;
       }
       hits[r] = got;
       if (got >= 0) {
@@ -196,8 +179,9 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
       int32_t got = -1;
       if (uh >= 0 && try_hit(K, st, xu, vy, vz)) got = uh;
       if (got < 0) {
-        const int32_t bh = search_row(S, K, rb, st, vy, vz, examined);
-        if (bh >= 0 && try_hit(K, st, S.hit[bh], vy, vz)) got = bh;
+        Hit xs;
+        const int32_t bh = search_row(S, K, rb, st, vy, vz, examined, xs);
+        if (bh >= 0 && try_hit(K, st, xs, vy, vz)) got = bh;
       }
       hits[r] = got;
       if (got >= 0) {

@@ -104,6 +104,10 @@ class Tracker:
     def track_event(self, slot: int = 0):
         check(self.L.tpc_track_event(self.ctx, slot), self.ctx)
 
+    def track_event_streams(self, slot: int = 0, n_streams: int = 4):
+        """Per-sector launch sequences spread over n_streams streams."""
+        check(self.L.tpc_track_event_streams(self.ctx, slot, n_streams), self.ctx)
+
     def track_sector(self, slot: int, sector: int):
         check(self.L.tpc_track_sector(self.ctx, slot, sector), self.ctx)
 

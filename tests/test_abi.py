@@ -50,7 +50,10 @@ def test_workspace_bytes(L):
     b = L.tpc_workspace_bytes(ctypes.byref(p2))
     p3 = default_params(max_clusters=1 << 20, max_slots=3)
     c = L.tpc_workspace_bytes(ctypes.byref(p3))
-    assert 0 < a < b and c >= 3 * a - 3 * 4096
+    # each further slot adds the same bytes; the per-stream scratch of the
+    # multi-stream path is carved once per context
+    slot = (c - a) // 2
+    assert 0 < a < b and c - a == 2 * slot and 0.8 * a < slot < a
     bad = default_params(max_slots=0)
     assert L.tpc_workspace_bytes(ctypes.byref(bad)) == 0
     bad = default_params(s_max=1.5)
@@ -117,6 +120,10 @@ def test_calls_rejected_before_device_work(L):
     assert L.tpc_track_event(ctx, 0) == _lib.TPC_ESTATE
     assert L.tpc_track_event(ctx, 3) == _lib.TPC_EINVAL
     assert L.tpc_track_sector(ctx, 0, 0) == _lib.TPC_ESTATE
+    assert L.tpc_track_event_streams(ctx, 0, 4) == _lib.TPC_ESTATE
+    assert L.tpc_track_event_streams(ctx, 0, 0) == _lib.TPC_EINVAL
+    assert L.tpc_track_event_streams(ctx, 0, 9) == _lib.TPC_EINVAL
+    assert L.tpc_track_event_streams(ctx, 2, 4) == _lib.TPC_EINVAL
     nt, nh = ctypes.c_int64(), ctypes.c_int64()
     assert L.tpc_get_tracks(ctx, 0, 0, None, 0, None, 0, ctypes.byref(nt),
                             ctypes.byref(nh)) == _lib.TPC_ESTATE

@@ -316,3 +316,54 @@ def test_serving_results_equal_alone(dev):
             assert np.array_equal(h, rh), (plain, i)
             for k in ("n_hits", "inner_id", "hit_off", "par", "cov", "chi2", "sector"):
                 assert np.array_equal(t[k], rt[k]), (plain, i, k)
+
+
+def test_autotune_grid_knobs_keep_tracks(dev):
+    """Every grid setting the autotuner tries gives the same tracks (the
+    tuner raises otherwise), including extreme bin sizes."""
+    from paper_1712_09416_amd.autotune import autotune
+    evs = [tpcgen.pbpb_event(tpcgen.seed_for(3, 900 + e), m) for e, m in enumerate([120, 700, 40])]
+    geo = evs[0].geometry()
+    offs = np.concatenate([[0], np.cumsum([e.n for e in evs])]).astype(np.int64)
+    cat = [torch.from_numpy(np.concatenate([getattr(e, k) for e in evs])).to(dev)
+           for k in ("sector", "row", "y", "z")]
+    cands = [(2.0, 2.0), (0.5, 0.5), (1.0, 3.0), (8.0, 1.0), (64.0, 10.0)]
+    res = autotune(geo, offs, *cat, candidates=cands, reps=1)
+    say(f"autotune: {res}")
+    assert res["best"] in cands and len(res["ms"]) == len(cands)
+
+
+def test_multi_stream_sectors_equal_fused(dev):
+    """Per-sector launch sequences spread over several streams (sectors in
+    flight together) give exactly the fused path's tracks, for a single
+    event and for a batch slot."""
+    from paper_1712_09416_amd import Tracker
+    ev = tpcgen.pbpb_event(tpcgen.seed_for(2) + 91, 1200)
+    geo = ev.geometry()
+    ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.sector, ev.row, ev.y, ev.z)]
+    trk = Tracker(geo, max_clusters=ev.n)
+    trk.load(0, *ins)
+    trk.track_event(0)
+    ref_t, ref_h = trk.get_tracks(0)
+    assert len(ref_t) > 100
+    for ns in (1, 3, 8):
+        trk.load(0, *ins)
+        trk.track_event_streams(0, ns)
+        t, h = trk.get_tracks(0)
+        assert np.array_equal(h, ref_h), ns
+        assert np.array_equal(t, ref_t), ns
+    trk.close()
+    evs = [tpcgen.pbpb_event(tpcgen.seed_for(3, 950 + e), m) for e, m in enumerate([300, 60, 900])]
+    offs = np.concatenate([[0], np.cumsum([e.n for e in evs])]).astype(np.int64)
+    cat = [torch.from_numpy(np.concatenate([getattr(e, k) for e in evs])).to(dev)
+           for k in ("sector", "row", "y", "z")]
+    trk = Tracker(geo, max_events=3, max_clusters=int(offs[-1]))
+    trk.load_batch(0, offs, *cat)
+    trk.track_event(0)
+    ref = [trk.get_tracks(0, e) for e in range(3)]
+    trk.load_batch(0, offs, *cat)
+    trk.track_event_streams(0, 4)
+    for e in range(3):
+        t, h = trk.get_tracks(0, e)
+        assert np.array_equal(h, ref[e][1]) and np.array_equal(t, ref[e][0]), e
+    trk.close()
