@@ -52,6 +52,14 @@ class Params(ctypes.Structure):
 
 # The oracle's own constants for the tracker (the values this project
 # adopted for a method the paper names without numbers).
+class MergeParams(ctypes.Structure):
+    _fields_ = [("chi2_max", ctypes.c_float), ("row_gap", ctypes.c_int32),
+                ("step_max", ctypes.c_float), ("passes", ctypes.c_int32),
+                ("s_max", ctypes.c_float)]
+
+
+DEFAULT_MERGE = dict(chi2_max=30.0, row_gap=12, step_max=2.0, passes=3, s_max=0.999)
+
 DEFAULT_PARAMS = dict(nf_window=3.0, nf_mmax=16.0, chi2_max=16.0, k_win=4.0, w_max=5.0,
                       s_max=0.95, c_s0=1.0, c_t0=1.0, c_q0=100.0, m_edge=1.0, m_z=1.0,
                       n_gap=6, n_min_tracklet=10, n_min_track=10)
@@ -92,6 +100,16 @@ def lib():
         L.orc_predict_d.argtypes = [P, P, f64, f64, f64]
         L.orc_update_f.argtypes = [P, P, f32, f32, f32, f32, f32, f32, ctypes.c_int, P]
         L.orc_update_d.argtypes = [P, P, f64, f64, f64, f64, f64, f64, ctypes.c_int, P]
+        L.orc_merge.restype = P
+        L.orc_merge.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(Params),
+                                ctypes.POINTER(MergeParams), P, ctypes.c_int64, P, P, P, P]
+        L.orc_merge_free.argtypes = [P]
+        for f in ("orc_merge_n_tracks", "orc_merge_n_hits"):
+            getattr(L, f).restype = ctypes.c_int64
+            getattr(L, f).argtypes = [P]
+        L.orc_merge_get.argtypes = [P, P, P, P, P, P, P, P]
+        L.orc_rotate_d.argtypes = [P, P, P, f64, f64, f64, f64]
+        L.orc_chi2_5.argtypes = [P, P, P]
         _lib = L
     return _lib
 
@@ -216,3 +234,68 @@ def update(p, C, my, mz, vy, vz, chi2max=16.0, smax=0.95, gated=True, precision=
 def curvature_b(bz_tesla: float) -> float:
     """b = -c Bz in cm^-1 per (c/GeV); d(phi)/dl = b * q/pT."""
     return -0.00299792458 * float(bz_tesla)
+
+
+# ---- cross-sector merger ------------------------------------------------------
+
+@dataclass
+class MergeResult:
+    tracks: np.ndarray        # TRACK_DTYPE, canonical order (merged and single)
+    hits: np.ndarray
+    n_segments: np.ndarray    # per output track
+    link_out: np.ndarray      # per input track: linked outer segment or -1
+    best_out: np.ndarray      # per input track: best outer candidate or -1
+    best_chi2: np.ndarray
+    merged_into: np.ndarray   # per input track: output track index
+
+    def track_hits(self, k: int) -> np.ndarray:
+        t = self.tracks[k]
+        return self.hits[t["hit_off"]: t["hit_off"] + t["n_hits"]]
+
+
+def merge(tracks, hits, row, y, z, geo: dict, params=None, **over) -> MergeResult:
+    """Join the track segments of one event across sector boundaries (input:
+    the tracks of `run` for that event, canonical order)."""
+    L = lib()
+    tracks = np.ascontiguousarray(tracks, TRACK_DTYPE)
+    hits = np.ascontiguousarray(hits, np.int32)
+    row = np.ascontiguousarray(row, np.uint8)
+    y = np.ascontiguousarray(y, np.float32)
+    z = np.ascontiguousarray(z, np.float32)
+    g = make_geometry(geo)
+    p = params if params is not None else make_params()
+    m = MergeParams()
+    d = dict(DEFAULT_MERGE)
+    d.update(over)
+    for k, v in d.items():
+        setattr(m, k, v)
+    n = len(tracks)
+    h = L.orc_merge(ctypes.byref(g), ctypes.byref(p), ctypes.byref(m), _ptr(tracks), n,
+                    _ptr(hits), _ptr(row), _ptr(y), _ptr(z))
+    try:
+        nt = L.orc_merge_n_tracks(h)
+        out = np.zeros(nt, TRACK_DTYPE)
+        oh = np.empty(L.orc_merge_n_hits(h), np.int32)
+        nseg = np.empty(nt, np.int32)
+        lo, bo, mi = (np.empty(n, np.int32) for _ in range(3))
+        bc = np.empty(n, np.float64)
+        L.orc_merge_get(h, _ptr(out), _ptr(oh), _ptr(nseg), _ptr(lo), _ptr(bo), _ptr(bc), _ptr(mi))
+        return MergeResult(out, oh, nseg, lo, bo, bc, mi)
+    finally:
+        L.orc_merge_free(h)
+
+
+def rotate(p, C, x, ca, sa, b, smax=0.95):
+    p = np.array(p, np.float64)
+    C = np.array(C, np.float64)
+    xx = np.array([x], np.float64)
+    ok = lib().orc_rotate_d(_ptr(p), _ptr(C), _ptr(xx), ca, sa, b, smax)
+    return bool(ok), p, C, float(xx[0])
+
+
+def chi2_5(S, d):
+    S = np.ascontiguousarray(S, np.float64)
+    d = np.ascontiguousarray(d, np.float64)
+    out = np.zeros(1, np.float64)
+    ok = lib().orc_chi2_5(_ptr(S), _ptr(d), _ptr(out))
+    return bool(ok), float(out[0])

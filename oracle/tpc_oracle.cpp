@@ -72,6 +72,16 @@ struct orc_track {
   int32_t tracklet;     // index into this sector's tracklet list (debug)
 };
 
+// Constants of the cross-sector merger.
+struct orc_merge_params {
+  float chi2_max;       // cut on the 5-parameter match chi2 of two segments
+  int32_t row_gap;      // largest pad-row distance between the segments
+  float step_max;       // longest transport step between frames (cm)
+  int32_t passes;       // inward refit passes of a merged track
+  float s_max;          // largest |sin phi| of the merger's transports (its
+                        // hits are already chosen, so this is no search cut)
+};
+
 }  // extern "C"
 
 namespace {
@@ -687,6 +697,413 @@ struct Sector {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Cross-sector merger.  A particle crossing the boundary between two
+// neighbouring sectors of one side leaves one track segment in each; the
+// per-sector tracker fits them separately.  The merger joins such segments
+// and refits the joined hit list across the sector frames.  The paper names
+// this step only as the continuation of the per-sector tracking; the
+// definition below is this project's:
+//  M1 every track's state at its outermost hit, from one outward Kalman pass
+//     over its hits seeded with its fitted parameters at the innermost hit
+//     and the prior covariance;
+//  M2 a pair (A, B) of tracks of one event, B in a neighbouring sector of
+//     A's side, with 0 < B.row_in - A.row_out <= row_gap, is compatible if
+//     A's outer state, turned into B's frame and transported to B's
+//     innermost row, matches B's fitted state: chi2 = d^T (C_A + C_B)^-1 d
+//     over the 5 parameters (Cholesky) <= chi2_max.  T and Q do not change
+//     under rotation or transport, and d_i^2 / S_ii never exceeds the full
+//     chi2, so pairs failing the cut on T or Q alone are skipped before any
+//     transport;
+//  M3 each A keeps its best B (smallest chi2, ties to the smaller track
+//     index) and each B its best A; a pair is linked if each is the other's
+//     best; links form chains inner -> outer;
+//  M4 every chain of two or more segments is refitted inward over all its
+//     hits (passes as in the per-sector refit: the first seeded with the
+//     outermost segment's outer state, each later one with the previous
+//     result carried out to the outermost hit), turning frames at the
+//     boundaries; a chain whose transport fails is left unmerged.  Output at
+//     the innermost hit, in the innermost segment's frame.
+// The frame of sector k is turned by 2 atan(tan_half_angle) from that of
+// sector k - 1; its cosine and sine are formed algebraically from the tangent.
+// All transports of the merger stop only beyond its own s_max.
+// ---------------------------------------------------------------------------
+
+// The state at x in one frame, expressed in the frame turned by the angle
+// with cosine ca and sine sa (the new x axis at azimuth +a): the point and
+// direction are unchanged, x' = x ca + y sa, y' = -x sa + y ca,
+// sin phi' = sin(phi - a).  The covariance is carried to the new x' along
+// the track: J(y', y) = ca - sa tan phi', J(z', y) = -sa T / cos phi',
+// J(s', y) = -b Q sa, J(s', s) = cos phi' / cos phi.  Returns false if
+// |sin phi'| would exceed s_max.
+template <class T>
+bool rotate(State<T>& st, T& x, T ca, T sa, T b, T smax) {
+  const T y = st.p[0], s = st.p[2], tl = st.p[3], q = st.p[4];
+  const T c = tsqrt(T(1) - s * s);
+  const T s1 = s * ca - c * sa;
+  if (!(tabs(s1) <= smax)) return false;
+  const T c1 = tsqrt(T(1) - s1 * s1);
+  const T x1 = x * ca + y * sa;
+  const T y1 = -x * sa + y * ca;
+  T J[5][5] = {};
+  for (int i = 0; i < 5; ++i) J[i][i] = T(1);
+  J[0][0] = ca - sa * (s1 / c1);
+  J[1][0] = -sa * tl / c1;
+  J[2][0] = -(b * q) * sa;
+  J[2][2] = c1 / c;
+  T Cf[5][5];
+  for (int i = 0, k = 0; i < 5; ++i)
+    for (int j = 0; j <= i; ++j, ++k) Cf[i][j] = Cf[j][i] = st.C[k];
+  T A[5][5];
+  for (int i = 0; i < 5; ++i)
+    for (int l = 0; l < 5; ++l) {
+      T a = T(0);
+      for (int k = 0; k < 5; ++k) a = a + J[i][k] * Cf[k][l];
+      A[i][l] = a;
+    }
+  for (int i = 0, k = 0; i < 5; ++i)
+    for (int j = 0; j <= i; ++j, ++k) {
+      T v = T(0);
+      for (int l = 0; l < 5; ++l) v = v + A[i][l] * J[j][l];
+      st.C[k] = v;
+    }
+  st.p[0] = y1;
+  st.p[2] = s1;
+  x = x1;
+  return true;
+}
+
+// Transport from x to xt in equal steps no longer than step_max.
+template <class T>
+bool transport_to(State<T>& st, T x, T xt, T b, T smax, T step_max) {
+  const T d = xt - x;
+  const int n = std::max(1, int(std::ceil(tabs(d) / step_max)));
+  const T dx = d / T(n);
+  for (int i = 0; i < n; ++i)
+    if (!predict(st, dx, b, smax)) return false;
+  return true;
+}
+
+// chi2 = d^T S^-1 d for a symmetric positive definite S (lower triangle,
+// packed like C), by Cholesky.  Returns false if S is not positive definite.
+template <class T>
+bool chi2_5(const T* S, const T* d, T& chi2) {
+  T L[5][5] = {};
+  for (int i = 0, k = 0; i < 5; ++i)
+    for (int j = 0; j <= i; ++j, ++k) L[i][j] = S[k];
+  for (int j = 0; j < 5; ++j) {
+    T v = L[j][j];
+    for (int k = 0; k < j; ++k) v = v - L[j][k] * L[j][k];
+    if (!(v > T(0))) return false;
+    const T ljj = tsqrt(v);
+    L[j][j] = ljj;
+    for (int i = j + 1; i < 5; ++i) {
+      T w = L[i][j];
+      for (int k = 0; k < j; ++k) w = w - L[i][k] * L[j][k];
+      L[i][j] = w / ljj;
+    }
+  }
+  T yv[5];
+  T sum = T(0);
+  for (int i = 0; i < 5; ++i) {
+    T w = d[i];
+    for (int k = 0; k < i; ++k) w = w - L[i][k] * yv[k];
+    yv[i] = w / L[i][i];
+    sum = sum + yv[i] * yv[i];
+  }
+  chi2 = sum;
+  return true;
+}
+
+struct MergeIn {
+  const orc_track* tracks;   // one event's tracks, canonical order
+  int64_t n_tracks;
+  const int32_t* hits;       // hit IDs, hit_off into this
+  const uint8_t* row;        // pad row of each cluster ID
+  const float* Y;
+  const float* Z;
+};
+
+struct MergeOut {
+  std::vector<orc_track> tracks;     // canonical order
+  std::vector<int32_t> hits;
+  std::vector<int32_t> n_segments;
+  std::vector<int32_t> link_out;     // per input track: linked outer segment or -1
+  std::vector<double> best_chi2;     // per input track: chi2 of its best outer partner
+  std::vector<int32_t> best_out;     // per input track: best outer partner or -1
+  std::vector<int32_t> merged_into;  // per input track: output track index
+};
+
+struct Merger {
+  Ctx<double> c;
+  orc_merge_params M;
+  double ca, sa;          // rotation between neighbouring sectors
+  const MergeIn& in;
+
+  Merger(const orc_geometry* g, const orc_params* P, const orc_merge_params* m, const MergeIn& i)
+      : M(*m), in(i) {
+    init_ctx(c, g, P);
+    c.smax = double(m->s_max);
+    const double t = double(g->tan_half_angle);
+    ca = (1.0 - t * t) / (1.0 + t * t);
+    sa = (2.0 * t) / (1.0 + t * t);
+  }
+
+  void prior(State<double>& st, double zv) const {
+    for (int i = 0; i < 15; ++i) st.C[i] = 0.0;
+    const double sy = sig_y(c, zv), sz = sig_z(c, zv);
+    st.C[0] = sy * sy;
+    st.C[2] = sz * sz;
+    st.C[5] = c.cs0;
+    st.C[9] = c.ct0;
+    st.C[14] = c.cq0;
+  }
+
+  // M1
+  bool outer_state(const orc_track& t, State<double>& st) const {
+    for (int i = 0; i < 5; ++i) st.p[i] = t.par[i];
+    prior(st, st.p[1]);
+    const int32_t* h = in.hits + t.hit_off;
+    int k = 1;
+    for (int r = t.row_in + 1; r <= t.row_out; ++r) {
+      if (!predict(st, c.X[r] - c.X[r - 1], c.b, c.smax)) return false;
+      if (k < t.n_hits && int(in.row[h[k]]) == r) {
+        const double sy = sig_y(c, st.p[1]), sz = sig_z(c, st.p[1]);
+        update(st, double(in.Y[h[k]]), double(in.Z[h[k]]), sy * sy, sz * sz, c.chi2max, c.smax,
+               false, (double*)nullptr);
+        ++k;
+      }
+    }
+    return true;
+  }
+
+  // +1 if sector b follows a counter-clockwise (frame turned by +a), -1 if
+  // it precedes it, 0 if not neighbours on the same side.
+  static int neighbour(int a, int b) {
+    if (a / 18 != b / 18) return 0;
+    const int ka = a % 18, kb = b % 18;
+    if (kb == (ka + 1) % 18) return 1;
+    if (ka == (kb + 1) % 18) return -1;
+    return 0;
+  }
+
+  // M2: chi2 of the pair (outer state of A, track B), false if incompatible
+  bool pair_chi2(const orc_track& A, const State<double>& outA, const orc_track& B,
+                 double& chi2) const {
+    const int dir = neighbour(A.sector, B.sector);
+    if (dir == 0) return false;
+    if (!(B.row_in > A.row_out && B.row_in - A.row_out <= M.row_gap)) return false;
+    const double cut = double(M.chi2_max);
+    const double dT = outA.p[3] - B.par[3], dQ = outA.p[4] - B.par[4];
+    if (dT * dT > cut * (outA.C[9] + B.cov[9])) return false;
+    if (dQ * dQ > cut * (outA.C[14] + B.cov[14])) return false;
+    State<double> st = outA;
+    double x = c.X[A.row_out];
+    if (!rotate(st, x, ca, double(dir) * sa, c.b, c.smax)) return false;
+    if (!transport_to(st, x, c.X[B.row_in], c.b, c.smax, double(M.step_max))) return false;
+    double d[5], S[15];
+    for (int i = 0; i < 5; ++i) d[i] = st.p[i] - B.par[i];
+    for (int i = 0; i < 15; ++i) S[i] = st.C[i] + B.cov[i];
+    if (!chi2_5(S, d, chi2)) return false;
+    return chi2 <= cut;
+  }
+
+  struct Seg {
+    int sector;
+    std::vector<int32_t> hits;   // ascending rows
+  };
+
+  // One inward pass over the chain (segments inner -> outer) seeded with
+  // (s, T, Q) at the outermost hit.
+  bool chain_pass(const std::vector<Seg>& segs, double s0, double t0, double q0,
+                  State<double>& out, double& chi2, int& n) const {
+    const Seg& last = segs.back();
+    const int32_t ho = last.hits.back();
+    State<double> st;
+    st.p[0] = double(in.Y[ho]);
+    st.p[1] = double(in.Z[ho]);
+    st.p[2] = s0;
+    st.p[3] = t0;
+    st.p[4] = q0;
+    prior(st, st.p[1]);
+    chi2 = 0.0;
+    n = 1;
+    int cur_row = in.row[ho];
+    for (int j = int(segs.size()) - 1; j >= 0; --j) {
+      const Seg& sg = segs[j];
+      int k = int(sg.hits.size()) - 1;
+      if (j == int(segs.size()) - 1) {
+        --k;                                  // the outermost hit seeded the pass
+      } else {
+        const int dir = neighbour(sg.sector, segs[j + 1].sector);
+        double x = c.X[cur_row];
+        if (!rotate(st, x, ca, -double(dir) * sa, c.b, c.smax)) return false;
+        const int r = in.row[sg.hits[k]];
+        if (!transport_to(st, x, c.X[r], c.b, c.smax, double(M.step_max))) return false;
+        const double sy = sig_y(c, st.p[1]), sz = sig_z(c, st.p[1]);
+        double ch = 0.0;
+        update(st, double(in.Y[sg.hits[k]]), double(in.Z[sg.hits[k]]), sy * sy, sz * sz,
+               c.chi2max, c.smax, false, &ch);
+        chi2 += ch;
+        ++n;
+        cur_row = r;
+        --k;
+      }
+      for (; k >= 0; --k) {
+        const int32_t h = sg.hits[k];
+        const int r = in.row[h];
+        for (int rr = cur_row - 1; rr >= r; --rr)
+          if (!predict(st, c.X[rr] - c.X[rr + 1], c.b, c.smax)) return false;
+        const double sy = sig_y(c, st.p[1]), sz = sig_z(c, st.p[1]);
+        double ch = 0.0;
+        update(st, double(in.Y[h]), double(in.Z[h]), sy * sy, sz * sz, c.chi2max, c.smax, false,
+               &ch);
+        chi2 += ch;
+        ++n;
+        cur_row = r;
+      }
+    }
+    out = st;
+    return true;
+  }
+
+  // Carry the inner result of a pass out to the outermost hit (parameters
+  // only matter: the next pass resets the covariance).
+  bool carry_out(const std::vector<Seg>& segs, State<double> st, double& s0, double& t0,
+                 double& q0) const {
+    double x = c.X[in.row[segs[0].hits.front()]];
+    for (size_t j = 0; j < segs.size(); ++j) {
+      const double xo = c.X[in.row[segs[j].hits.back()]];
+      if (!transport_to(st, x, xo, c.b, c.smax, double(M.step_max))) return false;
+      x = xo;
+      if (j + 1 < segs.size()) {
+        const int dir = neighbour(segs[j].sector, segs[j + 1].sector);
+        if (!rotate(st, x, ca, double(dir) * sa, c.b, c.smax)) return false;
+      }
+    }
+    s0 = st.p[2];
+    t0 = st.p[3];
+    q0 = st.p[4];
+    return true;
+  }
+
+  void run(MergeOut& o) const {
+    const int64_t n = in.n_tracks;
+    std::vector<State<double>> outer(n);
+    std::vector<char> ok(n, 0);
+    for (int64_t i = 0; i < n; ++i) ok[i] = outer_state(in.tracks[i], outer[i]) ? 1 : 0;
+    // M2 + M3: best partners both ways
+    std::vector<int32_t> best_out(n, -1), best_in(n, -1);
+    std::vector<double> chi_out(n, 0.0), chi_in(n, 0.0);
+    std::vector<std::vector<int32_t>> by_sector(36);
+    for (int64_t i = 0; i < n; ++i) by_sector[in.tracks[i].sector].push_back(int32_t(i));
+    for (int64_t a = 0; a < n; ++a) {
+      if (!ok[a]) continue;
+      const int sa_ = in.tracks[a].sector;
+      const int side = sa_ / 18, k = sa_ % 18;
+      for (int nbk : {(k + 1) % 18, (k + 17) % 18}) {
+        for (int32_t bi : by_sector[side * 18 + nbk]) {
+          double ch;
+          if (!pair_chi2(in.tracks[a], outer[a], in.tracks[bi], ch)) continue;
+          if (best_out[a] < 0 || ch < chi_out[a] || (ch == chi_out[a] && bi < best_out[a])) {
+            best_out[a] = bi;
+            chi_out[a] = ch;
+          }
+          if (best_in[bi] < 0 || ch < chi_in[bi] || (ch == chi_in[bi] && a < best_in[bi])) {
+            best_in[bi] = int32_t(a);
+            chi_in[bi] = ch;
+          }
+        }
+      }
+    }
+    o.best_out = best_out;
+    o.best_chi2 = chi_out;
+    o.link_out.assign(n, -1);
+    std::vector<int32_t> link_in(n, -1);
+    for (int64_t a = 0; a < n; ++a) {
+      const int32_t bi = best_out[a];
+      if (bi >= 0 && best_in[bi] == a) {
+        o.link_out[a] = bi;
+        link_in[bi] = int32_t(a);
+      }
+    }
+    // M4: chains from their innermost segment
+    struct Out {
+      orc_track t;
+      std::vector<int32_t> hits;
+      int32_t nseg;
+      std::vector<int32_t> members;
+    };
+    std::vector<Out> outs;
+    std::vector<char> used(n, 0);
+    for (int64_t a = 0; a < n; ++a) {
+      if (link_in[a] >= 0) continue;            // not a chain head
+      std::vector<int32_t> chain{int32_t(a)};
+      while (o.link_out[chain.back()] >= 0) chain.push_back(o.link_out[chain.back()]);
+      bool merged = false;
+      Out m;
+      if (chain.size() > 1) {
+        std::vector<Seg> segs;
+        for (int32_t k : chain) {
+          const orc_track& t = in.tracks[k];
+          segs.push_back({t.sector, std::vector<int32_t>(in.hits + t.hit_off,
+                                                         in.hits + t.hit_off + t.n_hits)});
+        }
+        const State<double>& so = outer[chain.back()];
+        double s0 = so.p[2], t0 = so.p[3], q0 = so.p[4];
+        State<double> res;
+        double chi2 = 0.0;
+        int nh = 0;
+        bool good = true;
+        for (int pass = 0; pass < M.passes && good; ++pass) {
+          if (pass > 0) good = carry_out(segs, res, s0, t0, q0);
+          if (good) good = chain_pass(segs, s0, t0, q0, res, chi2, nh);
+        }
+        if (good) {
+          const orc_track& t0r = in.tracks[chain.front()];
+          const orc_track& tl = in.tracks[chain.back()];
+          m.t = t0r;
+          m.t.n_hits = nh;
+          m.t.row_out = tl.row_out;
+          for (int i = 0; i < 5; ++i) m.t.par[i] = res.p[i];
+          for (int i = 0; i < 15; ++i) m.t.cov[i] = res.C[i];
+          m.t.chi2 = chi2;
+          m.t.ndf = 2 * nh - 5;
+          for (const Seg& sg : segs) m.hits.insert(m.hits.end(), sg.hits.begin(), sg.hits.end());
+          m.nseg = int32_t(chain.size());
+          m.members = chain;
+          outs.push_back(std::move(m));
+          merged = true;
+        }
+      }
+      if (!merged) {
+        for (int32_t k : chain) {
+          Out u;
+          u.t = in.tracks[k];
+          u.hits.assign(in.hits + u.t.hit_off, in.hits + u.t.hit_off + u.t.n_hits);
+          u.nseg = 1;
+          u.members = {k};
+          outs.push_back(std::move(u));
+        }
+      }
+    }
+    std::sort(outs.begin(), outs.end(),
+              [](const Out& x, const Out& y) { return x.t.inner_id < y.t.inner_id; });
+    o.tracks.clear();
+    o.hits.clear();
+    o.n_segments.clear();
+    o.merged_into.assign(n, -1);
+    for (size_t i = 0; i < outs.size(); ++i) {
+      Out& u = outs[i];
+      u.t.hit_off = int64_t(o.hits.size());
+      o.hits.insert(o.hits.end(), u.hits.begin(), u.hits.end());
+      o.tracks.push_back(u.t);
+      o.n_segments.push_back(u.nseg);
+      for (int32_t k : u.members) o.merged_into[k] = int32_t(i);
+    }
+  }
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -935,6 +1352,55 @@ void orc_get_tracklets(void* h, int sector, int32_t* info /* [n,6] */, uint32_t*
     std::memcpy(uhit + 159 * i, v[i].uhit, 159 * 4);
     std::memcpy(dhit + 159 * i, v[i].dhit, 159 * 4);
   }
+}
+
+// Cross-sector merger of one event's tracks (canonical order, hit IDs
+// into hit_ids; row / y / z indexed by cluster ID).
+void* orc_merge(const orc_geometry* g, const orc_params* P, const orc_merge_params* M,
+                const orc_track* tracks, int64_t n_tracks, const int32_t* hit_ids,
+                const uint8_t* row, const float* y, const float* z) {
+  MergeIn in{tracks, n_tracks, hit_ids, row, y, z};
+  MergeOut* o = new MergeOut();
+  Merger m(g, P, M, in);
+  m.run(*o);
+  return o;
+}
+
+void orc_merge_free(void* h) { delete static_cast<MergeOut*>(h); }
+int64_t orc_merge_n_tracks(void* h) { return int64_t(static_cast<MergeOut*>(h)->tracks.size()); }
+int64_t orc_merge_n_hits(void* h) { return int64_t(static_cast<MergeOut*>(h)->hits.size()); }
+
+// Merged tracks (canonical order) and hit IDs; per input track, the linked
+// outer segment, the best outer candidate, its chi2 and the output track
+// it went into.
+void orc_merge_get(void* h, orc_track* out, int32_t* hit_ids, int32_t* n_segments,
+                   int32_t* link_out, int32_t* best_out, double* best_chi2,
+                   int32_t* merged_into) {
+  MergeOut* o = static_cast<MergeOut*>(h);
+  std::memcpy(out, o->tracks.data(), o->tracks.size() * sizeof(orc_track));
+  std::memcpy(hit_ids, o->hits.data(), o->hits.size() * 4);
+  std::memcpy(n_segments, o->n_segments.data(), o->n_segments.size() * 4);
+  const size_t n = o->link_out.size();
+  std::memcpy(link_out, o->link_out.data(), n * 4);
+  std::memcpy(best_out, o->best_out.data(), n * 4);
+  std::memcpy(best_chi2, o->best_chi2.data(), n * 8);
+  std::memcpy(merged_into, o->merged_into.data(), n * 4);
+}
+
+// Frame rotation of one double state (pins): x in/out; returns 0 if refused.
+int orc_rotate_d(double* p, double* C, double* x, double ca, double sa, double b, double smax) {
+  State<double> st;
+  std::memcpy(st.p, p, 40);
+  std::memcpy(st.C, C, 120);
+  if (!rotate(st, *x, ca, sa, b, smax)) return 0;
+  std::memcpy(p, st.p, 40);
+  std::memcpy(C, st.C, 120);
+  return 1;
+}
+
+// Cholesky chi2 of a 5-vector (pins): returns 0 if S is not positive definite.
+int orc_chi2_5(const double* S, const double* d, double* chi2) {
+  return chi2_5(S, d, *chi2) ? 1 : 0;
 }
 
 // Single steps, for the pins of the Kalman primitives.  p[5], C[15] in/out.
