@@ -206,6 +206,53 @@ int tpc_get_links(tpc_ctx* ctx, int slot, int event, int32_t* up, int32_t* dn, i
 int tpc_kf_step_f32(tpc_ctx* ctx, float* state, const float* dx, const float* meas,
                     float* result, int64_t n);
 
+/* Constants of the cross-sector merger. */
+typedef struct tpc_merge_params {
+  float chi2_max;           /* cut on the 5-parameter match chi2 of two segments */
+  int32_t row_gap;          /* largest pad-row distance between the segments */
+  float step_max;           /* longest transport step between sector frames (cm, >= 0.1) */
+  int32_t passes;           /* inward refit passes of a merged track (1..8) */
+  float s_max;              /* largest |sin phi| of the merger's transports (< 1) */
+} tpc_merge_params;
+
+/* Defaults: chi2_max 30, row_gap 12, step_max 2 cm, passes 3, s_max 0.999. */
+int tpc_merge_params_default(tpc_merge_params* m);
+
+/* Join track segments across sector boundaries, for every event of a
+ * tracked slot (the step after the per-sector tracking: a particle crossing
+ * from one sector into its neighbour on the same side leaves one segment in
+ * each).  Per track, the state at its outermost hit (an outward Kalman pass
+ * seeded with its fitted parameters); each pair (A, B), B in a neighbouring
+ * sector with 0 < B.row_in - A.row_out <= row_gap, is compared after
+ * turning A's outer state into B's frame (sectors are 2 atan(tan_half_angle)
+ * apart) and transporting it to B's innermost row: chi2 of the 5-parameter
+ * difference with covariance C_A + C_B, kept if <= chi2_max; A and B are
+ * linked when each is the other's smallest-chi2 partner (ties to the
+ * smaller track index); each chain of linked segments is refitted inward
+ * over all its hits in `passes` passes, turning frames at the boundaries,
+ * and replaces its segments (a chain whose refit fails stays as segments).
+ * The merged track keeps its innermost segment's sector, frame, inner hit
+ * and canonical position.  Asynchronous on the context stream; read with
+ * tpc_get_merged.  Errors: TPC_EINVAL (bad parameters), TPC_ESTATE (slot
+ * not tracked, or during graph capture), TPC_EDEVICE. */
+int tpc_merge(tpc_ctx* ctx, int slot, const tpc_merge_params* m);
+
+/* Like tpc_get_tracks, for the merger's output of one event; n_segments
+ * (may be NULL) receives the number of segments of each track.
+ * Synchronises.  Errors: TPC_EINVAL, TPC_ESTATE (not merged since the last
+ * staging), TPC_EOVERFLOW (buffers too small; counts filled in). */
+int tpc_get_merged(tpc_ctx* ctx, int slot, int event, tpc_track* out, int64_t max_tracks,
+                   int32_t* hit_ids, int64_t max_hits, int32_t* n_segments, int64_t* n_tracks,
+                   int64_t* n_hits);
+
+/* Merger diagnostics of one event, per track of tpc_get_tracks' list (host
+ * arrays of that length, each may be NULL): the linked outer segment, the
+ * best outer candidate (-1 none), its chi2, and the index of the
+ * tpc_get_merged track the track went into.  Synchronises.  Errors:
+ * TPC_EINVAL, TPC_ESTATE. */
+int tpc_get_merge_links(tpc_ctx* ctx, int slot, int event, int32_t* link_out, int32_t* best_out,
+                        double* best_chi2, int32_t* merged_into);
+
 /* Record into a HIP graph, without running it, the whole sequence
  * tpc_track_event would enqueue for the slot as currently staged (grid,
  * finding, fitting, ordering; kernels only, no memset or copy nodes).  The

@@ -722,7 +722,8 @@ struct Sector {
 //     hits (passes as in the per-sector refit: the first seeded with the
 //     outermost segment's outer state, each later one with the previous
 //     result carried out to the outermost hit), turning frames at the
-//     boundaries; a chain whose transport fails is left unmerged.  Output at
+//     boundaries; a chain whose transport fails (or whose outermost segment
+//     has no outer state) is left unmerged.  Output at
 //     the innermost hit, in the innermost segment's frame.
 // The frame of sector k is turned by 2 atan(tan_half_angle) from that of
 // sector k - 1; its cosine and sine are formed algebraically from the tangent.
@@ -773,10 +774,12 @@ bool rotate(State<T>& st, T& x, T ca, T sa, T b, T smax) {
   return true;
 }
 
-// Transport from x to xt in equal steps no longer than step_max.
+// Transport from x to xt in equal steps no longer than step_max (refused
+// beyond 1000 cm: no path inside the chamber is that long).
 template <class T>
 bool transport_to(State<T>& st, T x, T xt, T b, T smax, T step_max) {
   const T d = xt - x;
+  if (!(tabs(d) <= T(1000))) return false;
   const int n = std::max(1, int(std::ceil(tabs(d) / step_max)));
   const T dx = d / T(n);
   for (int i = 0; i < n; ++i)
@@ -1054,7 +1057,7 @@ struct Merger {
         State<double> res;
         double chi2 = 0.0;
         int nh = 0;
-        bool good = true;
+        bool good = ok[chain.back()] != 0;     // the seed must exist
         for (int pass = 0; pass < M.passes && good; ++pass) {
           if (pass > 0) good = carry_out(segs, res, s0, t0, q0);
           if (good) good = chain_pass(segs, s0, t0, q0, res, chi2, nh);

@@ -20,6 +20,7 @@ EXPORTS = ("tpc_params_default", "tpc_workspace_bytes", "tpc_init_geometry", "tp
            "tpc_get_tracks",
            "tpc_device_results", "tpc_get_links", "tpc_kf_step_f32", "tpc_graph_capture",
            "tpc_graph_launch", "tpc_poll", "tpc_set_profiling", "tpc_get_profile",
+           "tpc_merge_params_default", "tpc_merge", "tpc_get_merged", "tpc_get_merge_links",
            "tpc_last_error", "tpc_destroy")
 STAGES = ("grid", "neighbours", "clean_starts", "tracklets", "weights_select", "refit", "output")
 
@@ -42,6 +43,12 @@ class Params(ctypes.Structure):
                 ("n_min_track", ctypes.c_int32), ("bin_target", ctypes.c_float),
                 ("bin_min_edge", ctypes.c_float), ("max_slots", ctypes.c_int32),
                 ("max_events", ctypes.c_int32), ("max_clusters", ctypes.c_int64)]
+
+
+class MergeParams(ctypes.Structure):
+    _fields_ = [("chi2_max", ctypes.c_float), ("row_gap", ctypes.c_int32),
+                ("step_max", ctypes.c_float), ("passes", ctypes.c_int32),
+                ("s_max", ctypes.c_float)]
 
 
 TRACK_DTYPE = np.dtype([("event", "<i4"), ("sector", "<i4"), ("n_hits", "<i4"),
@@ -87,6 +94,10 @@ def load() -> ctypes.CDLL:
     L.tpc_poll.argtypes = [P, I]
     L.tpc_set_profiling.argtypes = [P, I]
     L.tpc_get_profile.argtypes = [P, P, P]
+    L.tpc_merge_params_default.argtypes = [ctypes.POINTER(MergeParams)]
+    L.tpc_merge.argtypes = [P, I, ctypes.POINTER(MergeParams)]
+    L.tpc_get_merged.argtypes = [P, I, I, P, I64, P, I64, P, P, P]
+    L.tpc_get_merge_links.argtypes = [P, I, I, P, P, P, P]
     L.tpc_last_error.restype = ctypes.c_char_p
     L.tpc_last_error.argtypes = [P]
     L.tpc_destroy.argtypes = [P]

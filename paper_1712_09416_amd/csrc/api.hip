@@ -26,6 +26,8 @@ struct SlotHost {
   hipGraphExec_t graph = nullptr;     // captured tracking sequence
   std::vector<int64_t> graph_ev_off;  // staged shape the graph was captured with
   const void* graph_in[4] = {};
+  MergeSlot m{};                      // cross-sector merger buffers
+  bool merged = false;                // merger output valid for the staged data
   uint8_t* own_sector = nullptr;
   uint8_t* own_row = nullptr;
   float* own_y = nullptr;
@@ -165,6 +167,34 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   s.ev_hit_off = c.take<uint32_t>(E + 1);
   s.err = c.take<uint32_t>(4);
   s.stats = c.take<unsigned long long>(8);
+  MergeSlot m;
+  m.sec_cnt = c.take<uint32_t>(S + 1);
+  m.sec_cur = c.take<uint32_t>(S);
+  m.sec_list = c.take<int32_t>(cap_tk);
+  m.op = c.take<double>(cap_tk * 5);
+  m.oc = c.take<double>(cap_tk * 15);
+  m.ok = c.take<int32_t>(cap_tk);
+  m.best_out = c.take<int32_t>(cap_tk);
+  m.chi_out = c.take<double>(cap_tk);
+  m.best_in = c.take<int32_t>(cap_tk);
+  m.chi_in = c.take<double>(cap_tk);
+  m.link_out = c.take<int32_t>(cap_tk);
+  m.link_in = c.take<int32_t>(cap_tk);
+  m.head_ok = c.take<int32_t>(cap_tk);
+  m.nseg = c.take<int32_t>(cap_tk);
+  m.nfit = c.take<int32_t>(cap_tk);
+  m.par = c.take<double>(cap_tk * 5);
+  m.cov = c.take<double>(cap_tk * 15);
+  m.chi2 = c.take<double>(cap_tk);
+  m.emit = c.take<uint32_t>(cap_tk + 1);
+  m.nh = c.take<uint32_t>(cap_tk + 1);
+  m.into = c.take<int32_t>(cap_tk);
+  m.tracks = c.take<tpc_track>(cap_tk);
+  m.hits = c.take<int32_t>(N);
+  m.out_nseg = c.take<int32_t>(cap_tk);
+  m.ev_track_off = c.take<uint32_t>(E + 1);
+  m.ev_hit_off = c.take<uint32_t>(E + 1);
+  if (h) h->m = m;
   s.cap_n = N;
   s.cap_tl = cap_tl;
   s.cap_tk = cap_tk;
@@ -379,6 +409,7 @@ int stage(tpc_ctx* ctx, int slot, int n_events, const int64_t* offs, const uint8
   hipStream_t st = ctx->stream;
   h.n = n;
   h.n_events = n_events;
+  h.merged = false;
   h.ev_off.assign(offs, offs + n_events + 1);
   s.n = n;
   s.n_events = n_events;
@@ -602,6 +633,125 @@ int tpc_track_event_streams(tpc_ctx* ctx, int slot, int n_streams) {
   const int rc = finalize(ctx, h);
   if (rc) return rc;
   return record_done(ctx, h);
+}
+
+int tpc_merge_params_default(tpc_merge_params* m) {
+  if (!m) return TPC_EINVAL;
+  m->chi2_max = 30.0f;
+  m->row_gap = 12;
+  m->step_max = 2.0f;
+  m->passes = 3;
+  m->s_max = 0.999f;
+  return TPC_OK;
+}
+
+int tpc_merge(tpc_ctx* ctx, int slot, const tpc_merge_params* mp) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  if (!mp || !(mp->chi2_max > 0.0f) || mp->row_gap < 1 || !(mp->step_max >= 0.1f) ||
+      mp->passes < 1 || mp->passes > 8 || !(mp->s_max > 0.0f && mp->s_max < 1.0f))
+    return ctx->fail(TPC_EINVAL, "bad merge parameters");
+  if (ctx->capturing) return ctx->fail(TPC_ESTATE, "not available under capture");
+  SlotHost& h = ctx->slots[slot];
+  if (h.state == 3) {
+    const int rc = finalize(ctx, h);
+    if (rc) return rc;
+  }
+  if (h.state != 4) return ctx->fail(TPC_ESTATE, "slot not tracked");
+  MergeConst C;
+  const double t = (double)ctx->g.tan_half_angle;
+  C.ca = (1.0 - t * t) / (1.0 + t * t);
+  C.sa = (2.0 * t) / (1.0 + t * t);
+  C.chi2_max = (double)mp->chi2_max;
+  C.step_max = (double)mp->step_max;
+  C.smax = (double)mp->s_max;
+  C.row_gap = mp->row_gap;
+  C.passes = mp->passes;
+  Slot& s = h.d;
+  MergeSlot& m = h.m;
+  hipStream_t st = ctx->stream;
+  const int64_t K = s.cap_tk;
+  const int64_t ns = s.n_sectors;
+  const int nbt = grid_stride_blocks(K, 64, 8192);
+  const int nb = grid_stride_blocks(K, 256);
+  k_zero_u32<<<grid_stride_blocks(ns + 1, 256), 256, 0, st>>>(m.sec_cnt, ns + 1);
+  k_zero_u32<<<grid_stride_blocks(ns, 256), 256, 0, st>>>(m.sec_cur, ns);
+  k_fill_i32<<<nb, 256, 0, st>>>(m.link_in, K, -1);
+  k_mg_count<<<nb, 256, 0, st>>>(s, m);
+  scan_u32(st, m.sec_cnt, nullptr, ns, s.scan_b, nullptr);
+  k_mg_scatter<<<nb, 256, 0, st>>>(s, m);
+  k_mg_outer<<<nbt, 64, 0, st>>>(s, ctx->k, m, C);
+  k_mg_best_out<<<nbt, 64, 0, st>>>(s, ctx->k, m, C);
+  k_mg_best_in<<<nbt, 64, 0, st>>>(s, ctx->k, m, C);
+  k_mg_link<<<nb, 256, 0, st>>>(s, m);
+  k_mg_chain<<<nbt, 64, 0, st>>>(s, ctx->k, m, C);
+  k_mg_emit<<<nb, 256, 0, st>>>(s, m);
+  scan_u32(st, m.emit, s.out_count, K, s.scan_b, nullptr);
+  scan_u32(st, m.nh, s.out_count, K, s.scan_b, nullptr);
+  k_mg_event_off<<<(h.n_events + 1 + 255) / 256, 256, 0, st>>>(s, m);
+  k_mg_write<<<nbt, 64, 0, st>>>(s, ctx->k, m);
+  TPC_LAUNCHED();
+  h.merged = true;
+  return record_done(ctx, h);
+}
+
+int tpc_get_merged(tpc_ctx* ctx, int slot, int event, tpc_track* out, int64_t max_tracks,
+                   int32_t* hit_ids, int64_t max_hits, int32_t* n_segments, int64_t* n_tracks,
+                   int64_t* n_hits) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  SlotHost& h = ctx->slots[slot];
+  if (event < 0 || event >= std::max(1, h.n_events)) return ctx->fail(TPC_EINVAL, "event out of range");
+  if (max_tracks < 0 || max_hits < 0) return ctx->fail(TPC_EINVAL, "negative buffer size");
+  if ((max_tracks > 0 && !out) || (max_hits > 0 && !hit_ids))
+    return ctx->fail(TPC_EINVAL, "null output buffer");
+  if (!h.merged || h.state != 4) return ctx->fail(TPC_ESTATE, "slot not merged");
+  hipStream_t st = ctx->stream;
+  uint32_t toff[2], hoff[2];
+  TPC_HIP(hipMemcpyAsync(toff, h.m.ev_track_off + event, sizeof(toff), hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipMemcpyAsync(hoff, h.m.ev_hit_off + event, sizeof(hoff), hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipStreamSynchronize(st));
+  const int64_t nt = (int64_t)toff[1] - toff[0];
+  const int64_t nh = (int64_t)hoff[1] - hoff[0];
+  if (n_tracks) *n_tracks = nt;
+  if (n_hits) *n_hits = nh;
+  if (nt > max_tracks || nh > max_hits) return ctx->fail(TPC_EOVERFLOW, "output buffers too small");
+  if (nt) TPC_HIP(hipMemcpyAsync(out, h.m.tracks + toff[0], nt * sizeof(tpc_track), hipMemcpyDeviceToHost, st));
+  if (nt && n_segments)
+    TPC_HIP(hipMemcpyAsync(n_segments, h.m.out_nseg + toff[0], nt * 4, hipMemcpyDeviceToHost, st));
+  if (nh) TPC_HIP(hipMemcpyAsync(hit_ids, h.m.hits + hoff[0], nh * 4, hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipStreamSynchronize(st));
+  return TPC_OK;
+}
+
+int tpc_get_merge_links(tpc_ctx* ctx, int slot, int event, int32_t* link_out, int32_t* best_out,
+                        double* best_chi2, int32_t* merged_into) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  SlotHost& h = ctx->slots[slot];
+  if (event < 0 || event >= std::max(1, h.n_events)) return ctx->fail(TPC_EINVAL, "event out of range");
+  if (!h.merged || h.state != 4) return ctx->fail(TPC_ESTATE, "slot not merged");
+  hipStream_t st = ctx->stream;
+  uint32_t toff[2], moff = 0;
+  TPC_HIP(hipMemcpyAsync(toff, h.d.ev_track_off + event, sizeof(toff), hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipMemcpyAsync(&moff, h.m.ev_track_off + event, 4, hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipStreamSynchronize(st));
+  const int64_t n = (int64_t)toff[1] - toff[0];
+  if (n == 0) return TPC_OK;
+  std::vector<int32_t> lo(n), bo(n), mi(n);
+  std::vector<double> bc(n);
+  TPC_HIP(hipMemcpyAsync(lo.data(), h.m.link_out + toff[0], n * 4, hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipMemcpyAsync(bo.data(), h.m.best_out + toff[0], n * 4, hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipMemcpyAsync(bc.data(), h.m.chi_out + toff[0], n * 8, hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipMemcpyAsync(mi.data(), h.m.into + toff[0], n * 4, hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipStreamSynchronize(st));
+  for (int64_t i = 0; i < n; ++i) {
+    if (link_out) link_out[i] = lo[i] >= 0 ? lo[i] - (int32_t)toff[0] : -1;
+    if (best_out) best_out[i] = bo[i] >= 0 ? bo[i] - (int32_t)toff[0] : -1;
+    if (best_chi2) best_chi2[i] = bc[i];
+    if (merged_into) merged_into[i] = mi[i] - (int32_t)moff;
+  }
+  return TPC_OK;
 }
 
 int tpc_graph_capture(tpc_ctx* ctx, int slot) {

@@ -1,0 +1,537 @@
+// Cross-sector merger: a particle that crosses the boundary between two
+// neighbouring sectors of one side leaves one track segment in each; the
+// per-sector tracker fits them separately.  This step (the continuation of
+// the per-sector tracking the paper's tracker chain performs next) joins
+// such segments and refits the joined hit list across the sector frames.
+//
+//  M1 each track's state at its outermost hit: one outward Kalman pass over
+//     its hits, seeded with its fitted parameters at the innermost hit and
+//     the prior covariance (lane per track);
+//  M2 pairs (A, B) of one event, B in a neighbouring sector of A's side,
+//     0 < B.row_in - A.row_out <= row_gap: A's outer state turned into B's
+//     frame and transported to B's innermost row is compared with B's
+//     fitted state, chi2 = d^T (C_A + C_B)^-1 d over the 5 parameters.
+//     T and Q do not change under rotation or transport and d_i^2 / S_ii
+//     never exceeds the chi2, so pairs failing the cut on them alone are
+//     skipped before any transport.  Lane per A (best outer partner) and
+//     lane per B (best inner partner), ties to the smaller track position;
+//  M3 a pair is linked if each is the other's best; links form chains;
+//  M4 each chain of >= 2 segments is refitted inward over all its hits, in
+//     passes (the first seeded with the outermost segment's outer state,
+//     each later one with the previous result carried out to the outermost
+//     hit), turning frames at the boundaries (lane per chain);
+//  then the output: merged chains in place of their segments, canonical
+//  order (event, innermost cluster ID) kept.
+//
+// Frame rotation: the frame of the neighbouring sector is turned by the
+// angle a with cosine ca and sine sa; x' = x ca + y sa, y' = -x sa + y ca,
+// sin phi' = sin(phi - a); the covariance is carried to the new x' along
+// the track, C' = J C J^T with J(y', y) = ca - sa tan phi',
+// J(z', y) = -sa T / cos phi', J(s', y) = -b Q sa, J(s', s) = cos phi' / cos phi
+// (dense products in index order, so the result is reproducible bit for bit).
+#include "tpc_device.h"
+#include "tpc_kernels.h"
+
+namespace tpc {
+
+constexpr int kMaxChain = 16;    // segments of one chain (each holds >= 10 of the 159 rows)
+
+__device__ __forceinline__ double xrow(const DevConst& K, int r) { return (double)K.row_x[r]; }
+
+__device__ __forceinline__ void prior_d(const DevConst& K, Helix<double>& st, double zv) {
+  const double sy = (double)K.sy0 + (double)K.sy1 * fabs(zv) / (double)K.z_max;
+  const double sz = (double)K.sz0 + (double)K.sz1 * fabs(zv) / (double)K.z_max;
+  reset_cov(st, sy * sy, sz * sz, (double)K.cs0, (double)K.ct0, (double)K.cq0);
+}
+
+// ungated update with the hit at global cluster index gid; returns its chi2
+__device__ __forceinline__ double update_hit(const Slot& S, const DevConst& K, Helix<double>& st,
+                                             int64_t gid) {
+  const double sy = (double)K.sy0 + (double)K.sy1 * fabs(st.z) / (double)K.z_max;
+  const double sz = (double)K.sz0 + (double)K.sz1 * fabs(st.z) / (double)K.z_max;
+  double ch = 0.0;
+  kalman_update(st, (double)S.y[gid], (double)S.z[gid], sy * sy, sz * sz, (double)K.chi2max,
+                (double)K.smax, false, &ch);
+  return ch;
+}
+
+__device__ bool rotate_frame(Helix<double>& h, double& x, double ca, double sa, double b,
+                             double smax) {
+  const double y = h.y, s = h.s, tl = h.t, q = h.q;
+  const double c = sqrt(1.0 - s * s);
+  const double s1 = s * ca - c * sa;
+  if (!(fabs(s1) <= smax)) return false;
+  const double c1 = sqrt(1.0 - s1 * s1);
+  const double x1 = x * ca + y * sa;
+  const double y1 = -x * sa + y * ca;
+  double J[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) J[i][j] = i == j ? 1.0 : 0.0;
+  J[0][0] = ca - sa * (s1 / c1);
+  J[1][0] = -sa * tl / c1;
+  J[2][0] = -(b * q) * sa;
+  J[2][2] = c1 / c;
+  double Cf[5][5];
+#pragma unroll
+  for (int i = 0, k = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j, ++k) Cf[i][j] = Cf[j][i] = h.c[k];
+  double A[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) a = a + J[i][k] * Cf[k][l];
+      A[i][l] = a;
+    }
+#pragma unroll
+  for (int i = 0, k = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j, ++k) {
+      double v = 0.0;
+#pragma unroll
+      for (int l = 0; l < 5; ++l) v = v + A[i][l] * J[j][l];
+      h.c[k] = v;
+    }
+  h.y = y1;
+  h.s = s1;
+  x = x1;
+  return true;
+}
+
+// from x to xt in equal steps of at most step_max (refused beyond 1000 cm,
+// longer than any path in the chamber, which also bounds the step count)
+__device__ bool transport_to_x(Helix<double>& h, double x, double xt, double b, double smax,
+                               double step_max) {
+  const double d = xt - x;
+  if (!(fabs(d) <= 1000.0)) return false;
+  const int n = max(1, (int)ceil(fabs(d) / step_max));
+  const double dx = d / (double)n;
+  for (int i = 0; i < n; ++i)
+    if (!transport(h, dx, b, smax)) return false;
+  return true;
+}
+
+// d^T S^-1 d by Cholesky (S packed like the covariance); false if S is not
+// positive definite
+__device__ bool chi2_5(const double* S, const double* d, double& chi2) {
+  double L[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) L[i][j] = 0.0;
+#pragma unroll
+  for (int i = 0, k = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j, ++k) L[i][j] = S[k];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    double v = L[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) v = v - L[j][k] * L[j][k];
+    if (!(v > 0.0)) return false;
+    const double ljj = sqrt(v);
+    L[j][j] = ljj;
+#pragma unroll
+    for (int i = j + 1; i < 5; ++i) {
+      double w = L[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) w = w - L[i][k] * L[j][k];
+      L[i][j] = w / ljj;
+    }
+  }
+  double yv[5];
+  double sum = 0.0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    double w = d[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) w = w - L[i][k] * yv[k];
+    yv[i] = w / L[i][i];
+    sum = sum + yv[i] * yv[i];
+  }
+  chi2 = sum;
+  return true;
+}
+
+// +1 if sector b (0..35 of one event) is the next one counter-clockwise of
+// a on the same side, -1 the previous one, 0 otherwise
+__device__ __forceinline__ int neighbour(int a, int b) {
+  if (a / 18 != b / 18) return 0;
+  const int ka = a % 18, kb = b % 18;
+  if (kb == (ka + 1) % 18) return 1;
+  if (ka == (kb + 1) % 18) return -1;
+  return 0;
+}
+
+__device__ __forceinline__ const int32_t* track_hits(const Slot& S, const tpc_track& t) {
+  return S.out_hits + S.ev_hit_off[t.event] + t.hit_off;
+}
+
+// M1
+__global__ void __launch_bounds__(64) k_mg_outer(Slot S, DevConst K, MergeSlot M, MergeConst C) {
+  const uint32_t ntk = S.out_count[0];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
+    const tpc_track t = S.out_tracks[a];
+    const int64_t ev0 = S.ev_off[t.event];
+    const int32_t* h = track_hits(S, t);
+    Helix<double> st;
+    st.y = t.par[0];
+    st.z = t.par[1];
+    st.s = t.par[2];
+    st.t = t.par[3];
+    st.q = t.par[4];
+    prior_d(K, st, st.z);
+    bool ok = true;
+    int k = 1;
+    for (int r = t.row_in + 1; r <= t.row_out; ++r) {
+      if (!transport(st, xrow(K, r) - xrow(K, r - 1), K.bd, C.smax)) {
+        ok = false;
+        break;
+      }
+      if (k < t.n_hits) {
+        const int64_t gid = ev0 + h[k];
+        if ((int)S.row[gid] == r) {
+          update_hit(S, K, st, gid);
+          ++k;
+        }
+      }
+    }
+    M.ok[a] = ok ? 1 : 0;
+    double* op = M.op + (size_t)a * 5;
+    op[0] = st.y;
+    op[1] = st.z;
+    op[2] = st.s;
+    op[3] = st.t;
+    op[4] = st.q;
+    double* oc = M.oc + (size_t)a * 15;
+    for (int i = 0; i < 15; ++i) oc[i] = st.c[i];
+  }
+}
+
+// track positions grouped by (event, sector)
+__global__ void k_mg_count(Slot S, MergeSlot M) {
+  const uint32_t ntk = S.out_count[0];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
+    const tpc_track& t = S.out_tracks[a];
+    atomicAdd(&M.sec_cnt[t.event * kSectorsPerEvent + t.sector], 1u);
+  }
+}
+
+__global__ void k_mg_scatter(Slot S, MergeSlot M) {
+  const uint32_t ntk = S.out_count[0];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
+    const tpc_track& t = S.out_tracks[a];
+    const int g = t.event * kSectorsPerEvent + t.sector;
+    M.sec_list[M.sec_cnt[g] + atomicAdd(&M.sec_cur[g], 1u)] = (int32_t)a;
+  }
+}
+
+// M2 for the pair (A with outer state st0, B); false if incompatible
+__device__ bool pair_chi2(const DevConst& K, const MergeConst& C, const tpc_track& A,
+                          const double* op, const double* oc, const tpc_track& B, double& chi2) {
+  const int dir = neighbour(A.sector, B.sector);
+  if (dir == 0) return false;
+  if (!(B.row_in > A.row_out && B.row_in - A.row_out <= C.row_gap)) return false;
+  const double cut = C.chi2_max;
+  const double dT = op[3] - B.par[3], dQ = op[4] - B.par[4];
+  if (dT * dT > cut * (oc[9] + B.cov[9])) return false;
+  if (dQ * dQ > cut * (oc[14] + B.cov[14])) return false;
+  Helix<double> st;
+  st.y = op[0];
+  st.z = op[1];
+  st.s = op[2];
+  st.t = op[3];
+  st.q = op[4];
+  for (int i = 0; i < 15; ++i) st.c[i] = oc[i];
+  double x = xrow(K, A.row_out);
+  if (!rotate_frame(st, x, C.ca, (double)dir * C.sa, K.bd, C.smax)) return false;
+  if (!transport_to_x(st, x, xrow(K, B.row_in), K.bd, C.smax, C.step_max)) return false;
+  double d[5], Sm[15];
+  d[0] = st.y - B.par[0];
+  d[1] = st.z - B.par[1];
+  d[2] = st.s - B.par[2];
+  d[3] = st.t - B.par[3];
+  d[4] = st.q - B.par[4];
+  for (int i = 0; i < 15; ++i) Sm[i] = st.c[i] + B.cov[i];
+  if (!chi2_5(Sm, d, chi2)) return false;
+  return chi2 <= cut;
+}
+
+// The candidates of a track: the tracks of the two neighbouring sectors of
+// its side in its event.
+template <class Fn>
+__device__ __forceinline__ void for_neighbours(const MergeSlot& M, const tpc_track& t, Fn&& fn) {
+  const int side = t.sector / 18, k = t.sector % 18;
+  const int nb[2] = {(k + 1) % 18, (k + 17) % 18};
+  for (int u = 0; u < 2; ++u) {
+    const int g = t.event * kSectorsPerEvent + side * 18 + nb[u];
+    for (uint32_t i = M.sec_cnt[g]; i < M.sec_cnt[g + 1]; ++i) fn(M.sec_list[i]);
+  }
+}
+
+// M2 + M3: best outer partner of each A
+__global__ void __launch_bounds__(64) k_mg_best_out(Slot S, DevConst K, MergeSlot M,
+                                                    MergeConst C) {
+  const uint32_t ntk = S.out_count[0];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
+    int32_t best = -1;
+    double bc = 0.0;
+    if (M.ok[a]) {
+      const tpc_track& A = S.out_tracks[a];
+      const double* op = M.op + (size_t)a * 5;
+      const double* oc = M.oc + (size_t)a * 15;
+      for_neighbours(M, A, [&](int32_t b) {
+        double ch;
+        if (!pair_chi2(K, C, A, op, oc, S.out_tracks[b], ch)) return;
+        if (best < 0 || ch < bc || (ch == bc && b < best)) {
+          best = b;
+          bc = ch;
+        }
+      });
+    }
+    M.best_out[a] = best;
+    M.chi_out[a] = bc;
+  }
+}
+
+// M2 + M3: best inner partner of each B
+__global__ void __launch_bounds__(64) k_mg_best_in(Slot S, DevConst K, MergeSlot M,
+                                                   MergeConst C) {
+  const uint32_t ntk = S.out_count[0];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < ntk; b += stride) {
+    const tpc_track& B = S.out_tracks[b];
+    int32_t best = -1;
+    double bc = 0.0;
+    for_neighbours(M, B, [&](int32_t a) {
+      if (!M.ok[a]) return;
+      double ch;
+      if (!pair_chi2(K, C, S.out_tracks[a], M.op + (size_t)a * 5, M.oc + (size_t)a * 15, B, ch))
+        return;
+      if (best < 0 || ch < bc || (ch == bc && a < best)) {
+        best = a;
+        bc = ch;
+      }
+    });
+    M.best_in[b] = best;
+    M.chi_in[b] = bc;
+  }
+}
+
+// M3: mutual best pairs (link_in filled with -1 before)
+__global__ void k_mg_link(Slot S, MergeSlot M) {
+  const uint32_t ntk = S.out_count[0];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
+    const int32_t b = M.best_out[a];
+    const bool linked = b >= 0 && M.best_in[b] == (int32_t)a;
+    M.link_out[a] = linked ? b : -1;
+    if (linked) M.link_in[b] = (int32_t)a;
+  }
+}
+
+struct Chain {
+  int n;
+  int32_t pos[kMaxChain];
+};
+
+// one inward pass over the chain, seeded with (s0, t0, q0) at the
+// outermost hit
+__device__ bool chain_pass(const Slot& S, const DevConst& K, const MergeConst& C, const Chain& ch,
+                           double s0, double t0, double q0, Helix<double>& out, double& chi2,
+                           int& n) {
+  const tpc_track L = S.out_tracks[ch.pos[ch.n - 1]];
+  const int64_t evL = S.ev_off[L.event];
+  const int32_t* hl = track_hits(S, L);
+  const int64_t go = evL + hl[L.n_hits - 1];
+  Helix<double> st;
+  st.y = (double)S.y[go];
+  st.z = (double)S.z[go];
+  st.s = s0;
+  st.t = t0;
+  st.q = q0;
+  prior_d(K, st, st.z);
+  chi2 = 0.0;
+  n = 1;
+  int cur_row = S.row[go];
+  for (int j = ch.n - 1; j >= 0; --j) {
+    const tpc_track T = S.out_tracks[ch.pos[j]];
+    const int64_t ev0 = S.ev_off[T.event];
+    const int32_t* h = track_hits(S, T);
+    int k = T.n_hits - 1;
+    if (j == ch.n - 1) {
+      --k;
+    } else {
+      const int dir = neighbour(T.sector, S.out_tracks[ch.pos[j + 1]].sector);
+      double x = xrow(K, cur_row);
+      if (!rotate_frame(st, x, C.ca, -(double)dir * C.sa, K.bd, C.smax)) return false;
+      const int64_t g = ev0 + h[k];
+      const int r = S.row[g];
+      if (!transport_to_x(st, x, xrow(K, r), K.bd, C.smax, C.step_max)) return false;
+      chi2 = chi2 + update_hit(S, K, st, g);
+      ++n;
+      cur_row = r;
+      --k;
+    }
+    for (; k >= 0; --k) {
+      const int64_t g = ev0 + h[k];
+      const int r = S.row[g];
+      for (int rr = cur_row - 1; rr >= r; --rr)
+        if (!transport(st, xrow(K, rr) - xrow(K, rr + 1), K.bd, C.smax)) return false;
+      chi2 = chi2 + update_hit(S, K, st, g);
+      ++n;
+      cur_row = r;
+    }
+  }
+  out = st;
+  return true;
+}
+
+// the inner result of a pass carried out to the outermost hit (the next
+// pass resets the covariance, so only its parameters matter)
+__device__ bool carry_out(const Slot& S, const DevConst& K, const MergeConst& C, const Chain& ch,
+                          Helix<double> st, double& s0, double& t0, double& q0) {
+  const tpc_track F = S.out_tracks[ch.pos[0]];
+  double x = xrow(K, S.row[S.ev_off[F.event] + track_hits(S, F)[0]]);
+  for (int j = 0; j < ch.n; ++j) {
+    const tpc_track T = S.out_tracks[ch.pos[j]];
+    const double xo = xrow(K, S.row[S.ev_off[T.event] + track_hits(S, T)[T.n_hits - 1]]);
+    if (!transport_to_x(st, x, xo, K.bd, C.smax, C.step_max)) return false;
+    x = xo;
+    if (j + 1 < ch.n) {
+      const int dir = neighbour(T.sector, S.out_tracks[ch.pos[j + 1]].sector);
+      if (!rotate_frame(st, x, C.ca, (double)dir * C.sa, K.bd, C.smax)) return false;
+    }
+  }
+  s0 = st.s;
+  t0 = st.t;
+  q0 = st.q;
+  return true;
+}
+
+// M4: refit of each chain (lane per chain head)
+__global__ void __launch_bounds__(64) k_mg_chain(Slot S, DevConst K, MergeSlot M, MergeConst C) {
+  const uint32_t ntk = S.out_count[0];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
+    M.head_ok[a] = 0;
+    if (M.link_in[a] >= 0 || M.link_out[a] < 0) continue;     // not the head of a chain
+    Chain ch;
+    ch.n = 0;
+    bool fits = true;
+    for (int32_t p = (int32_t)a; p >= 0; p = M.link_out[p]) {
+      if (ch.n == kMaxChain) {
+        fits = false;
+        break;
+      }
+      ch.pos[ch.n++] = p;
+    }
+    const int32_t last = ch.pos[ch.n - 1];
+    bool good = fits && M.ok[last] != 0;
+    double s0 = M.op[(size_t)last * 5 + 2], t0 = M.op[(size_t)last * 5 + 3],
+           q0 = M.op[(size_t)last * 5 + 4];
+    Helix<double> res;
+    double chi2 = 0.0;
+    int nh = 0;
+    for (int pass = 0; pass < C.passes && good; ++pass) {
+      if (pass > 0) good = carry_out(S, K, C, ch, res, s0, t0, q0);
+      if (good) good = chain_pass(S, K, C, ch, s0, t0, q0, res, chi2, nh);
+    }
+    if (!good) continue;
+    M.head_ok[a] = 1;
+    M.nseg[a] = ch.n;
+    M.nfit[a] = nh;
+    double* par = M.par + (size_t)a * 5;
+    par[0] = res.y;
+    par[1] = res.z;
+    par[2] = res.s;
+    par[3] = res.t;
+    par[4] = res.q;
+    double* cov = M.cov + (size_t)a * 15;
+    for (int i = 0; i < 15; ++i) cov[i] = res.c[i];
+    M.chi2[a] = chi2;
+  }
+}
+
+__device__ __forceinline__ int32_t chain_head(const MergeSlot& M, int32_t a) {
+  int32_t h = a;
+  while (M.link_in[h] >= 0) h = M.link_in[h];
+  return h;
+}
+
+// output items: a refitted chain replaces its segments (at its head's
+// position), every other track stays
+__global__ void k_mg_emit(Slot S, MergeSlot M) {
+  const uint32_t ntk = S.out_count[0];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
+    const int32_t h = chain_head(M, (int32_t)a);
+    uint32_t e = 1, n = (uint32_t)S.out_tracks[a].n_hits;
+    if (M.head_ok[h]) {
+      e = h == (int32_t)a ? 1u : 0u;
+      n = h == (int32_t)a ? (uint32_t)M.nfit[h] : 0u;
+    }
+    M.emit[a] = e;
+    M.nh[a] = n;
+  }
+}
+
+__global__ void k_mg_event_off(Slot S, MergeSlot M) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > S.n_events) return;
+  const uint32_t k = S.ev_track_off[e];
+  M.ev_track_off[e] = M.emit[k];
+  M.ev_hit_off[e] = M.nh[k];
+}
+
+__global__ void __launch_bounds__(64) k_mg_write(Slot S, DevConst K, MergeSlot M) {
+  const uint32_t ntk = S.out_count[0];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
+    const int32_t h = chain_head(M, (int32_t)a);
+    const bool merged = M.head_ok[h] != 0;
+    const int32_t src = merged ? h : (int32_t)a;
+    M.into[a] = (int32_t)M.emit[src];
+    if (merged && h != (int32_t)a) continue;
+    const uint32_t pos = M.emit[a];
+    const uint32_t hpos = M.nh[a];
+    tpc_track o = S.out_tracks[a];
+    const int e = o.event;
+    int32_t* dst = M.hits + hpos;
+    if (merged) {
+      int32_t last = h;
+      int nh = 0;
+      for (int32_t p = h; p >= 0; p = M.link_out[p]) {
+        const tpc_track T = S.out_tracks[p];
+        const int32_t* src_h = track_hits(S, T);
+        for (int i = 0; i < T.n_hits; ++i) dst[nh + i] = src_h[i];
+        nh += T.n_hits;
+        last = p;
+      }
+      o.n_hits = M.nfit[h];
+      o.row_out = S.out_tracks[last].row_out;
+      o.ndf = 2 * o.n_hits - 5;
+      for (int i = 0; i < 5; ++i) o.par[i] = M.par[(size_t)h * 5 + i];
+      for (int i = 0; i < 15; ++i) o.cov[i] = M.cov[(size_t)h * 15 + i];
+      o.chi2 = M.chi2[h];
+      M.out_nseg[pos] = M.nseg[h];
+    } else {
+      const int32_t* src_h = track_hits(S, o);
+      for (int i = 0; i < o.n_hits; ++i) dst[i] = src_h[i];
+      M.out_nseg[pos] = 1;
+    }
+    o.hit_off = (int64_t)(hpos - M.ev_hit_off[e]);
+    M.tracks[pos] = o;
+  }
+}
+
+}  // namespace tpc

@@ -32,5 +32,16 @@ __global__ void k_flags(Slot S);
 __global__ void k_order(Slot S);
 __global__ void k_event_hits(Slot S);
 __global__ void k_write_out(Slot S, DevConst K);
+// cross-sector merger
+__global__ void k_mg_count(Slot S, MergeSlot M);
+__global__ void k_mg_scatter(Slot S, MergeSlot M);
+__global__ void k_mg_outer(Slot S, DevConst K, MergeSlot M, MergeConst C);
+__global__ void k_mg_best_out(Slot S, DevConst K, MergeSlot M, MergeConst C);
+__global__ void k_mg_best_in(Slot S, DevConst K, MergeSlot M, MergeConst C);
+__global__ void k_mg_link(Slot S, MergeSlot M);
+__global__ void k_mg_chain(Slot S, DevConst K, MergeSlot M, MergeConst C);
+__global__ void k_mg_emit(Slot S, MergeSlot M);
+__global__ void k_mg_event_off(Slot S, MergeSlot M);
+__global__ void k_mg_write(Slot S, DevConst K, MergeSlot M);
 
 }  // namespace tpc

@@ -142,6 +142,39 @@ class Tracker:
                                     ctypes.byref(nh)), self.ctx)
         return tracks, hits
 
+    # -- cross-sector merger ----------------------------------------------------
+    def merge(self, slot: int = 0, **over):
+        """Join segments across sector boundaries (asynchronous)."""
+        m = _lib.MergeParams()
+        check(self.L.tpc_merge_params_default(ctypes.byref(m)))
+        for k, v in over.items():
+            setattr(m, k, v)
+        check(self.L.tpc_merge(self.ctx, slot, ctypes.byref(m)), self.ctx)
+
+    def get_merged(self, slot: int = 0, event: int = 0):
+        """(tracks, hit IDs, segments per track) of one event after merge()."""
+        nt, nh = ctypes.c_int64(0), ctypes.c_int64(0)
+        rc = self.L.tpc_get_merged(self.ctx, slot, event, None, 0, None, 0, None,
+                                   ctypes.byref(nt), ctypes.byref(nh))
+        if rc not in (_lib.TPC_OK, _lib.TPC_EOVERFLOW):
+            check(rc, self.ctx)
+        tracks = np.zeros(nt.value, TRACK_DTYPE)
+        hits = np.zeros(nh.value, np.int32)
+        nseg = np.zeros(nt.value, np.int32)
+        check(self.L.tpc_get_merged(self.ctx, slot, event, tracks.ctypes.data, len(tracks),
+                                    hits.ctypes.data, len(hits), nseg.ctypes.data,
+                                    ctypes.byref(nt), ctypes.byref(nh)), self.ctx)
+        return tracks, hits, nseg
+
+    def merge_links(self, slot: int, event: int, n_tracks: int):
+        """Per track of get_tracks(slot, event): linked outer segment, best
+        outer candidate, its chi2, output track it went into."""
+        lo, bo, mi = (np.empty(n_tracks, np.int32) for _ in range(3))
+        bc = np.empty(n_tracks, np.float64)
+        check(self.L.tpc_get_merge_links(self.ctx, slot, event, lo.ctypes.data, bo.ctypes.data,
+                                         bc.ctypes.data, mi.ctypes.data), self.ctx)
+        return dict(link_out=lo, best_out=bo, best_chi2=bc, merged_into=mi)
+
     def get_links(self, slot: int, event: int, n: int):
         out = [np.empty(n, np.int32) for _ in range(4)]
         check(self.L.tpc_get_links(self.ctx, slot, event, *[o.ctypes.data for o in out]), self.ctx)

@@ -43,6 +43,17 @@ def test_params_defaults_match_oracle(L):
         assert getattr(p, k) == pytest.approx(v), k
 
 
+def test_merge_defaults_match_oracle(L):
+    from oracle import oracle
+    mp = _lib.MergeParams()
+    assert L.tpc_merge_params_default(ctypes.byref(mp)) == _lib.TPC_OK
+    om = oracle.MergeParams()
+    for k, v in oracle.DEFAULT_MERGE.items():
+        setattr(om, k, v)
+        assert getattr(mp, k) == getattr(om, k), k      # the same float32 / int32 values
+    assert ctypes.sizeof(_lib.MergeParams) == ctypes.sizeof(oracle.MergeParams) == 20
+
+
 def test_workspace_bytes(L):
     p = default_params(max_clusters=1 << 20)
     a = L.tpc_workspace_bytes(ctypes.byref(p))
@@ -124,6 +135,19 @@ def test_calls_rejected_before_device_work(L):
     assert L.tpc_track_event_streams(ctx, 0, 0) == _lib.TPC_EINVAL
     assert L.tpc_track_event_streams(ctx, 0, 9) == _lib.TPC_EINVAL
     assert L.tpc_track_event_streams(ctx, 2, 4) == _lib.TPC_EINVAL
+    mp = _lib.MergeParams()
+    assert L.tpc_merge_params_default(ctypes.byref(mp)) == _lib.TPC_OK
+    assert L.tpc_merge(ctx, 0, ctypes.byref(mp)) == _lib.TPC_ESTATE
+    assert L.tpc_merge(ctx, 0, None) == _lib.TPC_EINVAL
+    for k, v in (("passes", 0), ("s_max", 1.0), ("row_gap", 0), ("chi2_max", 0.0),
+                 ("step_max", 0.05)):
+        bad = _lib.MergeParams()
+        L.tpc_merge_params_default(ctypes.byref(bad))
+        setattr(bad, k, v)
+        assert L.tpc_merge(ctx, 0, ctypes.byref(bad)) == _lib.TPC_EINVAL, k
+    assert L.tpc_get_merged(ctx, 0, 0, None, 0, None, 0, None, ctypes.byref(ctypes.c_int64()),
+                            ctypes.byref(ctypes.c_int64())) == _lib.TPC_ESTATE
+    assert L.tpc_get_merge_links(ctx, 0, 0, None, None, None, None) == _lib.TPC_ESTATE
     nt, nh = ctypes.c_int64(), ctypes.c_int64()
     assert L.tpc_get_tracks(ctx, 0, 0, None, 0, None, 0, ctypes.byref(nt),
                             ctypes.byref(nh)) == _lib.TPC_ESTATE
