@@ -176,6 +176,28 @@ def bench_serve(pool, geo, n_req: int) -> dict:
         print(f"bench: serve plain={plain} rate {rate:.1f}/s: {out}", file=sys.stderr, flush=True)
         return out
 
+    def serve_calib(rate, with_calib):
+        """The same stream with a 0.4% drift-velocity error in every event,
+        with or without the calibration side task."""
+        import tpcgen
+        from paper_1712_09416_amd.calib import DriftCalibration
+        dist = {id(e): tpcgen.drift_z(e.sector, e.z, 0.004) for e in picks}
+        times = poisson_arrivals(len(picks), rate, seed=7)
+        rq = [Request(float(t), e.sector, e.row, e.y, dist[id(e)], tag=e.name)
+              for t, e in zip(times, picks)]
+        cal = DriftCalibration(250.0, every=50) if with_calib else None
+        srv = Server(geo, n_streams=4, max_events=8, cap_clusters=cap, calib=cal)
+        srv.run(rq[:40])
+        st = srv.run(rq, warmup=warm)
+        srv.close()
+        out = st.summary()
+        if cal is not None:
+            out["calibration"] = {"fits": len(cal.history), "eps_true": 0.004, "eps_final": cal.eps,
+                                  "every_events": 50}
+        print(f"bench: serve drift calib={with_calib} rate {rate:.1f}/s: {out}", file=sys.stderr,
+              flush=True)
+        return out
+
     c_plain = capacity(True)
     print(f"bench: serve plain capacity {c_plain:.1f} events/s", file=sys.stderr, flush=True)
     c_cb = capacity(False)
@@ -186,7 +208,11 @@ def bench_serve(pool, geo, n_req: int) -> dict:
             "at_0.7_plain_capacity": {"rate_events_per_s": r1, "plain": serve(True, r1),
                                       "continuous_batching": serve(False, r1)},
             "at_0.7_cb_capacity": {"rate_events_per_s": 0.7 * c_cb,
-                                   "continuous_batching": serve(False, 0.7 * c_cb)}}
+                                   "continuous_batching": serve(False, 0.7 * c_cb)},
+            "drift_calibration_side_task": {
+                "rate_events_per_s": 0.7 * c_cb,
+                "without": serve_calib(0.7 * c_cb, False),
+                "with": serve_calib(0.7 * c_cb, True)}}
 
 
 def cpu_baseline(ev, threads: int) -> dict:
@@ -211,6 +237,8 @@ def main() -> int:
                     help="steps of the per-sector (plain) launch sequence, for comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
+    ap.add_argument("--merge-reps", type=int, default=5,
+                    help="timed runs of the cross-sector merger on the central event (0: skip)")
     ap.add_argument("--e2e-steps", type=int, default=20,
                     help="end-to-end steps (host clusters in, host tracks out)")
     ap.add_argument("--batch-events", type=int, default=64,
@@ -318,6 +346,24 @@ def main() -> int:
     ms_per_step = wall_ms / args.steps
     value = ev.n / (ms_per_step * 1e-3)
 
+    # cross-sector merger on the tracked central event (the step after the
+    # per-sector path; timed on its own, not part of the step above)
+    merge = None
+    if args.merge_reps > 0:
+        trk.load(0, *ins)
+        trk.track_event(0)
+        trk.merge(0)
+        torch.cuda.synchronize()
+        m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        m0.record(st)
+        for _ in range(args.merge_reps):
+            trk.merge(0)
+        m1.record(st)
+        torch.cuda.synchronize()
+        mt, mh, mseg = trk.get_merged(0)
+        merge = {"ms": m0.elapsed_time(m1) / args.merge_reps, "tracks_in": int(len(tracks)),
+                 "tracks_out": int(len(mt)), "chains": int((mseg > 1).sum())}
+
     # plain: the same event with the per-sector launch sequence
     plain = None
     if args.plain_steps > 0:
@@ -371,6 +417,7 @@ def main() -> int:
         "tracks": int(len(tracks)),
         "track_hits": int(len(hits)),
         "plain": plain,
+        "merge": merge,
         "end_to_end": ({"what": "pinned host clusters -> H2D -> tracking -> tracks in host memory",
                         "p50_ms": float(np.percentile(e2e, 50)),
                         "p99_ms": float(np.percentile(e2e, 99)),

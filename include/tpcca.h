@@ -253,6 +253,39 @@ int tpc_get_merged(tpc_ctx* ctx, int slot, int event, tpc_track* out, int64_t ma
 int tpc_get_merge_links(tpc_ctx* ctx, int slot, int event, int32_t* link_out, int32_t* best_out,
                         double* best_chi2, int32_t* merged_into);
 
+/* Drift-velocity calibration from tracks (paper, Section 3: online
+ * calibration runs on the online reconstruction, accumulates data over many
+ * events and fits from time to time; Section 5.3: its result is fed back
+ * into the cluster transformation).  z of a cluster comes from its drift
+ * time to its side's readout plane (sectors 0-17 at +z_max, 18-35 at
+ * -z_max); a drift velocity off by the relative eps gives the measured
+ * z' = z (1 + eps) - side eps z_max, so primary tracks carried to the beam
+ * axis point to z0 = -side eps z_max.
+ *
+ * tpc_calib_accumulate: for every track of a tracked slot with >= 30 hits,
+ * its parameters at the innermost hit are transported (double, steps of at
+ * most 2 cm, |sin phi| <= 0.999) to x = 0 of its sector frame; if |y0| <= 2
+ * cm, 1 is added to bin floor((z0 - z_lo) / w) (w = (z_hi - z_lo) / n_bins,
+ * in range only) of hist[side][n_bins] (device memory, uint32, side 0 = A;
+ * the caller zeroes it; integer atomics, so counts do not depend on order).
+ * Asynchronous on the context stream (covered by tpc_poll).  Errors:
+ * TPC_EINVAL, TPC_ESTATE (slot not tracked).
+ *
+ * tpc_calib_fit: on the given stream (device hist and out), each side's
+ * median of z0 (linear inside the median bin; NaN if the side is empty)
+ * and eps = (median_C - median_A) / (2 z_max): out[3] = {median_A,
+ * median_C, eps}.  One small kernel; meant to run beside the tracking on a
+ * stream of its own.  Errors: TPC_EINVAL, TPC_EDEVICE.
+ *
+ * tpc_calib_correct_z: z[i] <- (z[i] + side eps z_max) / (1 + eps) for n
+ * device clusters (side from sector[i]); |eps| < 0.5.  Asynchronous on the
+ * context stream.  Errors: TPC_EINVAL. */
+int tpc_calib_accumulate(tpc_ctx* ctx, int slot, uint32_t* hist, int n_bins, float z_lo,
+                         float z_hi);
+int tpc_calib_fit(const uint32_t* hist, int n_bins, float z_lo, float z_hi, float z_max,
+                  double* out, void* hip_stream);
+int tpc_calib_correct_z(tpc_ctx* ctx, const uint8_t* sector, float* z, int64_t n, double eps);
+
 /* Record into a HIP graph, without running it, the whole sequence
  * tpc_track_event would enqueue for the slot as currently staged (grid,
  * finding, fitting, ordering; kernels only, no memset or copy nodes).  The

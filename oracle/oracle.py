@@ -110,6 +110,7 @@ def lib():
         L.orc_merge_get.argtypes = [P, P, P, P, P, P, P, P]
         L.orc_rotate_d.argtypes = [P, P, P, f64, f64, f64, f64]
         L.orc_chi2_5.argtypes = [P, P, P]
+        L.orc_calib_z0.argtypes = [ctypes.POINTER(Geometry), P, ctypes.c_int64, f64, f64, P, P, P]
         _lib = L
     return _lib
 
@@ -299,3 +300,71 @@ def chi2_5(S, d):
     out = np.zeros(1, np.float64)
     ok = lib().orc_chi2_5(_ptr(S), _ptr(d), _ptr(out))
     return bool(ok), float(out[0])
+
+
+# ---- drift-velocity calibration -------------------------------------------------
+# Accumulate, per side (sectors 0-17: A, z > 0; 18-35: C), the beam-axis z0 of
+# primary-like tracks into an integer histogram; the fit takes each side's
+# median (linear inside the median bin) and eps = (med_C - med_A) / (2 z_max).
+
+CALIB = dict(n_bins=4000, z_lo=-20.0, z_hi=20.0, n_min=30, y0_max=2.0, step_max=2.0,
+             s_max=0.999)
+
+
+def calib_z0(tracks, geo: dict):
+    """(y0, z0, ok) per track: parameters transported to x = 0."""
+    tracks = np.ascontiguousarray(tracks, TRACK_DTYPE)
+    n = len(tracks)
+    y0, z0 = np.zeros(n), np.zeros(n)
+    ok = np.zeros(n, np.int32)
+    g = make_geometry(geo)
+    lib().orc_calib_z0(ctypes.byref(g), _ptr(tracks), n, CALIB["step_max"], CALIB["s_max"],
+                       _ptr(y0), _ptr(z0), _ptr(ok))
+    return y0, z0, ok.astype(bool)
+
+
+def calib_histogram(tracks, geo: dict, n_bins=None, z_lo=None, z_hi=None):
+    """[2, n_bins] uint32 counts of z0 for the selected tracks of one event."""
+    n_bins = n_bins or CALIB["n_bins"]
+    z_lo = CALIB["z_lo"] if z_lo is None else z_lo
+    z_hi = CALIB["z_hi"] if z_hi is None else z_hi
+    y0, z0, ok = calib_z0(tracks, geo)
+    w = (float(np.float32(z_hi)) - float(np.float32(z_lo))) / n_bins
+    lo = float(np.float32(z_lo))
+    sel = ok & (tracks["n_hits"] >= CALIB["n_min"]) & (np.abs(y0) <= CALIB["y0_max"])
+    f = (z0 - lo) / w
+    sel &= (f >= 0.0) & (f < n_bins)
+    b = np.floor(f[sel]).astype(np.int64)
+    side = (np.asarray(tracks["sector"])[sel] // 18).astype(np.int64)
+    h = np.zeros((2, n_bins), np.uint32)
+    np.add.at(h, (side, b), 1)
+    return h
+
+
+def calib_fit(hist, z_max: float, z_lo=None, z_hi=None):
+    """(median z0 of side A, of side C, eps); NaN where a side is empty."""
+    n_bins = hist.shape[1]
+    z_lo = CALIB["z_lo"] if z_lo is None else z_lo
+    z_hi = CALIB["z_hi"] if z_hi is None else z_hi
+    lo = float(np.float32(z_lo))
+    w = (float(np.float32(z_hi)) - lo) / n_bins
+    med = []
+    for side in range(2):
+        c = hist[side].astype(np.int64)
+        n = int(c.sum())
+        if n == 0:
+            med.append(float("nan"))
+            continue
+        half = n / 2.0
+        cum = np.concatenate([[0], np.cumsum(c)])
+        b = int(np.nonzero(cum[1:] >= half)[0][0])
+        med.append(lo + (b + (half - float(cum[b])) / float(c[b])) * w)
+    zm = float(np.float32(z_max))
+    return med[0], med[1], (med[1] - med[0]) / (2.0 * zm)
+
+
+def drift_correct(sector, z, eps: float, z_max: float):
+    """Cluster z corrected for a drift-velocity error eps (float32 out)."""
+    s = np.where(np.asarray(sector) < 18, 1.0, -1.0)
+    zm = float(np.float32(z_max))
+    return ((np.asarray(z, np.float64) + s * eps * zm) / (1.0 + eps)).astype(np.float32)

@@ -1390,6 +1390,27 @@ void orc_merge_get(void* h, orc_track* out, int32_t* hit_ids, int32_t* n_segment
   std::memcpy(merged_into, o->merged_into.data(), n * 4);
 }
 
+// Drift-velocity calibration, per track: the track's parameters at its
+// innermost hit transported (double, equal steps of at most step_max, stop
+// beyond |sin phi| = s_max) to x = 0 of its sector frame, i.e. to the beam
+// axis for a track from the origin.  y0, z0 out; ok = 0 if the transport
+// stopped.  A drift velocity off by a relative eps moves every cluster to
+// z (1 + eps) - side eps z_max, so primary tracks then point to
+// z0 = -side eps z_max: the two sides' z0 differ by 2 eps z_max.
+void orc_calib_z0(const orc_geometry* g, const orc_track* tracks, int64_t n, double step_max,
+                  double s_max, double* y0, double* z0, int32_t* ok) {
+  const double b = -0.00299792458 * double(g->bz_tesla);
+  for (int64_t i = 0; i < n; ++i) {
+    State<double> st;
+    for (int k = 0; k < 5; ++k) st.p[k] = tracks[i].par[k];
+    for (int k = 0; k < 15; ++k) st.C[k] = 0.0;
+    const bool good = transport_to(st, tracks[i].x_ref, 0.0, b, s_max, step_max);
+    ok[i] = good ? 1 : 0;
+    y0[i] = st.p[0];
+    z0[i] = st.p[1];
+  }
+}
+
 // Frame rotation of one double state (pins): x in/out; returns 0 if refused.
 int orc_rotate_d(double* p, double* C, double* x, double ca, double sa, double b, double smax) {
   State<double> st;

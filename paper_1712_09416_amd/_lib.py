@@ -21,6 +21,7 @@ EXPORTS = ("tpc_params_default", "tpc_workspace_bytes", "tpc_init_geometry", "tp
            "tpc_device_results", "tpc_get_links", "tpc_kf_step_f32", "tpc_graph_capture",
            "tpc_graph_launch", "tpc_poll", "tpc_set_profiling", "tpc_get_profile",
            "tpc_merge_params_default", "tpc_merge", "tpc_get_merged", "tpc_get_merge_links",
+           "tpc_calib_accumulate", "tpc_calib_fit", "tpc_calib_correct_z",
            "tpc_last_error", "tpc_destroy")
 STAGES = ("grid", "neighbours", "clean_starts", "tracklets", "weights_select", "refit", "output")
 
@@ -98,6 +99,10 @@ def load() -> ctypes.CDLL:
     L.tpc_merge.argtypes = [P, I, ctypes.POINTER(MergeParams)]
     L.tpc_get_merged.argtypes = [P, I, I, P, I64, P, I64, P, P, P]
     L.tpc_get_merge_links.argtypes = [P, I, I, P, P, P, P]
+    F, D = ctypes.c_float, ctypes.c_double
+    L.tpc_calib_accumulate.argtypes = [P, I, P, I, F, F]
+    L.tpc_calib_fit.argtypes = [P, I, F, F, F, P, P]
+    L.tpc_calib_correct_z.argtypes = [P, P, P, I64, D]
     L.tpc_last_error.restype = ctypes.c_char_p
     L.tpc_last_error.argtypes = [P]
     L.tpc_destroy.argtypes = [P]

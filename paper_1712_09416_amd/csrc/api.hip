@@ -754,6 +754,49 @@ int tpc_get_merge_links(tpc_ctx* ctx, int slot, int event, int32_t* link_out, in
   return TPC_OK;
 }
 
+int tpc_calib_accumulate(tpc_ctx* ctx, int slot, uint32_t* hist, int n_bins, float z_lo,
+                         float z_hi) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  if (!hist || n_bins < 1 || n_bins > (1 << 20) || !std::isfinite(z_lo) || !std::isfinite(z_hi) ||
+      !(z_hi > z_lo))
+    return ctx->fail(TPC_EINVAL, "bad histogram arguments");
+  if (ctx->capturing) return ctx->fail(TPC_ESTATE, "not available under capture");
+  SlotHost& h = ctx->slots[slot];
+  if (h.state == 3) {
+    const int rc = finalize(ctx, h);
+    if (rc) return rc;
+  }
+  if (h.state != 4) return ctx->fail(TPC_ESTATE, "slot not tracked");
+  const double w = ((double)z_hi - (double)z_lo) / (double)n_bins;
+  k_cal_accumulate<<<grid_stride_blocks(h.d.cap_tk, 64, 4096), 64, 0, ctx->stream>>>(
+      h.d, ctx->k, hist, n_bins, (double)z_lo, w);
+  TPC_LAUNCHED();
+  return record_done(ctx, h);
+}
+
+int tpc_calib_fit(const uint32_t* hist, int n_bins, float z_lo, float z_hi, float z_max,
+                  double* out, void* hip_stream) {
+  if (!hist || !out || n_bins < 1 || n_bins > (1 << 20) || !std::isfinite(z_lo) ||
+      !std::isfinite(z_hi) || !(z_hi > z_lo) || !(z_max > 0.0f))
+    return TPC_EINVAL;
+  const double w = ((double)z_hi - (double)z_lo) / (double)n_bins;
+  k_cal_fit<<<1, 256, 0, reinterpret_cast<hipStream_t>(hip_stream)>>>(hist, n_bins, (double)z_lo, w,
+                                                                       (double)z_max, out);
+  return hipGetLastError() == hipSuccess ? TPC_OK : TPC_EDEVICE;
+}
+
+int tpc_calib_correct_z(tpc_ctx* ctx, const uint8_t* sector, float* z, int64_t n, double eps) {
+  if (!ctx) return TPC_EINVAL;
+  if (n < 0 || (n > 0 && (!sector || !z))) return ctx->fail(TPC_EINVAL, "bad cluster arrays");
+  if (!std::isfinite(eps) || !(std::fabs(eps) < 0.5)) return ctx->fail(TPC_EINVAL, "eps out of range");
+  if (n == 0) return TPC_OK;
+  k_cal_correct<<<grid_stride_blocks(n, 256), 256, 0, ctx->stream>>>(sector, z, n, eps,
+                                                                    (double)ctx->g.z_max);
+  TPC_LAUNCHED();
+  return TPC_OK;
+}
+
 int tpc_graph_capture(tpc_ctx* ctx, int slot) {
   if (!ctx) return TPC_EINVAL;
   if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");

@@ -35,7 +35,7 @@ struct PairBest {
   }
 };
 
-constexpr int kNfReg = 8;        // up-row candidates held in registers per hit
+constexpr int kNfCand = 32;      // up-row candidates listed per hit before a nested scan
 
 // a3: one block per (sector, row).  For each hit h of row r (1..157), the
 // pair (d in row r-1, u in row r+1) inside the origin-pointing windows
@@ -43,12 +43,15 @@ constexpr int kNfReg = 8;        // up-row candidates held in registers per hit
 // closest to h, measured by m = dy^2 / (1.5 sy^2) + dz^2 / (1.5 sz^2);
 // ties go to the smaller (id_d, id_u); the pair is kept if m <= m_max.
 // Rows 0 and 158 get no links.
-// One lane per hit.  The up-row candidates (a few per hit at the densest
-// occupancy) are read once into registers and paired with every down-row
-// candidate as it is read; a hit with more than kNfReg up candidates scans
-// the up window again per down candidate.  Both rows are read through the
-// caches (the batched window reads keep few round trips in flight per hit).
+// One lane per hit.  The up-row candidates are listed once in LDS
+// (thread-minor, so a wave's accesses fall in distinct banks) and paired
+// with every down-row candidate as it is read; a hit with more than kNfCand
+// up candidates scans the up window again per down candidate.  Both rows
+// are read through the caches with the batched window reads (measured
+// faster than staging the rows in LDS, and than holding the candidates in
+// registers, whose fixed-length pairing loop costs more than it saves).
 __global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, int g0) {
+  __shared__ uint32_t cand[kNfCand * kNfThreads];
   const int row = blockIdx.x;
   const int g = g0 + blockIdx.y;
   const int sr = g * kRows + row;
@@ -68,47 +71,37 @@ __global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, i
   const float rho_u = K.row_x[row + 1] / xr;
   const float f = (xr - K.row_x[row - 1]) / (K.row_x[row + 1] - K.row_x[row - 1]);
   const float W = K.nf_w;
+  uint32_t* my = cand + threadIdx.x;
   for (uint32_t h = h0 + threadIdx.x; h < h1; h += blockDim.x) {
     const Hit x = S.hit[h];
     const float yh = x.y, zh = x.z;
     const float ypu = yh * rho_u, zpu = zh * rho_u;
     const float ypd = yh * rho_d, zpd = zh * rho_d;
-    const float sy = sigma_y(K, zh), sz = sigma_z(K, zh);
-    const float wy = 1.0f / (1.5f * (sy * sy));
-    const float wz = 1.0f / (1.5f * (sz * sz));
-    float cy[kNfReg], cz[kNfReg];
-    uint32_t cid[kNfReg];
-    int32_t cp[kNfReg];
     int nu = 0;
     for_window_hits(Bu, bou, S.hit, ypu, zpu, W, W, [&](uint32_t u, const Hit& c) {
       if (!(fabsf(c.y - ypu) <= W && fabsf(c.z - zpu) <= W)) return;
-#pragma unroll
-      for (int k = 0; k < kNfReg; ++k) {
-        if (k == nu) {
-          cy[k] = c.y;
-          cz[k] = c.z;
-          cid[k] = c.id;
-          cp[k] = (int32_t)u;
-        }
-      }
+      if (nu < kNfCand) my[nu * kNfThreads] = u;
       ++nu;
     });
     PairBest best;
     if (nu > 0) {
+      const float sy = sigma_y(K, zh), sz = sigma_z(K, zh);
+      const float wy = 1.0f / (1.5f * (sy * sy));
+      const float wz = 1.0f / (1.5f * (sz * sz));
       for_window_hits(Bd, bod, S.hit, ypd, zpd, W, W, [&](uint32_t d, const Hit& xd) {
         if (!(fabsf(xd.y - ypd) <= W && fabsf(xd.z - zpd) <= W)) return;
-        if (nu <= kNfReg) {
-#pragma unroll
-          for (int k = 0; k < kNfReg; ++k) {
-            if (k < nu)
-              best.offer(nf_metric(xd.y, xd.z, cy[k], cz[k], yh, zh, f, wy, wz), xd.id, cid[k],
-                         (int32_t)d, cp[k]);
+        if (nu <= kNfCand) {
+          for (int k = 0; k < nu; ++k) {
+            const uint32_t u = my[k * kNfThreads];
+            const Hit xu = S.hit[u];
+            best.offer(nf_metric(xd.y, xd.z, xu.y, xu.z, yh, zh, f, wy, wz), xd.id, xu.id,
+                       (int32_t)d, (int32_t)u);
           }
         } else {
           for_window_hits(Bu, bou, S.hit, ypu, zpu, W, W, [&](uint32_t u, const Hit& c) {
             if (!(fabsf(c.y - ypu) <= W && fabsf(c.z - zpu) <= W)) return;
-            best.offer(nf_metric(xd.y, xd.z, c.y, c.z, yh, zh, f, wy, wz), xd.id, c.id, (int32_t)d,
-                       (int32_t)u);
+            best.offer(nf_metric(xd.y, xd.z, c.y, c.z, yh, zh, f, wy, wz), xd.id, c.id,
+                       (int32_t)d, (int32_t)u);
           });
         }
       });

@@ -103,19 +103,6 @@ __device__ bool rotate_frame(Helix<double>& h, double& x, double ca, double sa, 
   return true;
 }
 
-// from x to xt in equal steps of at most step_max (refused beyond 1000 cm,
-// longer than any path in the chamber, which also bounds the step count)
-__device__ bool transport_to_x(Helix<double>& h, double x, double xt, double b, double smax,
-                               double step_max) {
-  const double d = xt - x;
-  if (!(fabs(d) <= 1000.0)) return false;
-  const int n = max(1, (int)ceil(fabs(d) / step_max));
-  const double dx = d / (double)n;
-  for (int i = 0; i < n; ++i)
-    if (!transport(h, dx, b, smax)) return false;
-  return true;
-}
-
 // d^T S^-1 d by Cholesky (S packed like the covariance); false if S is not
 // positive definite
 __device__ bool chi2_5(const double* S, const double* d, double& chi2) {

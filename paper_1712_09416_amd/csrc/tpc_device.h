@@ -416,4 +416,17 @@ __device__ __forceinline__ void reset_cov(Helix<F>& h, F vy, F vz, F cs0, F ct0,
   h.c[14] = cq0;
 }
 
+// From x to xt in equal steps of at most step_max (refused beyond 1000 cm,
+// longer than any path in the chamber, which also bounds the step count).
+__device__ __forceinline__ bool transport_to_x(Helix<double>& h, double x, double xt, double b,
+                                               double smax, double step_max) {
+  const double d = xt - x;
+  if (!(fabs(d) <= 1000.0)) return false;
+  const int n = max(1, (int)ceil(fabs(d) / step_max));
+  const double dx = d / (double)n;
+  for (int i = 0; i < n; ++i)
+    if (!transport(h, dx, b, smax)) return false;
+  return true;
+}
+
 }  // namespace tpc

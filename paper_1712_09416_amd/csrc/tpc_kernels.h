@@ -43,5 +43,11 @@ __global__ void k_mg_chain(Slot S, DevConst K, MergeSlot M, MergeConst C);
 __global__ void k_mg_emit(Slot S, MergeSlot M);
 __global__ void k_mg_event_off(Slot S, MergeSlot M);
 __global__ void k_mg_write(Slot S, DevConst K, MergeSlot M);
+// drift-velocity calibration
+__global__ void k_cal_accumulate(Slot S, DevConst K, uint32_t* hist, int n_bins, double z_lo,
+                                 double w);
+__global__ void k_cal_fit(const uint32_t* hist, int n_bins, double z_lo, double w, double z_max,
+                          double* out);
+__global__ void k_cal_correct(const uint8_t* sector, float* z, int64_t n, double eps, double z_max);
 
 }  // namespace tpc

@@ -16,6 +16,11 @@ chain).  Here, on one GPU:
 
 Mode "plain" is the reference: one tracker, one event at a time, tracked
 with the per-sector launch sequence.
+
+With `calib` (a DriftCalibration), a drift-velocity calibration runs beside
+the loop: every batch's clusters get the current z correction before
+tracking and its tracks are accumulated; fits run on a stream of their own
+and are polled, never waited for (paper, Sections 3 and 5.1).
 """
 from __future__ import annotations
 
@@ -78,7 +83,7 @@ class _Worker:
         self.d_z = torch.empty(cap, dtype=torch.float32, device=device)
         self.batch: list[int] = []
 
-    def submit(self, reqs: list[Request], ids: list[int], plain: bool):
+    def submit(self, reqs: list[Request], ids: list[int], plain: bool, calib=None):
         offs = np.zeros(len(ids) + 1, np.int64)
         for k, i in enumerate(ids):
             offs[k + 1] = offs[k] + reqs[i].n
@@ -95,6 +100,7 @@ class _Worker:
             for d, h in ((self.d_sector, self.h_sector), (self.d_row, self.h_row),
                          (self.d_y, self.h_y), (self.d_z, self.h_z)):
                 d[:n].copy_(h[:n], non_blocking=True)
+            self.tag = calib.on_submit(self.trk, self.d_sector, self.d_z, n) if calib else None
             self.trk.load_batch(0, offs, self.d_sector[:n], self.d_row[:n], self.d_y[:n],
                                 self.d_z[:n])
         if plain:
@@ -102,6 +108,8 @@ class _Worker:
                 self.trk.track_sector(0, s)
         else:
             self.trk.track_event(0)
+        if calib:
+            calib.on_tracked(self.trk, self.tag)
         self.batch = list(ids)
 
     def close(self):
@@ -114,8 +122,9 @@ class Server:
 
     def __init__(self, geometry: dict, n_streams: int = 4, max_events: int = 8,
                  cap_clusters: int = 4 << 20, budget_clusters: int | None = None,
-                 device: str = "cuda:0", plain: bool = False):
+                 device: str = "cuda:0", plain: bool = False, calib=None):
         self.plain = plain
+        self.calib = calib        # optional DriftCalibration side task
         if plain:
             n_streams, max_events = 1, 1
         self.max_events = max_events
@@ -145,6 +154,8 @@ class Server:
                 pending.append(order[nxt])
                 nxt += 1
             progressed = False
+            if self.calib and self.calib.poll():      # side task: never waits
+                progressed = True
             # completions
             for w in list(busy):
                 wk = self.workers[w]
@@ -156,6 +167,8 @@ class Server:
                     in_flight -= reqs[i].n
                     if collect:
                         results[i] = (tracks, hits)
+                if self.calib:
+                    self.calib.on_complete(wk.tag, len(wk.batch))
                 del busy[w]
                 free.append(w)
                 progressed = True
@@ -171,7 +184,7 @@ class Server:
                 if not take:
                     break
                 w = free.pop()
-                self.workers[w].submit(reqs, take, self.plain)
+                self.workers[w].submit(reqs, take, self.plain, self.calib)
                 busy[w] = True
                 in_flight += n
                 progressed = True

@@ -175,6 +175,23 @@ class Tracker:
                                          bc.ctypes.data, mi.ctypes.data), self.ctx)
         return dict(link_out=lo, best_out=bo, best_chi2=bc, merged_into=mi)
 
+    # -- drift-velocity calibration -------------------------------------------
+    def calib_accumulate(self, slot: int, hist: torch.Tensor, z_lo: float = -20.0,
+                         z_hi: float = 20.0):
+        """Add the slot's tracks' beam-axis z0 to hist ([2, n_bins] int32/uint32
+        on the device; asynchronous on the tracker's stream)."""
+        assert hist.is_cuda and hist.dim() == 2 and hist.shape[0] == 2 and hist.is_contiguous()
+        assert hist.dtype in (torch.int32,)
+        check(self.L.tpc_calib_accumulate(self.ctx, slot, hist.data_ptr(), hist.shape[1], z_lo,
+                                          z_hi), self.ctx)
+
+    def calib_correct_z(self, sector: torch.Tensor, z: torch.Tensor, eps: float):
+        """Correct device cluster z in place for a drift-velocity error eps."""
+        assert sector.is_cuda and z.is_cuda and sector.dtype == torch.uint8
+        assert z.dtype == torch.float32 and z.is_contiguous() and sector.is_contiguous()
+        check(self.L.tpc_calib_correct_z(self.ctx, sector.data_ptr(), z.data_ptr(), z.numel(),
+                                         float(eps)), self.ctx)
+
     def get_links(self, slot: int, event: int, n: int):
         out = [np.empty(n, np.int32) for _ in range(4)]
         check(self.L.tpc_get_links(self.ctx, slot, event, *[o.ctypes.data for o in out]), self.ctx)
@@ -219,3 +236,14 @@ class Tracker:
             self.close()
         except Exception:
             pass
+
+
+def calib_fit(hist: torch.Tensor, out: torch.Tensor, z_max: float, z_lo: float = -20.0,
+              z_hi: float = 20.0, stream=None):
+    """Median z0 per side and eps into out (3 float64 on the device), on the
+    given stream (default: torch's current one); asynchronous."""
+    L = _lib.load()
+    assert hist.is_cuda and out.is_cuda and out.dtype == torch.float64 and out.numel() >= 3
+    st = stream if stream is not None else torch.cuda.current_stream(hist.device)
+    check(L.tpc_calib_fit(hist.data_ptr(), hist.shape[1], z_lo, z_hi, z_max, out.data_ptr(),
+                          st.cuda_stream))

@@ -479,3 +479,68 @@ def test_merge_edge_cases(dev, oracle_lib):
         assert np.array_equal(gt[k], tracks[k]), k
     merge_case(trk, 0, 0, ev, oracle_lib)
     trk.close()
+
+
+# ---------------------------------------------------------------------------
+# drift-velocity calibration
+
+def test_calibration_matches_oracle(dev, oracle_lib):
+    """Histogram of beam-axis z0 (integers), fitted medians and eps, and the
+    z correction: bit-identical to the oracle's on the same tracks."""
+    from paper_1712_09416_amd import Tracker
+    from paper_1712_09416_amd.tracker import calib_fit
+    ev = tpcgen.distort_drift(tpcgen.pbpb_event(tpcgen.seed_for(4, 103), 2000), 0.003)
+    geo = ev.geometry()
+    trk = Tracker(geo, max_clusters=ev.n)
+    ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.sector, ev.row, ev.y, ev.z)]
+    trk.load(0, *ins)
+    trk.track_event(0)
+    hist = torch.zeros((2, 4000), dtype=torch.int32, device=dev)
+    trk.calib_accumulate(0, hist)
+    tracks, _ = trk.get_tracks(0)
+    ref = oracle_lib.calib_histogram(as_oracle_tracks(tracks, oracle_lib), geo)
+    trk.synchronize()
+    h = hist.cpu().numpy().view(np.uint32)
+    assert np.array_equal(h, ref)
+    out = torch.zeros(3, dtype=torch.float64, device=dev)
+    calib_fit(hist, out, 250.0, stream=trk.stream)
+    trk.synchronize()
+    got = out.cpu().numpy()
+    exp = np.array(oracle_lib.calib_fit(ref, 250.0))
+    say(f"calibration: {got} (oracle {exp})")
+    assert np.array_equal(got, exp)
+    assert abs(got[2] - 0.003) < 1e-4
+    z = ins[3].clone()
+    trk.calib_correct_z(ins[0], z, float(got[2]))
+    trk.synchronize()
+    assert np.array_equal(z.cpu().numpy(), oracle_lib.drift_correct(ev.sector, ev.z, float(got[2]), 250.0))
+    # an empty side gives NaN
+    h1 = torch.zeros((2, 4000), dtype=torch.int32, device=dev)
+    h1[0, 2000] = 3
+    calib_fit(h1, out, 250.0, stream=trk.stream)
+    trk.synchronize()
+    got = out.cpu().numpy()
+    assert got[0] == 0.005 and np.isnan(got[1]) and np.isnan(got[2])
+    trk.close()
+
+
+def test_calibration_side_task_converges_while_serving(dev):
+    """Events served with a 0.4% drift-velocity error: the side task's fits
+    (polled, never waited for) bring the correction to the true value, and
+    every event is still served."""
+    from paper_1712_09416_amd.calib import DriftCalibration
+    from paper_1712_09416_amd.serve import Server, Request, poisson_arrivals
+    pool = [tpcgen.distort_drift(tpcgen.pbpb_event(tpcgen.seed_for(4, 110 + e), 1500), 0.004)
+            for e in range(6)]
+    geo = pool[0].geometry()
+    arr = poisson_arrivals(90, 400.0, seed=9)
+    reqs = [Request(float(arr[i]), pool[i % 6].sector, pool[i % 6].row, pool[i % 6].y,
+                    pool[i % 6].z) for i in range(90)]
+    cal = DriftCalibration(250.0, every=12, device=dev)
+    srv = Server(geo, n_streams=3, max_events=4, cap_clusters=2_000_000, calib=cal)
+    st = srv.run(reqs)
+    srv.close()
+    say(f"calibration fits: {cal.history}; serving {st.summary()}")
+    assert st.n_requests == 90
+    assert len(cal.history) >= 2
+    assert abs(cal.eps - 0.004) < 2e-4, cal.eps

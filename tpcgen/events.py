@@ -353,3 +353,19 @@ def serve_event(e: int) -> Event:
     if u < 0.95:
         return pbpb_event(seed, 2000, name="peripheral_2000")
     return pbpb_event(seed, 15000, name="central_pbpb_15000")
+
+
+def drift_z(sector, z, eps: float) -> np.ndarray:
+    """Cluster z as reconstructed with a drift velocity off by the relative
+    eps.  z comes from the drift time to the readout plane at +-z_max of
+    each side (sectors 0-17: A side, z > 0; 18-35: C side), so the measured
+    z is z (1 + eps) - side eps z_max."""
+    side = np.where(np.asarray(sector) < 18, 1.0, -1.0)
+    zz = np.asarray(z, np.float64)
+    return (zz * (1.0 + eps) - side * eps * G.Z_MAX).astype(np.float32)
+
+
+def distort_drift(ev: Event, eps: float) -> Event:
+    """The event with drift_z applied; truth is unchanged."""
+    import dataclasses
+    return dataclasses.replace(ev, z=drift_z(ev.sector, ev.z, eps), name=f"{ev.name}_drift{eps:g}")
