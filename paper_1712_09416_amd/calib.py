@@ -68,8 +68,8 @@ class DriftCalibration:
     def on_complete(self, tag: _Hist, n_events: int):
         tag.inflight -= 1
         tag.events += n_events
-        if tag is self.cur and tag.events >= self.every and self.pending is None \\
-                and self.fitting is None:
+        if (tag is self.cur and tag.events >= self.every and self.pending is None
+                and self.fitting is None):
             tag.closed = True
             self.pending = tag
             self.cur = _Hist(self.n_bins, self.device, self.eps)

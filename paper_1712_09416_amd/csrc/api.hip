@@ -168,9 +168,12 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   s.err = c.take<uint32_t>(4);
   s.stats = c.take<unsigned long long>(8);
   MergeSlot m;
-  m.sec_cnt = c.take<uint32_t>(S + 1);
-  m.sec_cur = c.take<uint32_t>(S);
-  m.sec_list = c.take<int32_t>(cap_tk);
+  m.in_off = c.take<uint32_t>(SR + 1);
+  m.in_cur = c.take<uint32_t>(SR);
+  m.in_list = c.take<int32_t>(cap_tk);
+  m.out_off = c.take<uint32_t>(SR + 1);
+  m.out_cur = c.take<uint32_t>(SR);
+  m.out_list = c.take<int32_t>(cap_tk);
   m.op = c.take<double>(cap_tk * 5);
   m.oc = c.take<double>(cap_tk * 15);
   m.ok = c.take<int32_t>(cap_tk);
@@ -674,11 +677,13 @@ int tpc_merge(tpc_ctx* ctx, int slot, const tpc_merge_params* mp) {
   const int64_t ns = s.n_sectors;
   const int nbt = grid_stride_blocks(K, 64, 8192);
   const int nb = grid_stride_blocks(K, 256);
-  k_zero_u32<<<grid_stride_blocks(ns + 1, 256), 256, 0, st>>>(m.sec_cnt, ns + 1);
-  k_zero_u32<<<grid_stride_blocks(ns, 256), 256, 0, st>>>(m.sec_cur, ns);
+  const int64_t nsr = ns * kRows;
+  for (uint32_t* p : {m.in_off, m.out_off}) k_zero_u32<<<grid_stride_blocks(nsr + 1, 256), 256, 0, st>>>(p, nsr + 1);
+  for (uint32_t* p : {m.in_cur, m.out_cur}) k_zero_u32<<<grid_stride_blocks(nsr, 256), 256, 0, st>>>(p, nsr);
   k_fill_i32<<<nb, 256, 0, st>>>(m.link_in, K, -1);
   k_mg_count<<<nb, 256, 0, st>>>(s, m);
-  scan_u32(st, m.sec_cnt, nullptr, ns, s.scan_b, nullptr);
+  scan_u32(st, m.in_off, nullptr, nsr, s.scan_b, nullptr);
+  scan_u32(st, m.out_off, nullptr, nsr, s.scan_b, nullptr);
   k_mg_scatter<<<nb, 256, 0, st>>>(s, m);
   k_mg_outer<<<nbt, 64, 0, st>>>(s, ctx->k, m, C);
   k_mg_best_out<<<nbt, 64, 0, st>>>(s, ctx->k, m, C);

@@ -44,15 +44,33 @@ __device__ __forceinline__ void prior_d(const DevConst& K, Helix<double>& st, do
   reset_cov(st, sy * sy, sz * sz, (double)K.cs0, (double)K.ct0, (double)K.cq0);
 }
 
-// ungated update with the hit at global cluster index gid; returns its chi2
-__device__ __forceinline__ double update_hit(const Slot& S, const DevConst& K, Helix<double>& st,
-                                             int64_t gid) {
+// ungated update with a measured (y, z); returns its chi2
+__device__ __forceinline__ double update_yz(const DevConst& K, Helix<double>& st, float y,
+                                            float z) {
   const double sy = (double)K.sy0 + (double)K.sy1 * fabs(st.z) / (double)K.z_max;
   const double sz = (double)K.sz0 + (double)K.sz1 * fabs(st.z) / (double)K.z_max;
   double ch = 0.0;
-  kalman_update(st, (double)S.y[gid], (double)S.z[gid], sy * sy, sz * sz, (double)K.chi2max,
-                (double)K.smax, false, &ch);
+  kalman_update(st, (double)y, (double)z, sy * sy, sz * sz, (double)K.chi2max, (double)K.smax,
+                false, &ch);
   return ch;
+}
+
+__device__ __forceinline__ double update_hit(const Slot& S, const DevConst& K, Helix<double>& st,
+                                             int64_t gid) {
+  return update_yz(K, st, S.y[gid], S.z[gid]);
+}
+
+// a cluster's pad row and coordinates, loaded together
+struct HitRec {
+  int row;
+  float y, z;
+};
+__device__ __forceinline__ HitRec load_hit(const Slot& S, int64_t gid) {
+  HitRec h;
+  h.row = S.row[gid];
+  h.y = S.y[gid];
+  h.z = S.z[gid];
+  return h;
 }
 
 __device__ bool rotate_frame(Helix<double>& h, double& x, double ca, double sa, double b,
@@ -201,13 +219,17 @@ __global__ void __launch_bounds__(64) k_mg_outer(Slot S, DevConst K, MergeSlot M
   }
 }
 
-// track positions grouped by (event, sector)
+// track positions grouped by (event, sector, first row) and by (event,
+// sector, last row); the order inside a group does not matter (ties are
+// broken by track position)
 __global__ void k_mg_count(Slot S, MergeSlot M) {
   const uint32_t ntk = S.out_count[0];
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
     const tpc_track& t = S.out_tracks[a];
-    atomicAdd(&M.sec_cnt[t.event * kSectorsPerEvent + t.sector], 1u);
+    const int g = t.event * kSectorsPerEvent + t.sector;
+    atomicAdd(&M.in_off[g * kRows + t.row_in], 1u);
+    atomicAdd(&M.out_off[g * kRows + t.row_out], 1u);
   }
 }
 
@@ -217,7 +239,9 @@ __global__ void k_mg_scatter(Slot S, MergeSlot M) {
   for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
     const tpc_track& t = S.out_tracks[a];
     const int g = t.event * kSectorsPerEvent + t.sector;
-    M.sec_list[M.sec_cnt[g] + atomicAdd(&M.sec_cur[g], 1u)] = (int32_t)a;
+    const int gi = g * kRows + t.row_in, go = g * kRows + t.row_out;
+    M.in_list[M.in_off[gi] + atomicAdd(&M.in_cur[gi], 1u)] = (int32_t)a;
+    M.out_list[M.out_off[go] + atomicAdd(&M.out_cur[go], 1u)] = (int32_t)a;
   }
 }
 
@@ -252,15 +276,21 @@ __device__ bool pair_chi2(const DevConst& K, const MergeConst& C, const tpc_trac
   return chi2 <= cut;
 }
 
-// The candidates of a track: the tracks of the two neighbouring sectors of
-// its side in its event.
+// Candidates of a track among the tracks of the two neighbouring sectors
+// of its side in its event, those whose row (`off` indexes first rows, or
+// last rows) lies in [r_lo, r_hi]: every pair the row condition of M2 admits.
 template <class Fn>
-__device__ __forceinline__ void for_neighbours(const MergeSlot& M, const tpc_track& t, Fn&& fn) {
+__device__ __forceinline__ void for_neighbours(const uint32_t* off, const int32_t* list,
+                                               const tpc_track& t, int r_lo, int r_hi, Fn&& fn) {
+  r_lo = max(r_lo, 0);
+  r_hi = min(r_hi, kRows - 1);
+  if (r_lo > r_hi) return;
   const int side = t.sector / 18, k = t.sector % 18;
   const int nb[2] = {(k + 1) % 18, (k + 17) % 18};
   for (int u = 0; u < 2; ++u) {
     const int g = t.event * kSectorsPerEvent + side * 18 + nb[u];
-    for (uint32_t i = M.sec_cnt[g]; i < M.sec_cnt[g + 1]; ++i) fn(M.sec_list[i]);
+    const uint32_t i1 = off[g * kRows + r_hi + 1];
+    for (uint32_t i = off[g * kRows + r_lo]; i < i1; ++i) fn(list[i]);
   }
 }
 
@@ -276,7 +306,7 @@ __global__ void __launch_bounds__(64) k_mg_best_out(Slot S, DevConst K, MergeSlo
       const tpc_track& A = S.out_tracks[a];
       const double* op = M.op + (size_t)a * 5;
       const double* oc = M.oc + (size_t)a * 15;
-      for_neighbours(M, A, [&](int32_t b) {
+      for_neighbours(M.in_off, M.in_list, A, A.row_out + 1, A.row_out + C.row_gap, [&](int32_t b) {
         double ch;
         if (!pair_chi2(K, C, A, op, oc, S.out_tracks[b], ch)) return;
         if (best < 0 || ch < bc || (ch == bc && b < best)) {
@@ -299,7 +329,7 @@ __global__ void __launch_bounds__(64) k_mg_best_in(Slot S, DevConst K, MergeSlot
     const tpc_track& B = S.out_tracks[b];
     int32_t best = -1;
     double bc = 0.0;
-    for_neighbours(M, B, [&](int32_t a) {
+    for_neighbours(M.out_off, M.out_list, B, B.row_in - C.row_gap, B.row_in - 1, [&](int32_t a) {
       if (!M.ok[a]) return;
       double ch;
       if (!pair_chi2(K, C, S.out_tracks[a], M.op + (size_t)a * 5, M.oc + (size_t)a * 15, B, ch))
@@ -369,14 +399,17 @@ __device__ bool chain_pass(const Slot& S, const DevConst& K, const MergeConst& C
       cur_row = r;
       --k;
     }
+    // the segment's remaining hits, inward, each loaded one hit ahead
+    HitRec nx;
+    if (k >= 0) nx = load_hit(S, ev0 + h[k]);
     for (; k >= 0; --k) {
-      const int64_t g = ev0 + h[k];
-      const int r = S.row[g];
-      for (int rr = cur_row - 1; rr >= r; --rr)
+      const HitRec hr = nx;
+      if (k > 0) nx = load_hit(S, ev0 + h[k - 1]);
+      for (int rr = cur_row - 1; rr >= hr.row; --rr)
         if (!transport(st, xrow(K, rr) - xrow(K, rr + 1), K.bd, C.smax)) return false;
-      chi2 = chi2 + update_hit(S, K, st, g);
+      chi2 = chi2 + update_yz(K, st, hr.y, hr.z);
       ++n;
-      cur_row = r;
+      cur_row = hr.row;
     }
   }
   out = st;

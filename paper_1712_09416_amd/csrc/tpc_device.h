@@ -131,9 +131,12 @@ struct Slot {
 // sectors, E = events).  Track positions are the slot's canonical output
 // positions.
 struct MergeSlot {
-  uint32_t* sec_cnt;        // [S+1] tracks per (event, sector), then offsets
-  uint32_t* sec_cur;        // [S] scatter cursors
-  int32_t* sec_list;        // [K] track positions grouped by (event, sector)
+  uint32_t* in_off;         // [S*159+1] tracks per (event, sector, first row), then offsets
+  uint32_t* in_cur;         // [S*159] scatter cursors
+  int32_t* in_list;         // [K] track positions grouped by (event, sector, first row)
+  uint32_t* out_off;        // [S*159+1] the same by last row
+  uint32_t* out_cur;        // [S*159]
+  int32_t* out_list;        // [K]
   double* op;               // [K][5] state at the outermost hit
   double* oc;               // [K][15]
   int32_t* ok;              // [K] outer state exists

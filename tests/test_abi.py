@@ -168,3 +168,17 @@ def test_batch_event_limit(L):
     offs = np.zeros(6, np.int64)
     assert L.tpc_load_batch(ctx, 0, 5, offs.ctypes.data, a.ctypes.data, a.ctypes.data,
                             f.ctypes.data, f.ctypes.data, None, _lib.TPC_HOST) == _lib.TPC_EINVAL
+
+
+def test_every_package_module_imports():
+    """Every module of the package and the generator imports on the CPU
+    (the binding loads the library lazily; nothing here touches a GPU)."""
+    import importlib
+    import pkgutil
+    import paper_1712_09416_amd as pkg
+    import tpcgen as gen
+    for mod in (pkg, gen):
+        for info in pkgutil.iter_modules(mod.__path__):
+            if info.name.startswith("lib"):          # the built shared library itself
+                continue
+            importlib.import_module(f"{mod.__name__}.{info.name}")

@@ -520,7 +520,8 @@ def test_calibration_matches_oracle(dev, oracle_lib):
     calib_fit(h1, out, 250.0, stream=trk.stream)
     trk.synchronize()
     got = out.cpu().numpy()
-    assert got[0] == 0.005 and np.isnan(got[1]) and np.isnan(got[2])
+    exp = oracle_lib.calib_fit(h1.cpu().numpy().view(np.uint32), 250.0)
+    assert got[0] == exp[0] and np.isnan(got[1]) and np.isnan(got[2])
     trk.close()
 
 
