@@ -198,6 +198,21 @@ def bench_serve(pool, geo, n_req: int) -> dict:
               flush=True)
         return out
 
+    def calib_ab(rate, reps=3):
+        """Without / with the side task, alternated (run-to-run spread of the
+        latencies is larger than the side task's cost); medians."""
+        runs = {False: [], True: []}
+        for _ in range(reps):
+            for w in (False, True):
+                runs[w].append(serve_calib(rate, w))
+        med = lambda rs, k: float(np.median([r[k] for r in rs]))  # noqa: E731
+        out = {"rate_events_per_s": rate, "repeats": reps}
+        for w, name in ((False, "without"), (True, "with")):
+            out[name] = {"p50_ms": med(runs[w], "p50_ms"), "p99_ms": med(runs[w], "p99_ms"),
+                         "runs": [{"p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"]} for r in runs[w]]}
+        out["with"]["calibration"] = runs[True][-1]["calibration"]
+        return out
+
     c_plain = capacity(True)
     print(f"bench: serve plain capacity {c_plain:.1f} events/s", file=sys.stderr, flush=True)
     c_cb = capacity(False)
@@ -209,10 +224,7 @@ def bench_serve(pool, geo, n_req: int) -> dict:
                                       "continuous_batching": serve(False, r1)},
             "at_0.7_cb_capacity": {"rate_events_per_s": 0.7 * c_cb,
                                    "continuous_batching": serve(False, 0.7 * c_cb)},
-            "drift_calibration_side_task": {
-                "rate_events_per_s": 0.7 * c_cb,
-                "without": serve_calib(0.7 * c_cb, False),
-                "with": serve_calib(0.7 * c_cb, True)}}
+            "drift_calibration_side_task": calib_ab(0.7 * c_cb)}
 
 
 def cpu_baseline(ev, threads: int) -> dict:

@@ -29,8 +29,12 @@ from .tracker import calib_fit
 
 
 class _Hist:
-    def __init__(self, n_bins, device, eps):
-        self.h = torch.zeros((2, n_bins), dtype=torch.int32, device=device)
+    def __init__(self, n_bins, device, eps, stream):
+        # zeroed on the side stream; trackers wait for `ready` before adding
+        with torch.cuda.stream(stream):
+            self.h = torch.zeros((2, n_bins), dtype=torch.int32, device=device)
+            self.ready = torch.cuda.Event()
+            self.ready.record(stream)
         self.eps = eps          # correction the events in it were tracked with
         self.inflight = 0       # batches submitted, not yet completed
         self.events = 0         # events completed into it
@@ -47,7 +51,7 @@ class DriftCalibration:
         self.stream = torch.cuda.Stream(self.device)
         self.out = torch.zeros(3, dtype=torch.float64, device=self.device)
         self.out_host = torch.zeros(3, dtype=torch.float64).pin_memory()
-        self.cur = _Hist(n_bins, self.device, self.eps)
+        self.cur = _Hist(n_bins, self.device, self.eps, self.stream)
         self.pending = None      # closed histogram waiting for its batches
         self.fitting = None      # (histogram, done event)
         self.history = []        # (eps measured, eps after) per fit
@@ -58,6 +62,8 @@ class DriftCalibration:
         the histogram tag of the batch."""
         if self.eps != 0.0:
             trk.calib_correct_z(d_sector[:n], d_z[:n], self.eps)
+        trk.stream.wait_event(self.cur.ready)
+        self.cur.h.record_stream(trk.stream)     # used there too: not reused before it is done
         self.cur.inflight += 1
         return self.cur
 
@@ -72,7 +78,7 @@ class DriftCalibration:
                 and self.fitting is None):
             tag.closed = True
             self.pending = tag
-            self.cur = _Hist(self.n_bins, self.device, self.eps)
+            self.cur = _Hist(self.n_bins, self.device, self.eps, self.stream)
 
     def poll(self) -> bool:
         """Start a pending fit once all its batches are in; adopt a finished
@@ -95,6 +101,6 @@ class DriftCalibration:
                 self.history.append((eps_r, new))
                 self.eps = new
                 # events tracked with the old estimate go nowhere from now on
-                self.cur = _Hist(self.n_bins, self.device, self.eps)
+                self.cur = _Hist(self.n_bins, self.device, self.eps, self.stream)
                 return True
         return False

@@ -141,7 +141,7 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   s.big_rows = c.take<uint32_t>(N / 1024 + 1);
   s.start_hit = c.take<int32_t>(cap_tl);
   s.start_sr = c.take<int32_t>(cap_tl);
-  s.tl_hits = c.take<int32_t>(cap_tl * kRows);
+  s.tl_hits = c.take<int32_t>((cap_tl + 63) / 64 * 64 * kRows);
   s.tl_info = c.take<int32_t>(cap_tl * 4);
   s.tl_weight = c.take<uint32_t>(cap_tl);
   s.tl_state = c.take<float>(cap_tl * 5);
@@ -355,7 +355,7 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
   // host bounds for the persistent grids (exact counts live on the device)
   const int64_t tl_bound = std::min<int64_t>(s.cap_tl, h.n / 3 + ns);
   const int nb_lane = std::max(8, grid_stride_blocks(tl_bound, 64, 16384) / 8 * 8);
-  const int nb_wave = grid_stride_blocks(tl_bound * 64, 256, 8192);
+  const int nb_sel = grid_stride_blocks(tl_bound, 256, 4096);
   k_neighbours<<<dim3(kRows, ns), 256, 0, st>>>(s, ctx->k, g0);
   if (marks) mark(ctx, 2);
   k_clean_rows<<<dim3(kRows, ns), 256, 0, st>>>(s, g0);
@@ -365,9 +365,9 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
   if (marks) mark(ctx, 3);
   k_tracklets<<<nb_lane, 64, 0, st>>>(s, ctx->k, g0);
   if (marks) mark(ctx, 4);
-  k_select<<<nb_wave, 256, 0, st>>>(s, ctx->k, g0);
+  k_select<<<nb_sel, 256, 0, st>>>(s, ctx->k, g0);
   scan_u32(st, s.tl_sel, s.range_cnt + 0, tl_bound, s.scan_b, s.range_cnt + 1, false);
-  k_track_write<<<nb_wave, 256, 0, st>>>(s, g0);
+  k_track_write<<<nb_sel, 256, 0, st>>>(s, g0);
   if (marks) mark(ctx, 5);
   k_refit<<<grid_stride_blocks(std::max<int64_t>(1, tl_bound / 4), 64, 4096), 64, 0, st>>>(s, ctx->k, g0);
   if (marks) mark(ctx, 6);

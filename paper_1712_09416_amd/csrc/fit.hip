@@ -4,75 +4,98 @@
 
 namespace tpc {
 
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+  return v;
+}
+
 // a6: a valid tracklet becomes a track if it owns (holds the maximal weight
 // of) at least n_min_track of its hits.  Writes 1/0 per tracklet of the
 // range; the scan of these flags places the tracks.
+// Lane per tracklet; a wave walks the rows its 64 consecutive tracklets
+// span together, so each row's hit-list reads are contiguous (tile layout).
 __global__ void __launch_bounds__(256) k_select(Slot S, DevConst K, int g0) {
   const uint32_t total = S.range_cnt[0];
   const uint32_t base = S.tl_base[g0];
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
-  for (uint32_t t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < total; t += nw) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t tb = (blockIdx.x * blockDim.x + threadIdx.x) & ~63u; tb < total; tb += stride) {
+    const uint32_t t = tb + lane;
     const uint32_t T = base + t;
-    const int32_t* info = S.tl_info + (size_t)T * 4;
-    uint32_t sel = 0;
-    if (info[3]) {
-      const uint32_t w = S.tl_weight[T];
-      const int32_t* hits = S.tl_hits + (size_t)T * kRows;
-      int cnt = 0;
-      for (int r0 = info[1]; r0 <= info[2]; r0 += 64) {
-        const int r = r0 + (int)lane;
-        bool own = false;
-        if (r <= info[2]) {
-          const int32_t h = hits[r];
-          own = h >= 0 && S.weight[h] == w;
-        }
-        cnt += __popcll(__ballot(own));
+    bool valid = false;
+    int rin = 1, rout = 0;
+    uint32_t w = 0;
+    if (t < total) {
+      const int32_t* info = S.tl_info + (size_t)T * 4;
+      valid = info[3] != 0;
+      if (valid) {
+        rin = info[1];
+        rout = info[2];
+        w = S.tl_weight[T];
       }
-      sel = cnt >= K.n_min_track ? 1u : 0u;
     }
-    if (lane == 0) S.tl_sel[t] = sel;
+    const int lo = wave_min(valid ? rin : kRows), hi = wave_max(valid ? rout : -1);
+    const TlRow hits = tl_row(S, T);
+    int cnt = 0;
+    for (int r = lo; r <= hi; ++r) {
+      if (valid && r >= rin && r <= rout) {
+        const int32_t h = hits[r];
+        if (h >= 0 && S.weight[h] == w) ++cnt;
+      }
+    }
+    if (t < total) S.tl_sel[t] = valid && cnt >= K.n_min_track ? 1u : 0u;
   }
 }
 
 // Selected tracklets -> tracks of the range (in tracklet order), each with
-// its owned hits compacted (ascending row).  One wave per tracklet.
+// its owned hits compacted (ascending row).  Lane per tracklet, rows walked
+// together by the wave as in k_select.
 __global__ void __launch_bounds__(256) k_track_write(Slot S, int g0) {
   const uint32_t total = S.range_cnt[0];
   const uint32_t ntk = S.range_cnt[1];
   const uint32_t tl0 = S.tl_base[g0], tk0 = S.tk_base[g0];
   const uint32_t lane = threadIdx.x & 63;
-  const unsigned long long below = (1ull << lane) - 1ull;
-  const uint32_t nw = (gridDim.x * blockDim.x) >> 6;
-  for (uint32_t t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < total; t += nw) {
-    const uint32_t pos = S.tl_sel[t];
-    const uint32_t next = t + 1 < total ? S.tl_sel[t + 1] : ntk;
-    if (next == pos) continue;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t tb = (blockIdx.x * blockDim.x + threadIdx.x) & ~63u; tb < total; tb += stride) {
+    const uint32_t t = tb + lane;
     const uint32_t T = tl0 + t;
-    const uint32_t k = tk0 + pos;
-    const int32_t* info = S.tl_info + (size_t)T * 4;
-    const uint32_t w = S.tl_weight[T];
-    const int32_t* hits = S.tl_hits + (size_t)T * kRows;
+    bool sel = false;
+    uint32_t k = 0, w = 0;
+    int rin = 1, rout = 0;
+    if (t < total) {
+      const uint32_t pos = S.tl_sel[t];
+      const uint32_t next = t + 1 < total ? S.tl_sel[t + 1] : ntk;
+      sel = next != pos;
+      if (sel) {
+        k = tk0 + pos;
+        const int32_t* info = S.tl_info + (size_t)T * 4;
+        rin = info[1];
+        rout = info[2];
+        w = S.tl_weight[T];
+      }
+    }
+    const int lo = wave_min(sel ? rin : kRows), hi = wave_max(sel ? rout : -1);
+    const TlRow hits = tl_row(S, T);
     int32_t* own = S.tk_own + (size_t)k * kRows;
     uint8_t* own_row = S.tk_own_row + (size_t)k * kRows;
     int cnt = 0;
-    for (int rb = info[1]; rb <= info[2]; rb += 64) {
-      const int r = rb + (int)lane;
-      int32_t h = -1;
-      bool mine = false;
-      if (r <= info[2]) {
-        h = hits[r];
-        mine = h >= 0 && S.weight[h] == w;
+    for (int r = lo; r <= hi; ++r) {
+      if (sel && r >= rin && r <= rout) {
+        const int32_t h = hits[r];
+        if (h >= 0 && S.weight[h] == w) {
+          own[cnt] = h;
+          own_row[cnt] = (uint8_t)r;
+          ++cnt;
+        }
       }
-      const unsigned long long m = __ballot(mine);
-      if (mine) {
-        const int j = cnt + __popcll(m & below);
-        own[j] = h;
-        own_row[j] = (uint8_t)r;
-      }
-      cnt += __popcll(m);
     }
-    if (lane == 0) {
+    if (sel) {
       S.tk_tracklet[k] = (int32_t)T;
       S.tk_nown[k] = cnt;
     }

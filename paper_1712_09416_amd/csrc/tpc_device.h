@@ -92,7 +92,7 @@ struct Slot {
   int32_t* start_hit;       // [tl capacity] sorted index of the start hit
   int32_t* start_sr;        // [tl capacity] (sector, row) of the start hit
   // tracklets
-  int32_t* tl_hits;         // [tl capacity][kRows] sorted index per row, -1 none
+  int32_t* tl_hits;         // [tl capacity / 64][kRows][64] sorted index per row, -1 none
   int32_t* tl_info;         // [tl capacity][4]: n, row_in, row_out, valid
   uint32_t* tl_weight;      // [tl capacity]
   float* tl_state;          // [tl capacity][5] inner state (y, z, s, T, Q)
@@ -126,6 +126,18 @@ struct Slot {
   int64_t cap_tk;
   int32_t cap_e;
 };
+
+// Row-indexed hit list of tracklet T.  Stored in tiles of 64 tracklets,
+// entry (T, r) at ((T / 64) * kRows + r) * 64 + T % 64: the lanes of a
+// wave (consecutive tracklets) stepping through the same row touch
+// neighbouring words, not one cache line each.
+struct TlRow {
+  int32_t* p;
+  __device__ __forceinline__ int32_t& operator[](int r) const { return p[(size_t)r * 64]; }
+};
+__device__ __forceinline__ TlRow tl_row(const Slot& S, uint32_t T) {
+  return TlRow{S.tl_hits + (size_t)(T >> 6) * kRows * 64 + (T & 63u)};
+}
 
 // Buffers of the cross-sector merger, per slot (K = track capacity, S =
 // sectors, E = events).  Track positions are the slot's canonical output

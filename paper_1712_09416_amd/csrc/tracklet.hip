@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
     const int32_t p0 = S.start_hit[T];
     const Hit x0 = S.hit[p0];
     const Hit x1 = S.hit[x0.upc];
-    int32_t* hits = S.tl_hits + (size_t)T * kRows;
+    const TlRow hits = tl_row(S, T);
 
     Helix<float> st;
     {
