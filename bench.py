@@ -31,6 +31,39 @@ BYTES_PER_ROW_VISIT = 24
 BYTES_PER_WINDOW_HIT = 12
 
 
+# HBM bytes of one k_tracklets launch measured with rocprofv3 counters
+# (FETCH_SIZE and WRITE_SIZE runs, scaled by the factor that makes each
+# counter read a 1 GiB copy's bytes); used only while the kernel's sources
+# are those the counters were taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tracklets_central_pbpb_traffic.md")
+KERNEL_SOURCES = ("paper_1712_09416_amd/csrc/tracklet.hip", "paper_1712_09416_amd/csrc/tpc_device.h",
+                  "paper_1712_09416_amd/csrc/tpc_kernels.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """(bytes per launch, source hash) from the committed counter summary,
+    or None if absent or taken on other kernel sources."""
+    import re
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9]+)", txt)
+    hsh = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
+    if not m or not hsh or hsh.group(1) != kernel_source_hash():
+        return None
+    return int(m.group(1))
+
+
 def tracklet_bytes(cnt: dict) -> int:
     return (BYTES_PER_TRACKLET * cnt["tracklets"] + BYTES_PER_ROW_VISIT * cnt["row_visits"]
             + BYTES_PER_WINDOW_HIT * cnt["window_hits"])
@@ -401,8 +434,10 @@ def main() -> int:
 
     t_tl = stage_ms["tracklets"] * 1e-3
     ach = tracklet_bytes(counters) / t_tl / 1e9
+    traffic = measured_traffic()
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "k_tracklets",
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_tracklets",
+            "algorithmic_bytes": tracklet_bytes(counters),
             "launch_ms": stage_ms["tracklets"], "copy_kernel_gbs": copy_gbs}
 
     out = {

@@ -88,6 +88,9 @@ typedef struct tpc_params {
   int32_t max_slots;        /* slots of a context */
   int32_t max_events;       /* events per slot */
   int64_t max_clusters;     /* clusters per slot */
+  float x0_cm;              /* radiation length of the gas for the multiple-scattering
+                               noise of every transport (0: no scattering) */
+  float ms_mass;            /* particle mass of the scattering law (GeV) */
 } tpc_params;
 
 /* One output track.  par / cov are given at x_ref, the pad-row radius of

@@ -47,7 +47,8 @@ class Params(ctypes.Structure):
                 ("c_s0", ctypes.c_float), ("c_t0", ctypes.c_float), ("c_q0", ctypes.c_float),
                 ("m_edge", ctypes.c_float), ("m_z", ctypes.c_float),
                 ("n_gap", ctypes.c_int32), ("n_min_tracklet", ctypes.c_int32),
-                ("n_min_track", ctypes.c_int32)]
+                ("n_min_track", ctypes.c_int32), ("x0_cm", ctypes.c_float),
+                ("ms_mass", ctypes.c_float)]
 
 
 # The oracle's own constants for the tracker (the values this project
@@ -62,7 +63,7 @@ DEFAULT_MERGE = dict(chi2_max=30.0, row_gap=12, step_max=2.0, passes=3, s_max=0.
 
 DEFAULT_PARAMS = dict(nf_window=3.0, nf_mmax=16.0, chi2_max=16.0, k_win=4.0, w_max=5.0,
                       s_max=0.95, c_s0=1.0, c_t0=1.0, c_q0=100.0, m_edge=1.0, m_z=1.0,
-                      n_gap=6, n_min_tracklet=10, n_min_track=10)
+                      n_gap=6, n_min_tracklet=10, n_min_track=10, x0_cm=0.0, ms_mass=0.13957)
 
 TRACK_DTYPE = np.dtype([("sector", "<i4"), ("n_hits", "<i4"), ("row_in", "<i4"),
                         ("row_out", "<i4"), ("hit_off", "<i8"), ("inner_id", "<i4"),
@@ -99,6 +100,7 @@ def lib():
         L.orc_predict_f.argtypes = [P, P, f32, f32, f32]
         L.orc_predict_d.argtypes = [P, P, f64, f64, f64]
         L.orc_update_f.argtypes = [P, P, f32, f32, f32, f32, f32, f32, ctypes.c_int, P]
+        L.orc_predict_ms_d.argtypes = [P, P, f64, f64, f64, f64, f64]
         L.orc_update_d.argtypes = [P, P, f64, f64, f64, f64, f64, f64, ctypes.c_int, P]
         L.orc_merge.restype = P
         L.orc_merge.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(Params),
@@ -219,6 +221,14 @@ def predict(p, C, dx, b, smax=0.95, precision=64):
     C = np.array(C, dt)
     f = lib().orc_predict_d if precision == 64 else lib().orc_predict_f
     ok = f(_ptr(p), _ptr(C), dx, b, smax)
+    return bool(ok), p, C
+
+
+def predict_ms(p, C, dx, b, kk, m2, smax=0.95):
+    """Double transport with the scattering noise (kk = k^2/X0, m2 = mass^2)."""
+    p = np.array(p, np.float64)
+    C = np.array(C, np.float64)
+    ok = lib().orc_predict_ms_d(_ptr(p), _ptr(C), dx, b, smax, kk, m2)
     return bool(ok), p, C
 
 

@@ -53,6 +53,8 @@ struct orc_params {
   int32_t n_gap;        // consecutive missed rows that end a phase
   int32_t n_min_tracklet;
   int32_t n_min_track;
+  float x0_cm;          // radiation length of the gas for the scattering noise (0: none)
+  float ms_mass;        // particle mass assumed by the scattering law (GeV)
 };
 
 // One output track.  Values of a float run are stored exactly in double.
@@ -109,7 +111,7 @@ template <class T> T tsqrt(T v) { return std::sqrt(v); }
 // the chord times asin(u)/u expanded to u^4 (u = half the chord over the
 // radius).  Returns false if |sin phi| would exceed s_max.
 template <class T>
-bool predict(State<T>& st, T dx, T b, T smax) {
+bool predict(State<T>& st, T dx, T b, T smax, T kk = T(0), T m2 = T(0)) {
   T* p = st.p;
   T* C = st.C;
   const T s = p[2], tl = p[3], q = p[4];
@@ -183,6 +185,23 @@ bool predict(State<T>& st, T dx, T b, T smax) {
   C[11] = c41 + jzs * c42 + jzt * c43 + jzq * c44;
   C[12] = c42 + jsq * c44;
   // C[13] (QT), C[14] (QQ) unchanged
+
+  // Multiple scattering in the gas (kk = k^2/X0 > 0): plane-angle variance
+  // theta0^2 = kk L / (beta p)^2 over the step's path L = |arc| sqrt(1+T^2),
+  // with 1/(beta p)^2 = (p^2 + m^2)/p^4 = a + m^2 a^2, a = Q^2/(1+T^2)
+  // (no division by Q, no logarithm).  The angles scatter at the end of the
+  // step: var(phi) = theta0^2 (1+T^2), var(lambda) = theta0^2, and with
+  // dQ = Q T dlambda, dT = (1+T^2) dlambda, ds = cos(phi) dphi.
+  if (kk > T(0)) {
+    const T t2 = T(1) + tl * tl;
+    const T L = tabs(ds) * tsqrt(t2);
+    const T a = (q * q) / t2;
+    const T th2 = kk * L * (a + m2 * (a * a));
+    C[5] = C[5] + (T(1) - s1 * s1) * (th2 * t2);
+    C[9] = C[9] + th2 * (t2 * t2);
+    C[13] = C[13] + th2 * (q * tl * t2);
+    C[14] = C[14] + th2 * (q * q * (tl * tl));
+  }
   return true;
 }
 
@@ -259,6 +278,7 @@ struct Ctx {
   T X[kRows];
   T b, smax, chi2max, kwin, wmax, tanh, medge, mz, zmax;
   T sy0, sy1, sz0, sz1, cs0, ct0, cq0, nfw, nfm;
+  T kk, m2;             // scattering law: k^2/X0 and mass^2 (0: no scattering)
 };
 
 template <class T>
@@ -286,6 +306,17 @@ void init_ctx(Ctx<T>& c, const orc_geometry* g, const orc_params* P) {
   c.cq0 = T(P->c_q0);
   c.nfw = T(P->nf_window);
   c.nfm = T(P->nf_mmax);
+  // k = 13.6 MeV (1 + 0.038 ln(L_ref / X0)) at L_ref = 1 cm, so the
+  // variance is linear in the path: theta0^2 = (k^2 / X0) L / (beta p)^2
+  if (P->x0_cm > 0.0f) {
+    const double x0 = double(P->x0_cm);
+    const double k = 0.0136 * (1.0 + 0.038 * std::log(1.0 / x0));
+    c.kk = T(k * k / x0);
+    c.m2 = T(double(P->ms_mass) * double(P->ms_mass));
+  } else {
+    c.kk = T(0);
+    c.m2 = T(0);
+  }
 }
 
 template <class T> T sig_y(const Ctx<T>& c, T z) { return c.sy0 + c.sy1 * tabs(z) / c.zmax; }
@@ -346,7 +377,7 @@ void refit_pass(const Ctx<R>& c, const float* Y, const float* Z, const int32_t* 
   o.n = 1;
   o.chi2 = R(0);
   for (int r = ro - 1; r >= rmin; --r) {
-    if (!predict(st, c.X[r] - c.X[r + 1], c.b, c.smax)) break;
+    if (!predict(st, c.X[r] - c.X[r + 1], c.b, c.smax, c.kk, c.m2)) break;
     const int32_t h = owned_by_row[r];
     if (h < 0) continue;
     const R sy = sig_y(c, st.p[1]), sz = sig_z(c, st.p[1]);
@@ -598,7 +629,7 @@ struct Sector {
     bool chain = true;
     int miss = 0;
     for (int r = r0 + 1; r < kRows; ++r) {
-      if (!predict(st, c.X[r] - c.X[r - 1], c.b, c.smax)) break;
+      if (!predict(st, c.X[r] - c.X[r - 1], c.b, c.smax, c.kk, c.m2)) break;
       if (!inside(st, r)) break;
       const T sy = sig_y(c, st.p[1]), sz = sig_z(c, st.p[1]);
       const T vy = sy * sy, vz = sz * sz;
@@ -634,7 +665,7 @@ struct Sector {
     last = st;
     miss = 0;
     for (int r = rout - 1; r >= 0; --r) {
-      if (!predict(st, c.X[r] - c.X[r + 1], c.b, c.smax)) break;
+      if (!predict(st, c.X[r] - c.X[r + 1], c.b, c.smax, c.kk, c.m2)) break;
       if (!inside(st, r)) break;
       const T sy = sig_y(c, st.p[1]), sz = sig_z(c, st.p[1]);
       const T vy = sy * sy, vz = sz * sz;
@@ -777,13 +808,13 @@ bool rotate(State<T>& st, T& x, T ca, T sa, T b, T smax) {
 // Transport from x to xt in equal steps no longer than step_max (refused
 // beyond 1000 cm: no path inside the chamber is that long).
 template <class T>
-bool transport_to(State<T>& st, T x, T xt, T b, T smax, T step_max) {
+bool transport_to(State<T>& st, T x, T xt, T b, T smax, T step_max, T kk = T(0), T m2 = T(0)) {
   const T d = xt - x;
   if (!(tabs(d) <= T(1000))) return false;
   const int n = std::max(1, int(std::ceil(tabs(d) / step_max)));
   const T dx = d / T(n);
   for (int i = 0; i < n; ++i)
-    if (!predict(st, dx, b, smax)) return false;
+    if (!predict(st, dx, b, smax, kk, m2)) return false;
   return true;
 }
 
@@ -869,7 +900,7 @@ struct Merger {
     const int32_t* h = in.hits + t.hit_off;
     int k = 1;
     for (int r = t.row_in + 1; r <= t.row_out; ++r) {
-      if (!predict(st, c.X[r] - c.X[r - 1], c.b, c.smax)) return false;
+      if (!predict(st, c.X[r] - c.X[r - 1], c.b, c.smax, c.kk, c.m2)) return false;
       if (k < t.n_hits && int(in.row[h[k]]) == r) {
         const double sy = sig_y(c, st.p[1]), sz = sig_z(c, st.p[1]);
         update(st, double(in.Y[h[k]]), double(in.Z[h[k]]), sy * sy, sz * sz, c.chi2max, c.smax,
@@ -903,7 +934,7 @@ struct Merger {
     State<double> st = outA;
     double x = c.X[A.row_out];
     if (!rotate(st, x, ca, double(dir) * sa, c.b, c.smax)) return false;
-    if (!transport_to(st, x, c.X[B.row_in], c.b, c.smax, double(M.step_max))) return false;
+    if (!transport_to(st, x, c.X[B.row_in], c.b, c.smax, double(M.step_max), c.kk, c.m2)) return false;
     double d[5], S[15];
     for (int i = 0; i < 5; ++i) d[i] = st.p[i] - B.par[i];
     for (int i = 0; i < 15; ++i) S[i] = st.C[i] + B.cov[i];
@@ -942,7 +973,7 @@ struct Merger {
         double x = c.X[cur_row];
         if (!rotate(st, x, ca, -double(dir) * sa, c.b, c.smax)) return false;
         const int r = in.row[sg.hits[k]];
-        if (!transport_to(st, x, c.X[r], c.b, c.smax, double(M.step_max))) return false;
+        if (!transport_to(st, x, c.X[r], c.b, c.smax, double(M.step_max), c.kk, c.m2)) return false;
         const double sy = sig_y(c, st.p[1]), sz = sig_z(c, st.p[1]);
         double ch = 0.0;
         update(st, double(in.Y[sg.hits[k]]), double(in.Z[sg.hits[k]]), sy * sy, sz * sz,
@@ -956,7 +987,7 @@ struct Merger {
         const int32_t h = sg.hits[k];
         const int r = in.row[h];
         for (int rr = cur_row - 1; rr >= r; --rr)
-          if (!predict(st, c.X[rr] - c.X[rr + 1], c.b, c.smax)) return false;
+          if (!predict(st, c.X[rr] - c.X[rr + 1], c.b, c.smax, c.kk, c.m2)) return false;
         const double sy = sig_y(c, st.p[1]), sz = sig_z(c, st.p[1]);
         double ch = 0.0;
         update(st, double(in.Y[h]), double(in.Z[h]), sy * sy, sz * sz, c.chi2max, c.smax, false,
@@ -977,7 +1008,7 @@ struct Merger {
     double x = c.X[in.row[segs[0].hits.front()]];
     for (size_t j = 0; j < segs.size(); ++j) {
       const double xo = c.X[in.row[segs[j].hits.back()]];
-      if (!transport_to(st, x, xo, c.b, c.smax, double(M.step_max))) return false;
+      if (!transport_to(st, x, xo, c.b, c.smax, double(M.step_max), c.kk, c.m2)) return false;
       x = xo;
       if (j + 1 < segs.size()) {
         const int dir = neighbour(segs[j].sector, segs[j + 1].sector);
@@ -1170,7 +1201,7 @@ static bool replay_one(const OrcResult& R, const Ctx<double>& c, const orc_track
   }
   bool ok = true;
   for (int r = r0 + 1; r <= t.row_out; ++r) {
-    ok = ok && predict(st, c.X[r] - c.X[r - 1], c.b, 10.0);
+    ok = ok && predict(st, c.X[r] - c.X[r - 1], c.b, 10.0, c.kk, c.m2);
     const int32_t h = t.uhit[r];
     if (h < 0) continue;
     double vy, vz;
@@ -1182,7 +1213,7 @@ static bool replay_one(const OrcResult& R, const Ctx<double>& c, const orc_track
   st.p[1] = z(hout);
   prior(st, z(hout));
   for (int r = t.row_out - 1; r >= t.row_in; --r) {
-    ok = ok && predict(st, c.X[r] - c.X[r + 1], c.b, 10.0);
+    ok = ok && predict(st, c.X[r] - c.X[r + 1], c.b, 10.0, c.kk, c.m2);
     const int32_t h = t.dhit[r];
     if (h < 0) continue;
     double vy, vz;
@@ -1443,6 +1474,17 @@ int orc_predict_d(double* p, double* C, double dx, double b, double smax) {
   std::memcpy(st.p, p, 40);
   std::memcpy(st.C, C, 120);
   if (!predict(st, dx, b, smax)) return 0;
+  std::memcpy(p, st.p, 40);
+  std::memcpy(C, st.C, 120);
+  return 1;
+}
+
+// One double transport with the scattering noise (kk = k^2/X0, m2 = mass^2).
+int orc_predict_ms_d(double* p, double* C, double dx, double b, double smax, double kk, double m2) {
+  State<double> st;
+  std::memcpy(st.p, p, 40);
+  std::memcpy(st.C, C, 120);
+  if (!predict(st, dx, b, smax, kk, m2)) return 0;
   std::memcpy(p, st.p, 40);
   std::memcpy(C, st.C, 120);
   return 1;

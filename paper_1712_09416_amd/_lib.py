@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
                 ("n_gap", ctypes.c_int32), ("n_min_tracklet", ctypes.c_int32),
                 ("n_min_track", ctypes.c_int32), ("bin_target", ctypes.c_float),
                 ("bin_min_edge", ctypes.c_float), ("max_slots", ctypes.c_int32),
-                ("max_events", ctypes.c_int32), ("max_clusters", ctypes.c_int64)]
+                ("max_events", ctypes.c_int32), ("max_clusters", ctypes.c_int64),
+                ("x0_cm", ctypes.c_float), ("ms_mass", ctypes.c_float)]
 
 
 class MergeParams(ctypes.Structure):

@@ -243,6 +243,9 @@ bool params_ok(const tpc_params* p) {
   if (!(p->nf_window > 0.0f && p->k_win > 0.0f && p->w_max > 0.0f)) return false;
   if (!(p->c_s0 > 0.0f && p->c_t0 > 0.0f && p->c_q0 > 0.0f)) return false;
   if (!(p->bin_target > 0.0f && p->bin_min_edge > 0.0f)) return false;
+  if (!(p->x0_cm >= 0.0f && p->ms_mass >= 0.0f && std::isfinite(p->x0_cm) &&
+        std::isfinite(p->ms_mass)))
+    return false;
   return true;
 }
 
@@ -464,6 +467,8 @@ int tpc_params_default(tpc_params* p) {
   p->max_slots = 1;
   p->max_events = 1;
   p->max_clusters = 4 << 20;
+  p->x0_cm = 0.0f;
+  p->ms_mass = 0.13957f;
   return TPC_OK;
 }
 
@@ -545,6 +550,19 @@ int tpc_init_geometry(tpc_ctx** out, const tpc_geometry* g, const tpc_params* p,
   k.n_min_track = p->n_min_track;
   k.bin_target = p->bin_target;
   k.bin_min_edge = p->bin_min_edge;
+  // scattering law: theta0^2 = (k^2 / X0) L / (beta p)^2 with
+  // k = 13.6 MeV (1 + 0.038 ln(1 cm / X0)); computed in double on the host
+  if (p->x0_cm > 0.0f) {
+    const double x0 = (double)p->x0_cm;
+    const double kms = 0.0136 * (1.0 + 0.038 * std::log(1.0 / x0));
+    k.kkd = kms * kms / x0;
+    k.m2d = (double)p->ms_mass * (double)p->ms_mass;
+  } else {
+    k.kkd = 0.0;
+    k.m2d = 0.0;
+  }
+  k.kk = (float)k.kkd;
+  k.m2 = (float)k.m2d;
   Carver c{ctx->ws, 0, false};
   ctx->slots.resize(p->max_slots);
   for (int i = 0; i < p->max_slots; ++i) carve_slot(c, *p, ctx->slots[i].d, &ctx->slots[i]);

@@ -141,7 +141,7 @@ __device__ __forceinline__ void refit_pass(const Slot& S, const DevConst& K, con
   if (j >= jmin) xn = S.hit[own[j]];
   const int rstop = j >= jmin ? (int)own_row[jmin] : o.rlast;
   for (int r = o.rlast - 1; r >= rstop; --r) {
-    if (!transport(st, (double)K.row_x[r] - (double)K.row_x[r + 1], K.bd, smax)) break;
+    if (!transport(st, (double)K.row_x[r] - (double)K.row_x[r + 1], K.bd, smax, K.kkd, K.m2d)) break;
     if (r != rn) continue;
     const Hit xh = xn;
     const double sy = sy0 + sy1 * fabs(st.z) / zmax, sz = sz0 + sz1 * fabs(st.z) / zmax;

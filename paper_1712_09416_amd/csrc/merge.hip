@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(64) k_mg_outer(Slot S, DevConst K, MergeSlot M
     bool ok = true;
     int k = 1;
     for (int r = t.row_in + 1; r <= t.row_out; ++r) {
-      if (!transport(st, xrow(K, r) - xrow(K, r - 1), K.bd, C.smax)) {
+      if (!transport(st, xrow(K, r) - xrow(K, r - 1), K.bd, C.smax, K.kkd, K.m2d)) {
         ok = false;
         break;
       }
@@ -264,7 +264,7 @@ __device__ bool pair_chi2(const DevConst& K, const MergeConst& C, const tpc_trac
   for (int i = 0; i < 15; ++i) st.c[i] = oc[i];
   double x = xrow(K, A.row_out);
   if (!rotate_frame(st, x, C.ca, (double)dir * C.sa, K.bd, C.smax)) return false;
-  if (!transport_to_x(st, x, xrow(K, B.row_in), K.bd, C.smax, C.step_max)) return false;
+  if (!transport_to_x(st, x, xrow(K, B.row_in), K.bd, C.smax, C.step_max, K.kkd, K.m2d)) return false;
   double d[5], Sm[15];
   d[0] = st.y - B.par[0];
   d[1] = st.z - B.par[1];
@@ -393,7 +393,7 @@ __device__ bool chain_pass(const Slot& S, const DevConst& K, const MergeConst& C
       if (!rotate_frame(st, x, C.ca, -(double)dir * C.sa, K.bd, C.smax)) return false;
       const int64_t g = ev0 + h[k];
       const int r = S.row[g];
-      if (!transport_to_x(st, x, xrow(K, r), K.bd, C.smax, C.step_max)) return false;
+      if (!transport_to_x(st, x, xrow(K, r), K.bd, C.smax, C.step_max, K.kkd, K.m2d)) return false;
       chi2 = chi2 + update_hit(S, K, st, g);
       ++n;
       cur_row = r;
@@ -406,7 +406,7 @@ __device__ bool chain_pass(const Slot& S, const DevConst& K, const MergeConst& C
       const HitRec hr = nx;
       if (k > 0) nx = load_hit(S, ev0 + h[k - 1]);
       for (int rr = cur_row - 1; rr >= hr.row; --rr)
-        if (!transport(st, xrow(K, rr) - xrow(K, rr + 1), K.bd, C.smax)) return false;
+        if (!transport(st, xrow(K, rr) - xrow(K, rr + 1), K.bd, C.smax, K.kkd, K.m2d)) return false;
       chi2 = chi2 + update_yz(K, st, hr.y, hr.z);
       ++n;
       cur_row = hr.row;
@@ -425,7 +425,7 @@ __device__ bool carry_out(const Slot& S, const DevConst& K, const MergeConst& C,
   for (int j = 0; j < ch.n; ++j) {
     const tpc_track T = S.out_tracks[ch.pos[j]];
     const double xo = xrow(K, S.row[S.ev_off[T.event] + track_hits(S, T)[T.n_hits - 1]]);
-    if (!transport_to_x(st, x, xo, K.bd, C.smax, C.step_max)) return false;
+    if (!transport_to_x(st, x, xo, K.bd, C.smax, C.step_max, K.kkd, K.m2d)) return false;
     x = xo;
     if (j + 1 < ch.n) {
       const int dir = neighbour(T.sector, S.out_tracks[ch.pos[j + 1]].sector);

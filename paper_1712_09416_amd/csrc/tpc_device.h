@@ -38,6 +38,8 @@ struct DevConst {
   int n_gap, n_min_tracklet, n_min_track;
   float bin_target;  // clusters per grid bin aimed at
   float bin_min_edge;
+  float kk, m2;             // scattering law k^2/X0 and mass^2 (0: no scattering), float
+  double kkd, m2d;          // the same in double (refit, merger)
 };
 
 // per (sector, row) grid description
@@ -276,7 +278,8 @@ template <> __device__ __forceinline__ double sqrt_(double v) { return sqrt(v); 
 // times asin(u)/u = 1 + u^2/6 + 3u^4/40 (u = half chord * curvature).
 // Returns false, leaving the state untouched, if |sin phi| would pass smax.
 template <class F>
-__device__ __forceinline__ bool transport(Helix<F>& h, F dx, F b, F smax) {
+__device__ __forceinline__ bool transport(Helix<F>& h, F dx, F b, F smax, F kk = F(0),
+                                          F m2 = F(0)) {
   const F one = F(1), half = F(0.5), two = F(2);
   const F bq = b * h.q;
   const F s1 = h.s + bq * dx;
@@ -345,6 +348,21 @@ __device__ __forceinline__ bool transport(Helix<F>& h, F dx, F b, F smax) {
   c[10] = qy + dy_ds * qs + dy_dq * qq;
   c[11] = qz + dz_ds * qs + dz_dt * qt + dz_dq * qq;
   c[12] = qs + ds_dq * qq;
+
+  // multiple scattering at the end of the step (kk = k^2/X0 > 0):
+  // theta0^2 = kk L (a + m^2 a^2), a = Q^2/(1+T^2), L = |arc| sqrt(1+T^2);
+  // var(phi) = theta0^2 (1+T^2), var(lambda) = theta0^2, dQ = Q T dlambda,
+  // dT = (1+T^2) dlambda
+  if (kk > F(0)) {
+    const F t2 = one + h.t * h.t;
+    const F L = fabs_(arc) * sqrt_(t2);
+    const F a = (h.q * h.q) / t2;
+    const F th2 = kk * L * (a + m2 * (a * a));
+    c[5] = c[5] + (one - s1 * s1) * (th2 * t2);
+    c[9] = c[9] + th2 * (t2 * t2);
+    c[13] = c[13] + th2 * (h.q * h.t * t2);
+    c[14] = c[14] + th2 * (h.q * h.q * (h.t * h.t));
+  }
   return true;
 }
 
@@ -434,13 +452,14 @@ __device__ __forceinline__ void reset_cov(Helix<F>& h, F vy, F vz, F cs0, F ct0,
 // From x to xt in equal steps of at most step_max (refused beyond 1000 cm,
 // longer than any path in the chamber, which also bounds the step count).
 __device__ __forceinline__ bool transport_to_x(Helix<double>& h, double x, double xt, double b,
-                                               double smax, double step_max) {
+                                               double smax, double step_max, double kk = 0.0,
+                                               double m2 = 0.0) {
   const double d = xt - x;
   if (!(fabs(d) <= 1000.0)) return false;
   const int n = max(1, (int)ceil(fabs(d) / step_max));
   const double dx = d / (double)n;
   for (int i = 0; i < n; ++i)
-    if (!transport(h, dx, b, smax)) return false;
+    if (!transport(h, dx, b, smax, kk, m2)) return false;
   return true;
 }
 

@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
     for (int r = r0 + 1; r < kRows; ++r) {
       ++visits;
       const RowBins rb = S.bins[g * kRows + r];   // independent of the state: issued early
-      if (!transport(st, K.row_x[r] - K.row_x[r - 1], K.b, K.smax)) break;
+      if (!transport(st, K.row_x[r] - K.row_x[r - 1], K.b, K.smax, K.kk, K.m2)) break;
       if (!inside(K, st, r, side_c)) break;
       const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
       const float vy = sy * sy, vz = sz * sz;
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
       } else {
         uh_next = -1;
       }
-      if (!transport(st, K.row_x[r] - K.row_x[r + 1], K.b, K.smax)) break;
+      if (!transport(st, K.row_x[r] - K.row_x[r + 1], K.b, K.smax, K.kk, K.m2)) break;
       if (!inside(K, st, r, side_c)) break;
       const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
       const float vy = sy * sy, vz = sz * sz;

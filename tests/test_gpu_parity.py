@@ -28,9 +28,9 @@ def say(*a):
     print(*a, flush=True)
 
 
-def gpu_run(ev, dev, mode="event", tracker=None, links=True, geometry=None):
+def gpu_run(ev, dev, mode="event", tracker=None, links=True, geometry=None, **params):
     from paper_1712_09416_amd import Tracker
-    trk = tracker or Tracker(geometry or ev.geometry(), max_clusters=max(ev.n, 4096))
+    trk = tracker or Tracker(geometry or ev.geometry(), max_clusters=max(ev.n, 4096), **params)
     ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.sector, ev.row, ev.y, ev.z)]
     trk.load(0, *ins)
     if mode == "event":
@@ -545,3 +545,19 @@ def test_calibration_side_task_converges_while_serving(dev):
     assert st.n_requests == 90
     assert len(cal.history) >= 2
     assert abs(cal.eps - 0.004) < 2e-4, cal.eps
+
+
+
+def test_multiple_scattering_matches_oracle(dev, oracle_lib):
+    """With the scattering noise on (X0 = 3000 cm, scattered tracks): links,
+    hit lists and parameters bit-identical to the oracle; within the bar of
+    the double replay."""
+    from tpcgen import events as E
+    ev = E.ms_sector_event(1005, 200, x0_cm=3000.0)
+    ref = oracle_lib.run_event(ev, precision=32, replay=True,
+                               params=oracle_lib.make_params(x0_cm=3000.0))
+    assert ref.replay_bad == 0 and len(ref.tracks) > 100
+    tracks, hits, lk = gpu_run(ev, dev, x0_cm=3000.0)
+    compare_links(lk, ref)
+    compare_tracks(tracks, hits, ref)
+    compare_replay(tracks, ref.replay)

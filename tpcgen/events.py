@@ -369,3 +369,106 @@ def distort_drift(ev: Event, eps: float) -> Event:
     """The event with drift_z applied; truth is unchanged."""
     import dataclasses
     return dataclasses.replace(ev, z=drift_z(ev.sector, ev.z, eps), name=f"{ev.name}_drift{eps:g}")
+
+
+# ----------------------------------------------------------------------------
+# multiple scattering (a model variant: the gas as a uniform scatterer)
+# ----------------------------------------------------------------------------
+
+X0_GAS_CM = 31000.0          # radiation length of the drift gas (reading: Ne-based mix)
+PION_MASS = 0.13957          # GeV, mass assumed for the scattering law
+
+
+def ms_theta2_per_cm(x0_cm: float) -> float:
+    """k^2 / X0 of the scattering law theta0^2 = k^2 (L / X0) / (beta p)^2
+    with k = 13.6 MeV (1 + 0.038 ln(L_ref / X0)) taken at L_ref = 1 cm: the
+    plane-angle variance per cm of path is ms_theta2_per_cm / (beta p)^2."""
+    k = 0.0136 * (1.0 + 0.038 * np.log(1.0 / x0_cm))
+    return k * k / x0_cm
+
+
+def ms_sector_event(seed, n_tracks=200, x0_cm=X0_GAS_CM, pt_lo=0.2, pt_hi=2.0,
+                    noise_frac=0.05, sigma=G.SIGMA_PP) -> Event:
+    """One TPC sector (sector 0) with multiple scattering in the gas: tracks
+    from the origin (pT log-uniform, phi inside the sector, 0 <= eta < 0.9)
+    are followed from pad row to pad row on the exact circle, and at the end
+    of each step the direction receives two independent Gaussian kicks of
+    variance theta0^2 (bending plane / dip), theta0^2 = k^2/X0 * L / (beta p)^2
+    for the path L of that step; |p| is kept (no energy loss), so
+    q/pT = q / (p cos(lambda)) follows the dip.  The kick of a step is given
+    at its end, so the truth (y, z, sin phi, tan lambda, q/pT) at a crossing
+    includes the scattering of the step into it."""
+    rng = np.random.default_rng(seed)
+    pt = _pt_loguniform(rng, n_tracks, pt_lo, pt_hi)
+    q = np.where(rng.uniform(size=n_tracks) < 0.5, -1.0, 1.0)
+    phi = rng.uniform(-np.deg2rad(8.0), np.deg2rad(8.0), n_tracks)   # local azimuth
+    lam = np.arctan(np.sinh(rng.uniform(0.0, 0.9, n_tracks)))
+    p = pt / np.cos(lam)
+    b = -G.C_LIGHT * G.BZ_TESLA
+    kk = ms_theta2_per_cm(x0_cm)
+    X = G.row_x().astype(np.float64)
+    tanh = np.tan(np.deg2rad(G.SECTOR_HALF_ANGLE_DEG))
+    x = np.zeros(n_tracks)
+    y = np.zeros(n_tracks)
+    z = np.zeros(n_tracks)
+    alive = np.ones(n_tracks, bool)
+    rec = {k: [] for k in ("pid", "row", "y", "z", "s", "T", "Q")}
+    pid_all = np.arange(n_tracks)
+    for r in range(G.N_ROWS):
+        Q = q / (p * np.cos(lam))          # q / pT, pT = p cos(lambda)
+        s0 = np.sin(phi)
+        dx = X[r] - x
+        s1 = s0 + b * Q * dx
+        alive &= np.abs(s1) < 0.999
+        s1 = np.clip(s1, -0.999, 0.999)
+        c0, c1 = np.sqrt(1 - s0 * s0), np.sqrt(1 - s1 * s1)
+        y = y + dx * (s0 + s1) / (c0 + c1)
+        dphi = np.arcsin(s1) - np.arcsin(s0)
+        bq = b * Q
+        with np.errstate(divide="ignore", invalid="ignore"):
+            lperp = np.where(np.abs(bq) > 1e-12, dphi / bq, dx * np.sqrt(1 + ((s0 + s1) / (c0 + c1)) ** 2))
+        T = np.tan(lam)
+        z = z + T * lperp
+        x = np.full(n_tracks, X[r])
+        phi = np.arcsin(s1)
+        # the step's scattering, at its end (before this row's crossing is
+        # recorded, as the fit adds a step's noise before that row's update)
+        L = lperp * np.sqrt(1 + T * T)
+        beta2p2 = p * p * p * p / (p * p + PION_MASS ** 2)        # (beta p)^2
+        th = np.sqrt(kk * np.abs(L) / beta2p2)
+        phi = phi + th * rng.normal(size=n_tracks) / np.cos(lam)
+        lam = lam + th * rng.normal(size=n_tracks)
+        alive &= (np.abs(y) <= X[r] * tanh) & (np.abs(z) <= G.Z_MAX) & (np.abs(np.sin(phi)) < 0.999)
+        sel = np.nonzero(alive)[0]
+        for k, v in (("pid", pid_all), ("row", np.full(n_tracks, r)), ("y", y), ("z", z),
+                     ("s", np.sin(phi)), ("T", np.tan(lam)), ("Q", q / (p * np.cos(lam)))):
+            rec[k].append(v[sel])
+    c = {k: np.concatenate(v) for k, v in rec.items()}
+    nsig = len(c["y"])
+    keep = np.ones(nsig, bool)
+    sy = _sigma(sigma[0], sigma[1], c["z"])
+    sz = _sigma(sigma[2], sigma[3], c["z"])
+    ym = c["y"] + rng.normal(size=nsig) * sy
+    zm = c["z"] + rng.normal(size=nsig) * sz
+    nnoise = int(round(noise_frac * nsig))
+    nrow = rng.integers(0, G.N_ROWS, nnoise)
+    ny = rng.uniform(-1.0, 1.0, nnoise) * X[nrow] * tanh
+    nz = rng.uniform(0.0, G.Z_MAX, nnoise)
+    N = nsig + nnoise
+    sector = np.zeros(N, np.uint8)
+    row = np.concatenate([c["row"], nrow]).astype(np.uint8)
+    yy = np.concatenate([ym, ny]).astype(np.float32)
+    zz = np.concatenate([zm, nz]).astype(np.float32)
+    pid = np.concatenate([c["pid"], np.full(nnoise, -1)]).astype(np.int32)
+    leg = np.concatenate([np.zeros(nsig, np.int32), np.full(nnoise, -1)]).astype(np.int32)
+    truth = np.full((N, 5), np.nan)
+    truth[:nsig] = np.stack([c["y"], c["z"], c["s"], c["T"], c["Q"]], axis=1)
+    qq = (30.0 + rng.exponential(40.0, N)).astype(np.float32)
+    perm = rng.permutation(N)
+    del keep
+    particles = dict(vx=np.zeros(n_tracks), vy=np.zeros(n_tracks), vz=np.zeros(n_tracks), pt=pt,
+                     phi=phi, eta=np.arcsinh(np.tan(lam)), charge=q,
+                     kind=np.zeros(n_tracks, np.int8))
+    return Event(name=f"ms_sector_{n_tracks}", seed=seed, sector=sector[perm], row=row[perm],
+                 y=yy[perm], z=zz[perm], q=qq[perm], pid=pid[perm], leg=leg[perm],
+                 truth=truth[perm], sigma=tuple(float(s) for s in sigma), particles=particles)
