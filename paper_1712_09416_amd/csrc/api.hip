@@ -14,7 +14,7 @@ using namespace tpc;
 namespace {
 
 constexpr int kScanTile = 1024;
-constexpr int64_t kCountChunkHost = 16384;   // clusters per block of k_count
+constexpr int64_t kCountChunkHost = 4096;    // clusters per block of k_count
 
 struct SlotHost {
   Slot d{};
@@ -127,9 +127,6 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   s.row_bin = c.take<uint32_t>(SR + 1);
   s.bin_off = c.take<uint32_t>(N + SR + 1);
   s.rank = c.take<uint32_t>(N);
-  s.ty = c.take<float>(N);
-  s.tz = c.take<float>(N);
-  s.tid = c.take<uint32_t>(N);
   s.hit = c.take<Hit>(N);
   s.up = c.take<int32_t>(N);
   s.dn = c.take<int32_t>(N);
@@ -979,10 +976,15 @@ int tpc_get_links(tpc_ctx* ctx, int slot, int event, int32_t* up, int32_t* dn, i
   SlotHost& h = ctx->slots[slot];
   if (h.state < 3) return ctx->fail(TPC_ESTATE, "slot not tracked");
   if (event < 0 || event >= h.n_events) return ctx->fail(TPC_EINVAL, "event out of range");
+  if (h.state == 3) {                  // the scratch below is free once finalised
+    const int rc = finalize(ctx, h);
+    if (rc) return rc;
+  }
   const int64_t ne = h.ev_off[event + 1] - h.ev_off[event];
   hipStream_t st = ctx->stream;
-  int32_t* tmp[4] = {reinterpret_cast<int32_t*>(h.d.rank), reinterpret_cast<int32_t*>(h.d.ty),
-                     reinterpret_cast<int32_t*>(h.d.tz), reinterpret_cast<int32_t*>(h.d.tid)};
+  // per-cluster buffers no longer needed after the canonical ordering
+  int32_t* tmp[4] = {reinterpret_cast<int32_t*>(h.d.rank), reinterpret_cast<int32_t*>(h.d.scan_a),
+                     h.d.tmap, reinterpret_cast<int32_t*>(h.d.weight)};
   for (int k = 0; k < 4; ++k) k_fill_i32<<<grid_stride_blocks(ne, 256), 256, 0, st>>>(tmp[k], ne, -1);
   k_links_out<<<grid_stride_blocks(ne, 256), 256, 0, st>>>(h.d, event, tmp[0], tmp[1], tmp[2], tmp[3]);
   TPC_LAUNCHED();

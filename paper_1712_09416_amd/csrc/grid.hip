@@ -26,7 +26,7 @@ __device__ __forceinline__ int event_of(const int64_t* ev_off, int n_events, int
 // One block per chunk of kCountChunk clusters of one event (blockIdx.y):
 // ranks are taken in an LDS histogram of the event's rows, then one global
 // atomic per row and block reserves the block's range.
-constexpr int kCountChunk = 16384;
+constexpr int kCountChunk = 4096;
 constexpr int kEventRows = kSectorsPerEvent * kRows;
 
 __global__ void __launch_bounds__(256) k_count(Slot S) {
@@ -128,7 +128,8 @@ __global__ void k_row_finish(Slot S) {
   }
 }
 
-// a2: clusters to their row (arrival order within the row)
+// a2: clusters to their row (arrival order within the row), as hit
+// records; the row sort then orders each row in place
 __global__ void k_scatter(Slot S) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n; i += stride) {
@@ -137,9 +138,12 @@ __global__ void k_scatter(Slot S) {
     const int e = event_of(S.ev_off, S.n_events, i);
     const int sr = (e * kSectorsPerEvent + S.sector[i]) * kRows + S.row[i];
     const uint32_t pos = S.row_off[sr] + rk;
-    S.ty[pos] = S.y[i];
-    S.tz[pos] = S.z[i];
-    S.tid[pos] = (uint32_t)i;
+    Hit h;                               // one 16-byte store per cluster
+    h.y = S.y[i];
+    h.z = S.z[i];
+    h.id = (uint32_t)i;
+    h.upc = -1;
+    S.hit[pos] = h;
   }
 }
 
@@ -173,7 +177,7 @@ __device__ __forceinline__ void row_sort(Slot& S, int sr, bool small) {
       Hit h;
       h.y = __builtin_nanf("");
       h.z = __builtin_nanf("");
-      h.id = S.tid[off + j];
+      h.id = S.hit[off + j].id;
       h.upc = -1;
       S.hit[off + j] = h;
     }
@@ -183,10 +187,11 @@ __device__ __forceinline__ void row_sort(Slot& S, int sr, bool small) {
   for (int bb = threadIdx.x; bb <= nb; bb += blockDim.x) hist[bb] = 0u;
   __syncthreads();
   for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
-    const float y = S.ty[off + j], z = S.tz[off + j];
+    const Hit hr = S.hit[off + j];
+    const float y = hr.y, z = hr.z;
     ly[j] = y;
     lz[j] = z;
-    lid[j] = S.tid[off + j];
+    lid[j] = hr.id;
     const uint32_t bin = (uint32_t)(bin_z(b, z) * b.ny + bin_y(b, y));
     lbin[j] = (uint16_t)bin;
     lrank[j] = (uint16_t)atomicAdd(&hist[bin], 1u);

@@ -77,9 +77,6 @@ struct Slot {
   uint32_t* row_bin;        // [SR+1] bins per row, then the rows' first bin
   uint32_t* bin_off;        // [n + SR + 1]
   uint32_t* rank;           // [n]
-  float* ty;                // [n] row-ordered, unsorted within a row
-  float* tz;
-  uint32_t* tid;
   Hit* hit;                 // [n] sorted by (sector, row, bin, id)
   // links (sorted-hit indices, -1 none); the cleaned up-link lives in hit[].upc
   int32_t* up;
