@@ -104,6 +104,10 @@ struct State {
 
 template <class T> T tabs(T v) { return v < T(0) ? -v : v; }
 template <class T> T tsqrt(T v) { return std::sqrt(v); }
+// a*b + c rounded once (IEEE fused multiply-add): every sum of products of
+// the Kalman filter below is written as a chain of these, the same chain as
+// in the GPU code, so both round at exactly the same points
+template <class T> T tfma(T a, T b, T c) { return std::fma(a, b, c); }
 
 // Transport by dx along the helix with curvature b*Q (b = -c*Bz).  The
 // circle is exact: sin phi is linear in x, y advances by dx times the tangent
@@ -116,20 +120,20 @@ bool predict(State<T>& st, T dx, T b, T smax, T kk = T(0), T m2 = T(0)) {
   T* C = st.C;
   const T s = p[2], tl = p[3], q = p[4];
   const T bq = b * q;
-  const T s1 = s + bq * dx;
+  const T s1 = tfma(bq, dx, s);
   if (!(tabs(s1) <= smax)) return false;
-  const T c0 = tsqrt(T(1) - s * s);
-  const T c1 = tsqrt(T(1) - s1 * s1);
+  const T c0 = tsqrt(tfma(-s, s, T(1)));
+  const T c1 = tsqrt(tfma(-s1, s1, T(1)));
   const T N = s + s1;
   const T D = c0 + c1;
   const T iD = T(1) / D;
   const T ic0 = T(1) / c0;
   const T ic1 = T(1) / c1;
   const T t = N * iD;
-  const T dl = tabs(dx) * tsqrt(T(1) + t * t);
+  const T dl = tabs(dx) * tsqrt(tfma(t, t, T(1)));
   const T u = T(0.5) * bq * dl;
   const T u2 = u * u;
-  T ds = dl * (T(1) + u2 * (T(1) / T(6) + u2 * (T(3) / T(40))));
+  T ds = dl * tfma(u2, tfma(u2, T(3) / T(40), T(1) / T(6)), T(1));
   if (dx < T(0)) ds = -ds;
 
   // Jacobian d(y1, z1, s1)/d(s, T, Q); the other entries are those of the
@@ -139,15 +143,15 @@ bool predict(State<T>& st, T dx, T b, T smax, T kk = T(0), T m2 = T(0)) {
   const T iD2 = iD * iD;
   const T sc0 = s * ic0;
   const T sc1 = s1 * ic1;
-  const T jys = dx * (T(2) * D + N * (sc0 + sc1)) * iD2;
-  const T jyq = b * dx * dx * (D + N * sc1) * iD2;
+  const T jys = dx * tfma(N, sc0 + sc1, T(2) * D) * iD2;
+  const T jyq = b * dx * dx * tfma(N, sc1, D) * iD2;
   const T jzs = tl * dx * N * (ic0 * ic1 * iD);
   const T jzt = ds;
   const T jzq = T(2) * tl * b * N * dx * dx * (iD2 * iD);
   const T jsq = b * dx;
 
-  p[0] = p[0] + dx * t;
-  p[1] = p[1] + tl * ds;
+  p[0] = tfma(dx, t, p[0]);
+  p[1] = tfma(tl, ds, p[1]);
   p[2] = s1;
 
   // C <- J C J^T, first A = J C (rows y, z, s change), then A J^T.
@@ -155,35 +159,35 @@ bool predict(State<T>& st, T dx, T b, T smax, T kk = T(0), T m2 = T(0)) {
   const T c30 = C[6], c31 = C[7], c32 = C[8], c33 = C[9];
   const T c40 = C[10], c41 = C[11], c42 = C[12], c43 = C[13], c44 = C[14];
 
-  const T a00 = c00 + jys * c20 + jyq * c40;
-  const T a02 = c20 + jys * c22 + jyq * c42;
-  const T a04 = c40 + jys * c42 + jyq * c44;
+  const T a00 = tfma(jyq, c40, tfma(jys, c20, c00));
+  const T a02 = tfma(jyq, c42, tfma(jys, c22, c20));
+  const T a04 = tfma(jyq, c44, tfma(jys, c42, c40));
 
-  const T a10 = c10 + jzs * c20 + jzt * c30 + jzq * c40;
-  const T a11 = c11 + jzs * c21 + jzt * c31 + jzq * c41;
-  const T a12 = c21 + jzs * c22 + jzt * c32 + jzq * c42;
-  const T a13 = c31 + jzs * c32 + jzt * c33 + jzq * c43;
-  const T a14 = c41 + jzs * c42 + jzt * c43 + jzq * c44;
+  const T a10 = tfma(jzq, c40, tfma(jzt, c30, tfma(jzs, c20, c10)));
+  const T a11 = tfma(jzq, c41, tfma(jzt, c31, tfma(jzs, c21, c11)));
+  const T a12 = tfma(jzq, c42, tfma(jzt, c32, tfma(jzs, c22, c21)));
+  const T a13 = tfma(jzq, c43, tfma(jzt, c33, tfma(jzs, c32, c31)));
+  const T a14 = tfma(jzq, c44, tfma(jzt, c43, tfma(jzs, c42, c41)));
 
-  const T a20 = c20 + jsq * c40;
-  const T a21 = c21 + jsq * c41;
-  const T a22 = c22 + jsq * c42;
-  const T a23 = c32 + jsq * c43;
-  const T a24 = c42 + jsq * c44;
+  const T a20 = tfma(jsq, c40, c20);
+  const T a21 = tfma(jsq, c41, c21);
+  const T a22 = tfma(jsq, c42, c22);
+  const T a23 = tfma(jsq, c43, c32);
+  const T a24 = tfma(jsq, c44, c42);
 
-  C[0] = a00 + jys * a02 + jyq * a04;
-  C[1] = a10 + jys * a12 + jyq * a14;
-  C[2] = a11 + jzs * a12 + jzt * a13 + jzq * a14;
-  C[3] = a20 + jys * a22 + jyq * a24;
-  C[4] = a21 + jzs * a22 + jzt * a23 + jzq * a24;
-  C[5] = a22 + jsq * a24;
-  C[6] = c30 + jys * c32 + jyq * c43;
-  C[7] = c31 + jzs * c32 + jzt * c33 + jzq * c43;
-  C[8] = c32 + jsq * c43;
+  C[0] = tfma(jyq, a04, tfma(jys, a02, a00));
+  C[1] = tfma(jyq, a14, tfma(jys, a12, a10));
+  C[2] = tfma(jzq, a14, tfma(jzt, a13, tfma(jzs, a12, a11)));
+  C[3] = tfma(jyq, a24, tfma(jys, a22, a20));
+  C[4] = tfma(jzq, a24, tfma(jzt, a23, tfma(jzs, a22, a21)));
+  C[5] = tfma(jsq, a24, a22);
+  C[6] = tfma(jyq, c43, tfma(jys, c32, c30));
+  C[7] = tfma(jzq, c43, tfma(jzt, c33, tfma(jzs, c32, c31)));
+  C[8] = tfma(jsq, c43, c32);
   // C[9] (TT) unchanged
-  C[10] = c40 + jys * c42 + jyq * c44;
-  C[11] = c41 + jzs * c42 + jzt * c43 + jzq * c44;
-  C[12] = c42 + jsq * c44;
+  C[10] = tfma(jyq, c44, tfma(jys, c42, c40));
+  C[11] = tfma(jzq, c44, tfma(jzt, c43, tfma(jzs, c42, c41)));
+  C[12] = tfma(jsq, c44, c42);
   // C[13] (QT), C[14] (QQ) unchanged
 
   // Multiple scattering in the gas (kk = k^2/X0 > 0): plane-angle variance
@@ -193,14 +197,14 @@ bool predict(State<T>& st, T dx, T b, T smax, T kk = T(0), T m2 = T(0)) {
   // step: var(phi) = theta0^2 (1+T^2), var(lambda) = theta0^2, and with
   // dQ = Q T dlambda, dT = (1+T^2) dlambda, ds = cos(phi) dphi.
   if (kk > T(0)) {
-    const T t2 = T(1) + tl * tl;
+    const T t2 = tfma(tl, tl, T(1));
     const T L = tabs(ds) * tsqrt(t2);
     const T a = (q * q) / t2;
-    const T th2 = kk * L * (a + m2 * (a * a));
-    C[5] = C[5] + (T(1) - s1 * s1) * (th2 * t2);
-    C[9] = C[9] + th2 * (t2 * t2);
-    C[13] = C[13] + th2 * (q * tl * t2);
-    C[14] = C[14] + th2 * (q * q * (tl * tl));
+    const T th2 = kk * L * tfma(m2, a * a, a);
+    C[5] = tfma(tfma(-s1, s1, T(1)), th2 * t2, C[5]);
+    C[9] = tfma(th2, t2 * t2, C[9]);
+    C[13] = tfma(th2, q * tl * t2, C[13]);
+    C[14] = tfma(th2, q * q * (tl * tl), C[14]);
   }
   return true;
 }
@@ -217,7 +221,7 @@ Gain2<T> weights(const State<T>& st, T vy, T vz) {
   const T s00 = st.C[0] + vy;
   const T s01 = st.C[1];
   const T s11 = st.C[2] + vz;
-  const T det = s00 * s11 - s01 * s01;
+  const T det = tfma(s00, s11, -(s01 * s01));
   const T idet = T(1) / det;
   g.w00 = s11 * idet;
   g.w01 = -s01 * idet;
@@ -229,7 +233,7 @@ Gain2<T> weights(const State<T>& st, T vy, T vz) {
 
 template <class T>
 T chi2_of(const Gain2<T>& g, T ry, T rz) {
-  return ry * (g.w00 * ry + g.w01 * rz) + rz * (g.w01 * ry + g.w11 * rz);
+  return tfma(ry, tfma(g.w00, ry, g.w01 * rz), rz * tfma(g.w01, ry, g.w11 * rz));
 }
 
 // Kalman update with the measured (my, mz).  With `gated` the update is
@@ -249,15 +253,15 @@ bool update(State<T>& st, T my, T mz, T vy, T vz, T chi2max, T smax, bool gated,
   const T col1[5] = {C[1], C[2], C[4], C[7], C[11]};  // C(i, z)
   T k0[5], k1[5];
   for (int i = 0; i < 5; ++i) {
-    k0[i] = col0[i] * g.w00 + col1[i] * g.w01;
-    k1[i] = col0[i] * g.w01 + col1[i] * g.w11;
+    k0[i] = tfma(col0[i], g.w00, col1[i] * g.w01);
+    k1[i] = tfma(col0[i], g.w01, col1[i] * g.w11);
   }
   State<T> nx;
-  for (int i = 0; i < 5; ++i) nx.p[i] = st.p[i] + (k0[i] * ry + k1[i] * rz);
+  for (int i = 0; i < 5; ++i) nx.p[i] = tfma(k0[i], ry, tfma(k1[i], rz, st.p[i]));
   int idx = 0;
   for (int i = 0; i < 5; ++i)
     for (int j = 0; j <= i; ++j, ++idx)
-      nx.C[idx] = C[idx] - (k0[i] * col0[j] + k1[i] * col1[j]);
+      nx.C[idx] = tfma(-k0[i], col0[j], tfma(-k1[i], col1[j], C[idx]));
   if (gated) {
     if (!(nx.C[0] > T(0) && nx.C[2] > T(0) && nx.C[5] > T(0) && nx.C[9] > T(0) &&
           nx.C[14] > T(0) && tabs(nx.p[2]) < smax))

@@ -268,6 +268,12 @@ template <> __device__ __forceinline__ double fabs_(double v) { return fabs(v); 
 template <class F> __device__ __forceinline__ F sqrt_(F v);
 template <> __device__ __forceinline__ float sqrt_(float v) { return sqrtf(v); }
 template <> __device__ __forceinline__ double sqrt_(double v) { return sqrt(v); }
+// a*b + c rounded once.  Every sum of products of the filter is a chain of
+// these in a fixed order (the CPU checker uses the same chains), so results
+// stay bit-identical with contraction switched off for everything else.
+template <class F> __device__ __forceinline__ F fma_(F a, F b, F c);
+template <> __device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
 
 // Move the state by dx along the circle of curvature b*q.  sin(phi) grows
 // linearly with x; y advances by dx times the tangent of the mid-angle
@@ -279,21 +285,21 @@ __device__ __forceinline__ bool transport(Helix<F>& h, F dx, F b, F smax, F kk =
                                           F m2 = F(0)) {
   const F one = F(1), half = F(0.5), two = F(2);
   const F bq = b * h.q;
-  const F s1 = h.s + bq * dx;
+  const F s1 = fma_(bq, dx, h.s);
   if (!(fabs_(s1) <= smax)) return false;
   const F s0 = h.s;
-  const F c0 = sqrt_(one - s0 * s0);
-  const F c1 = sqrt_(one - s1 * s1);
+  const F c0 = sqrt_(fma_(-s0, s0, one));
+  const F c1 = sqrt_(fma_(-s1, s1, one));
   const F N = s0 + s1;
   const F D = c0 + c1;
   const F iD = one / D;
   const F ic0 = one / c0;
   const F ic1 = one / c1;
   const F tmid = N * iD;
-  const F chord = fabs_(dx) * sqrt_(one + tmid * tmid);
+  const F chord = fabs_(dx) * sqrt_(fma_(tmid, tmid, one));
   const F u = half * bq * chord;
   const F u2 = u * u;
-  F arc = chord * (one + u2 * (one / F(6) + u2 * (F(3) / F(40))));
+  F arc = chord * fma_(u2, fma_(u2, F(3) / F(40), one / F(6)), one);
   if (dx < F(0)) arc = -arc;
 
   // Jacobian; dz/dQ to leading order, 2 T b N dx^2 / D^3 (the mid-angle
@@ -301,15 +307,15 @@ __device__ __forceinline__ bool transport(Helix<F>& h, F dx, F b, F smax, F kk =
   const F iD2 = iD * iD;
   const F r0 = s0 * ic0;
   const F r1 = s1 * ic1;
-  const F dy_ds = dx * (two * D + N * (r0 + r1)) * iD2;
-  const F dy_dq = b * dx * dx * (D + N * r1) * iD2;
+  const F dy_ds = dx * fma_(N, r0 + r1, two * D) * iD2;
+  const F dy_dq = b * dx * dx * fma_(N, r1, D) * iD2;
   const F dz_ds = h.t * dx * N * (ic0 * ic1 * iD);
   const F dz_dt = arc;
   const F dz_dq = two * h.t * b * N * dx * dx * (iD2 * iD);
   const F ds_dq = b * dx;
 
-  h.y = h.y + dx * tmid;
-  h.z = h.z + h.t * arc;
+  h.y = fma_(dx, tmid, h.y);
+  h.z = fma_(h.t, arc, h.z);
   h.s = s1;
 
   F* c = h.c;
@@ -317,48 +323,48 @@ __device__ __forceinline__ bool transport(Helix<F>& h, F dx, F b, F smax, F kk =
   const F ty = c[6], tz = c[7], ts = c[8], tt = c[9];
   const F qy = c[10], qz = c[11], qs = c[12], qt = c[13], qq = c[14];
 
-  // rows y, z, s of J*C
-  const F jy_y = yy + dy_ds * sy + dy_dq * qy;
-  const F jy_s = sy + dy_ds * ss + dy_dq * qs;
-  const F jy_q = qy + dy_ds * qs + dy_dq * qq;
-  const F jz_y = zy + dz_ds * sy + dz_dt * ty + dz_dq * qy;
-  const F jz_z = zz + dz_ds * sz + dz_dt * tz + dz_dq * qz;
-  const F jz_s = sz + dz_ds * ss + dz_dt * ts + dz_dq * qs;
-  const F jz_t = tz + dz_ds * ts + dz_dt * tt + dz_dq * qt;
-  const F jz_q = qz + dz_ds * qs + dz_dt * qt + dz_dq * qq;
-  const F js_y = sy + ds_dq * qy;
-  const F js_z = sz + ds_dq * qz;
-  const F js_s = ss + ds_dq * qs;
-  const F js_t = ts + ds_dq * qt;
-  const F js_q = qs + ds_dq * qq;
+  // rows y, z, s of J*C (the columns that the product below reads)
+  const F jy_y = fma_(dy_dq, qy, fma_(dy_ds, sy, yy));
+  const F jy_s = fma_(dy_dq, qs, fma_(dy_ds, ss, sy));
+  const F jy_q = fma_(dy_dq, qq, fma_(dy_ds, qs, qy));
+  const F jz_y = fma_(dz_dq, qy, fma_(dz_dt, ty, fma_(dz_ds, sy, zy)));
+  const F jz_z = fma_(dz_dq, qz, fma_(dz_dt, tz, fma_(dz_ds, sz, zz)));
+  const F jz_s = fma_(dz_dq, qs, fma_(dz_dt, ts, fma_(dz_ds, ss, sz)));
+  const F jz_t = fma_(dz_dq, qt, fma_(dz_dt, tt, fma_(dz_ds, ts, tz)));
+  const F jz_q = fma_(dz_dq, qq, fma_(dz_dt, qt, fma_(dz_ds, qs, qz)));
+  const F js_y = fma_(ds_dq, qy, sy);
+  const F js_z = fma_(ds_dq, qz, sz);
+  const F js_s = fma_(ds_dq, qs, ss);
+  const F js_t = fma_(ds_dq, qt, ts);
+  const F js_q = fma_(ds_dq, qq, qs);
 
-  // (J*C)*J^T, lower triangle
-  c[0] = jy_y + dy_ds * jy_s + dy_dq * jy_q;
-  c[1] = jz_y + dy_ds * jz_s + dy_dq * jz_q;
-  c[2] = jz_z + dz_ds * jz_s + dz_dt * jz_t + dz_dq * jz_q;
-  c[3] = js_y + dy_ds * js_s + dy_dq * js_q;
-  c[4] = js_z + dz_ds * js_s + dz_dt * js_t + dz_dq * js_q;
-  c[5] = js_s + ds_dq * js_q;
-  c[6] = ty + dy_ds * ts + dy_dq * qt;
-  c[7] = tz + dz_ds * ts + dz_dt * tt + dz_dq * qt;
-  c[8] = ts + ds_dq * qt;
-  c[10] = qy + dy_ds * qs + dy_dq * qq;
-  c[11] = qz + dz_ds * qs + dz_dt * qt + dz_dq * qq;
-  c[12] = qs + ds_dq * qq;
+  // (J*C)*J^T, lower triangle; TT, QT, QQ unchanged
+  c[0] = fma_(dy_dq, jy_q, fma_(dy_ds, jy_s, jy_y));
+  c[1] = fma_(dy_dq, jz_q, fma_(dy_ds, jz_s, jz_y));
+  c[2] = fma_(dz_dq, jz_q, fma_(dz_dt, jz_t, fma_(dz_ds, jz_s, jz_z)));
+  c[3] = fma_(dy_dq, js_q, fma_(dy_ds, js_s, js_y));
+  c[4] = fma_(dz_dq, js_q, fma_(dz_dt, js_t, fma_(dz_ds, js_s, js_z)));
+  c[5] = fma_(ds_dq, js_q, js_s);
+  c[6] = fma_(dy_dq, qt, fma_(dy_ds, ts, ty));
+  c[7] = fma_(dz_dq, qt, fma_(dz_dt, tt, fma_(dz_ds, ts, tz)));
+  c[8] = fma_(ds_dq, qt, ts);
+  c[10] = fma_(dy_dq, qq, fma_(dy_ds, qs, qy));
+  c[11] = fma_(dz_dq, qq, fma_(dz_dt, qt, fma_(dz_ds, qs, qz)));
+  c[12] = fma_(ds_dq, qq, qs);
 
   // multiple scattering at the end of the step (kk = k^2/X0 > 0):
   // theta0^2 = kk L (a + m^2 a^2), a = Q^2/(1+T^2), L = |arc| sqrt(1+T^2);
   // var(phi) = theta0^2 (1+T^2), var(lambda) = theta0^2, dQ = Q T dlambda,
   // dT = (1+T^2) dlambda
   if (kk > F(0)) {
-    const F t2 = one + h.t * h.t;
+    const F t2 = fma_(h.t, h.t, one);
     const F L = fabs_(arc) * sqrt_(t2);
     const F a = (h.q * h.q) / t2;
-    const F th2 = kk * L * (a + m2 * (a * a));
-    c[5] = c[5] + (one - s1 * s1) * (th2 * t2);
-    c[9] = c[9] + th2 * (t2 * t2);
-    c[13] = c[13] + th2 * (h.q * h.t * t2);
-    c[14] = c[14] + th2 * (h.q * h.q * (h.t * h.t));
+    const F th2 = kk * L * fma_(m2, a * a, a);
+    c[5] = fma_(fma_(-s1, s1, one), th2 * t2, c[5]);
+    c[9] = fma_(th2, t2 * t2, c[9]);
+    c[13] = fma_(th2, h.q * h.t * t2, c[13]);
+    c[14] = fma_(th2, h.q * h.q * (h.t * h.t), c[14]);
   }
   return true;
 }
@@ -375,7 +381,7 @@ __device__ __forceinline__ Resid<F> resid_weights(const Helix<F>& h, F vy, F vz)
   const F s00 = h.c[0] + vy;
   const F s01 = h.c[1];
   const F s11 = h.c[2] + vz;
-  const F det = s00 * s11 - s01 * s01;
+  const F det = fma_(s00, s11, -(s01 * s01));
   const F inv = F(1) / det;
   r.w00 = s11 * inv;
   r.w01 = -s01 * inv;
@@ -387,7 +393,7 @@ __device__ __forceinline__ Resid<F> resid_weights(const Helix<F>& h, F vy, F vz)
 
 template <class F>
 __device__ __forceinline__ F chi2_of(const Resid<F>& w, F ry, F rz) {
-  return ry * (w.w00 * ry + w.w01 * rz) + rz * (w.w01 * ry + w.w11 * rz);
+  return fma_(ry, fma_(w.w00, ry, w.w01 * rz), rz * fma_(w.w01, ry, w.w11 * rz));
 }
 
 // Kalman update with the measurement (my, mz).  gated: refuse (state
@@ -409,20 +415,20 @@ __device__ __forceinline__ bool kalman_update(Helix<F>& h, F my, F mz, F vy, F v
   F ky[5], kz[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    ky[i] = cy[i] * w.w00 + cz[i] * w.w01;
-    kz[i] = cy[i] * w.w01 + cz[i] * w.w11;
+    ky[i] = fma_(cy[i], w.w00, cz[i] * w.w01);
+    kz[i] = fma_(cy[i], w.w01, cz[i] * w.w11);
   }
   Helix<F> o;
-  o.y = h.y + (ky[0] * ry + kz[0] * rz);
-  o.z = h.z + (ky[1] * ry + kz[1] * rz);
-  o.s = h.s + (ky[2] * ry + kz[2] * rz);
-  o.t = h.t + (ky[3] * ry + kz[3] * rz);
-  o.q = h.q + (ky[4] * ry + kz[4] * rz);
+  o.y = fma_(ky[0], ry, fma_(kz[0], rz, h.y));
+  o.z = fma_(ky[1], ry, fma_(kz[1], rz, h.z));
+  o.s = fma_(ky[2], ry, fma_(kz[2], rz, h.s));
+  o.t = fma_(ky[3], ry, fma_(kz[3], rz, h.t));
+  o.q = fma_(ky[4], ry, fma_(kz[4], rz, h.q));
   int k = 0;
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
 #pragma unroll
-    for (int j = 0; j <= i; ++j, ++k) o.c[k] = c[k] - (ky[i] * cy[j] + kz[i] * cz[j]);
+    for (int j = 0; j <= i; ++j, ++k) o.c[k] = fma_(-ky[i], cy[j], fma_(-kz[i], cz[j], c[k]));
   }
   if (gated) {
     if (!(o.c[0] > F(0) && o.c[2] > F(0) && o.c[5] > F(0) && o.c[9] > F(0) && o.c[14] > F(0) &&
