@@ -15,6 +15,28 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+// Rows are walked kRowBatch at a time: the hit-list entries of a batch are
+// loaded together, then the weights of their hits, so a batch costs two
+// memory round trips instead of two per row.
+constexpr int kRowBatch = 8;
+
+// hv[u] = the tracklet's hit in row r0+u if that row is inside [rin, rout]
+// of an active lane, else -1 (rows outside are not read).
+__device__ __forceinline__ void load_row_batch(const TlRow& hits, int r0, bool active, int rin,
+                                               int rout, int32_t (&hv)[kRowBatch]) {
+#pragma unroll
+  for (int u = 0; u < kRowBatch; ++u) {
+    const int r = r0 + u;
+    hv[u] = (active && r >= rin && r <= rout) ? hits[r] : -1;
+  }
+}
+
+__device__ __forceinline__ void load_weights(const Slot& S, const int32_t (&hv)[kRowBatch],
+                                             uint32_t (&wv)[kRowBatch]) {
+#pragma unroll
+  for (int u = 0; u < kRowBatch; ++u) wv[u] = hv[u] >= 0 ? S.weight[hv[u]] : 0u;
+}
+
 // a6: a valid tracklet becomes a track if it owns (holds the maximal weight
 // of) at least n_min_track of its hits.  Writes 1/0 per tracklet of the
 // range; the scan of these flags places the tracks.
@@ -43,11 +65,13 @@ __global__ void __launch_bounds__(256) k_select(Slot S, DevConst K, int g0) {
     const int lo = wave_min(valid ? rin : kRows), hi = wave_max(valid ? rout : -1);
     const TlRow hits = tl_row(S, T);
     int cnt = 0;
-    for (int r = lo; r <= hi; ++r) {
-      if (valid && r >= rin && r <= rout) {
-        const int32_t h = hits[r];
-        if (h >= 0 && S.weight[h] == w) ++cnt;
-      }
+    for (int r0 = lo; r0 <= hi; r0 += kRowBatch) {
+      int32_t hv[kRowBatch];
+      load_row_batch(hits, r0, valid, rin, rout, hv);
+      uint32_t wv[kRowBatch];
+      load_weights(S, hv, wv);
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) cnt += (hv[u] >= 0 && wv[u] == w) ? 1 : 0;
     }
     if (t < total) S.tl_sel[t] = valid && cnt >= K.n_min_track ? 1u : 0u;
   }
@@ -85,12 +109,16 @@ __global__ void __launch_bounds__(256) k_track_write(Slot S, int g0) {
     int32_t* own = S.tk_own + (size_t)k * kRows;
     uint8_t* own_row = S.tk_own_row + (size_t)k * kRows;
     int cnt = 0;
-    for (int r = lo; r <= hi; ++r) {
-      if (sel && r >= rin && r <= rout) {
-        const int32_t h = hits[r];
-        if (h >= 0 && S.weight[h] == w) {
-          own[cnt] = h;
-          own_row[cnt] = (uint8_t)r;
+    for (int r0 = lo; r0 <= hi; r0 += kRowBatch) {
+      int32_t hv[kRowBatch];
+      load_row_batch(hits, r0, sel, rin, rout, hv);
+      uint32_t wv[kRowBatch];
+      load_weights(S, hv, wv);
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        if (hv[u] >= 0 && wv[u] == w) {
+          own[cnt] = hv[u];
+          own_row[cnt] = (uint8_t)(r0 + u);
           ++cnt;
         }
       }
