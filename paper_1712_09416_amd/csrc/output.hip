@@ -138,6 +138,8 @@ __global__ void k_event_hits(Slot S) {
   if (e <= S.n_events) S.ev_hit_off[e] = S.out_ntk[S.ev_track_off[e]];
 }
 
+constexpr int kOutBatch = 8;
+
 // Track records and hit lists (hit offsets relative to the event).
 __global__ void k_write_out(Slot S, DevConst K) {
   const uint32_t ntk = S.out_count[0];
@@ -180,7 +182,20 @@ __global__ void k_write_out(Slot S, DevConst K) {
     for (int i = 0; i < 15; ++i) o.cov[i] = cov[i];
     o.chi2 = S.tk_chi2[k];
     S.out_tracks[pos] = o;
-    for (int j = j0; j < nown; ++j) S.out_hits[hoff + (j - j0)] = (int32_t)((int64_t)S.hit[own[j]].id - ev0);
+    // hit IDs kOutBatch at a time: the batch's positions, then their
+    // records, are loaded together before any store
+    int32_t* dst = S.out_hits + hoff;
+    for (int jb = j0; jb < nown; jb += kOutBatch) {
+      int32_t pv[kOutBatch];
+#pragma unroll
+      for (int u = 0; u < kOutBatch; ++u) pv[u] = jb + u < nown ? own[jb + u] : -1;
+      uint32_t iv[kOutBatch];
+#pragma unroll
+      for (int u = 0; u < kOutBatch; ++u) iv[u] = pv[u] >= 0 ? S.hit[pv[u]].id : 0u;
+#pragma unroll
+      for (int u = 0; u < kOutBatch; ++u)
+        if (jb + u < nown) dst[jb + u - j0] = (int32_t)((int64_t)iv[u] - ev0);
+    }
   }
 }
 
