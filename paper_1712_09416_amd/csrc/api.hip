@@ -308,6 +308,10 @@ int grid_stride_blocks(int64_t n, int threads, int cap = 4096) {
 // data[n].
 void scan_u32(hipStream_t st, uint32_t* data, const uint32_t* n_dev, int64_t n_bound,
               uint32_t* partial, uint32_t* total_out, bool write_end = true) {
+  if (n_bound <= kSmallScanMax) {
+    k_scan_small<<<1, 1024, 0, st>>>(data, n_dev, n_bound, total_out, write_end ? 1 : 0);
+    return;
+  }
   const int nb = (int)std::max<int64_t>(1, (n_bound + kScanTile - 1) / kScanTile);
   k_scan_tiles<<<nb, 256, 0, st>>>(data, n_dev, n_bound, partial);
   k_scan_partials<<<1, 1024, 0, st>>>(partial, nb, data, n_dev, n_bound, total_out,

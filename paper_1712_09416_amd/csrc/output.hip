@@ -88,6 +88,45 @@ __global__ void __launch_bounds__(1024) k_scan_partials(uint32_t* partial, int n
   }
 }
 
+// Whole scan in one 1024-thread block for n <= kSmallScanMax (the per-row
+// and per-sector tables): each thread scans a contiguous run of
+// kSmallPerThread values in registers.  In place; writes the total to
+// data[n] (write_end) and *total_out (if given).
+__global__ void __launch_bounds__(1024) k_scan_small(uint32_t* data, const uint32_t* n_dev,
+                                                     int64_t n_host, uint32_t* total_out,
+                                                     int write_end) {
+  __shared__ uint32_t ws[16];
+  const uint32_t n = scan_n(n_dev, n_host);
+  const uint32_t base = threadIdx.x * kSmallPerThread;
+  uint32_t v[kSmallPerThread];
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kSmallPerThread; ++j) {
+    v[j] = base + j < n ? data[base + j] : 0u;
+    s += v[j];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t inc = wave_incl_scan(s);
+  if (lane == 63) ws[w] = inc;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (i < w) before += ws[i];
+    tot += ws[i];
+  }
+  uint32_t run = before + inc - s;
+#pragma unroll
+  for (int j = 0; j < kSmallPerThread; ++j) {
+    if (base + j < n) data[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 0) {
+    if (write_end) data[n] = tot;
+    if (total_out) *total_out = tot;
+  }
+}
+
 // in-place capable: each thread reads its values before writing them
 __global__ void __launch_bounds__(kScanBlock) k_scan_apply(const uint32_t* in, const uint32_t* n_dev,
                                                            int64_t n_host, const uint32_t* partial,

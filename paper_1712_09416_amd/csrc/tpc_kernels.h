@@ -28,6 +28,10 @@ __global__ void k_scan_partials(uint32_t* partial, int nb, uint32_t* out, const 
                                 int64_t n_host, uint32_t* total_out, int write_end);
 __global__ void k_scan_apply(const uint32_t* in, const uint32_t* n_dev, int64_t n_host,
                              const uint32_t* partial, uint32_t* out);
+constexpr int kSmallPerThread = 16;
+constexpr int64_t kSmallScanMax = 1024 * kSmallPerThread;
+__global__ void k_scan_small(uint32_t* data, const uint32_t* n_dev, int64_t n_host,
+                             uint32_t* total_out, int write_end);
 __global__ void k_flags(Slot S);
 __global__ void k_order(Slot S);
 __global__ void k_event_hits(Slot S);
