@@ -28,8 +28,11 @@ __device__ __forceinline__ int event_of(const int64_t* ev_off, int n_events, int
 // atomic per row and block reserves the block's range.
 constexpr int kCountChunk = 4096;
 constexpr int kEventRows = kSectorsPerEvent * kRows;
+constexpr int kCountThreads = 256;
+constexpr int kRowsPerThread = (kEventRows + kCountThreads - 1) / kCountThreads;
+constexpr int kCountBatch = 4;
 
-__global__ void __launch_bounds__(256) k_count(Slot S) {
+__global__ void __launch_bounds__(kCountThreads) k_count(Slot S) {
   __shared__ uint32_t hist[kEventRows];
   const int e = blockIdx.y;
   const int64_t e0 = S.ev_off[e], e1 = S.ev_off[e + 1];
@@ -38,29 +41,72 @@ __global__ void __launch_bounds__(256) k_count(Slot S) {
   const int64_t i1 = min(e1, i0 + (int64_t)kCountChunk);
   for (int r = threadIdx.x; r < kEventRows; r += blockDim.x) hist[r] = 0u;
   __syncthreads();
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    S.tmap[i] = -1;
-    const int sec = S.sector[i];
-    const int row = S.row[i];
-    const float y = S.y[i], z = S.z[i];
-    if (sec >= kSectorsPerEvent || row >= kRows || !isfinite(y) || !isfinite(z)) {
-      atomicAdd(&S.err[0], 1u);
-      S.rank[i] = kNoHit;
-      continue;
+  // clusters kCountBatch per thread at a time: loads first, then the LDS
+  // ranks
+  for (int64_t ib = i0 + threadIdx.x; ib < i1; ib += kCountBatch * kCountThreads) {
+    int sec[kCountBatch], row[kCountBatch];
+    float y[kCountBatch], z[kCountBatch];
+#pragma unroll
+    for (int u = 0; u < kCountBatch; ++u) {
+      const int64_t i = ib + u * kCountThreads;
+      sec[u] = 0;
+      row[u] = 0;
+      y[u] = 0.0f;
+      z[u] = 0.0f;
+      if (i < i1) {
+        sec[u] = S.sector[i];
+        row[u] = S.row[i];
+        y[u] = S.y[i];
+        z[u] = S.z[i];
+      }
     }
-    S.rank[i] = atomicAdd(&hist[sec * kRows + row], 1u);
+#pragma unroll
+    for (int u = 0; u < kCountBatch; ++u) {
+      const int64_t i = ib + u * kCountThreads;
+      if (i >= i1) continue;
+      S.tmap[i] = -1;
+      if (sec[u] >= kSectorsPerEvent || row[u] >= kRows || !isfinite(y[u]) || !isfinite(z[u])) {
+        atomicAdd(&S.err[0], 1u);
+        S.rank[i] = kNoHit;
+        continue;
+      }
+      S.rank[i] = atomicAdd(&hist[sec[u] * kRows + row[u]], 1u);
+    }
   }
   __syncthreads();
+  // every atomic of the thread is issued before the first result is used
   uint32_t* cnt = S.row_cnt + (size_t)e * kEventRows;
-  for (int r = threadIdx.x; r < kEventRows; r += blockDim.x) {
-    const uint32_t c = hist[r];
-    hist[r] = c ? atomicAdd(&cnt[r], c) : 0u;
+  uint32_t res[kRowsPerThread];
+#pragma unroll
+  for (int k = 0; k < kRowsPerThread; ++k) {
+    const int r = threadIdx.x + k * kCountThreads;
+    const uint32_t c = r < kEventRows ? hist[r] : 0u;
+    res[k] = c ? atomicAdd(&cnt[r], c) : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < kRowsPerThread; ++k) {
+    const int r = threadIdx.x + k * kCountThreads;
+    if (r < kEventRows) hist[r] = res[k];
   }
   __syncthreads();
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const uint32_t rk = S.rank[i];
-    if (rk == kNoHit) continue;
-    S.rank[i] = rk + hist[S.sector[i] * kRows + S.row[i]];
+  for (int64_t ib = i0 + threadIdx.x; ib < i1; ib += kCountBatch * kCountThreads) {
+    uint32_t rk[kCountBatch];
+    int sr[kCountBatch];
+#pragma unroll
+    for (int u = 0; u < kCountBatch; ++u) {
+      const int64_t i = ib + u * kCountThreads;
+      rk[u] = kNoHit;
+      sr[u] = 0;
+      if (i < i1) {
+        rk[u] = S.rank[i];
+        sr[u] = S.sector[i] * kRows + S.row[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kCountBatch; ++u) {
+      const int64_t i = ib + u * kCountThreads;
+      if (i < i1 && rk[u] != kNoHit) S.rank[i] = rk[u] + hist[sr[u]];
+    }
   }
 }
 
