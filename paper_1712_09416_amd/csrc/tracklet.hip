@@ -206,9 +206,14 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
     // of the tracklets holding it; issued here, without waiting for results,
     // so the atomics overlap the other lanes' Kalman steps
     if (valid) {
-      for (int r = rin; r <= rout; ++r) {
-        const int32_t h = hits[r];
-        if (h >= 0) atomicMax(&S.weight[h], w);
+      // the list is read back eight rows per memory round trip
+      for (int r0 = rin; r0 <= rout; r0 += 8) {
+        int32_t hv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) hv[u] = r0 + u <= rout ? hits[r0 + u] : -1;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (hv[u] >= 0) atomicMax(&S.weight[hv[u]], w);
       }
     }
     float* sv = S.tl_state + (size_t)T * 5;
