@@ -176,20 +176,49 @@ __global__ void k_row_finish(Slot S) {
 
 // a2: clusters to their row (arrival order within the row), as hit
 // records; the row sort then orders each row in place
+// Clusters kCountBatch per thread at a time (strided by the grid, so each
+// load stays coalesced): the batch's fields, then its row offsets, are
+// loaded together.
 __global__ void k_scatter(Slot S) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n; i += stride) {
-    const uint32_t rk = S.rank[i];
-    if (rk == kNoHit) continue;
-    const int e = event_of(S.ev_off, S.n_events, i);
-    const int sr = (e * kSectorsPerEvent + S.sector[i]) * kRows + S.row[i];
-    const uint32_t pos = S.row_off[sr] + rk;
-    Hit h;                               // one 16-byte store per cluster
-    h.y = S.y[i];
-    h.z = S.z[i];
-    h.id = (uint32_t)i;
-    h.upc = -1;
-    S.hit[pos] = h;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t ib = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ib < S.n;
+       ib += kCountBatch * nthreads) {
+    uint32_t rk[kCountBatch];
+    int sr[kCountBatch];
+    float y[kCountBatch], z[kCountBatch];
+#pragma unroll
+    for (int u = 0; u < kCountBatch; ++u) {
+      const int64_t i = ib + u * nthreads;
+      rk[u] = kNoHit;
+      sr[u] = 0;
+      y[u] = 0.0f;
+      z[u] = 0.0f;
+      if (i < S.n) {
+        rk[u] = S.rank[i];
+        sr[u] = S.sector[i] * kRows + S.row[i];
+        y[u] = S.y[i];
+        z[u] = S.z[i];
+      }
+    }
+    uint32_t base[kCountBatch];
+#pragma unroll
+    for (int u = 0; u < kCountBatch; ++u) {
+      base[u] = 0u;
+      if (rk[u] != kNoHit) {
+        const int e = event_of(S.ev_off, S.n_events, ib + u * nthreads);
+        base[u] = S.row_off[e * kEventRows + sr[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kCountBatch; ++u) {
+      if (rk[u] == kNoHit) continue;
+      Hit h;                               // one 16-byte store per cluster
+      h.y = y[u];
+      h.z = z[u];
+      h.id = (uint32_t)(ib + u * nthreads);
+      h.upc = -1;
+      S.hit[base[u] + rk[u]] = h;
+    }
   }
 }
 
