@@ -126,9 +126,13 @@ bool predict(State<T>& st, T dx, T b, T smax, T kk = T(0), T m2 = T(0)) {
   const T c1 = tsqrt(tfma(-s1, s1, T(1)));
   const T N = s + s1;
   const T D = c0 + c1;
-  const T iD = T(1) / D;
-  const T ic0 = T(1) / c0;
-  const T ic1 = T(1) / c1;
+  // one division: the reciprocals of D, c0 and c1 are products with
+  // 1/(c0 c1 D)
+  const T c01 = c0 * c1;
+  const T inv = T(1) / (c01 * D);
+  const T iD = c01 * inv;
+  const T ic0 = (c1 * D) * inv;
+  const T ic1 = (c0 * D) * inv;
   const T t = N * iD;
   const T dl = tabs(dx) * tsqrt(tfma(t, t, T(1)));
   const T u = T(0.5) * bq * dl;
@@ -282,6 +286,7 @@ struct Ctx {
   T X[kRows];
   T b, smax, chi2max, kwin, wmax, tanh, medge, mz, zmax;
   T sy0, sy1, sz0, sz1, cs0, ct0, cq0, nfw, nfm;
+  T sy1z, sz1z;         // sigma_1 / z_max of the error model
   T kk, m2;             // scattering law: k^2/X0 and mass^2 (0: no scattering)
 };
 
@@ -305,6 +310,8 @@ void init_ctx(Ctx<T>& c, const orc_geometry* g, const orc_params* P) {
   c.sy1 = T(g->sigma_y1);
   c.sz0 = T(g->sigma_z0);
   c.sz1 = T(g->sigma_z1);
+  c.sy1z = c.sy1 / c.zmax;
+  c.sz1z = c.sz1 / c.zmax;
   c.cs0 = T(P->c_s0);
   c.ct0 = T(P->c_t0);
   c.cq0 = T(P->c_q0);
@@ -323,8 +330,10 @@ void init_ctx(Ctx<T>& c, const orc_geometry* g, const orc_params* P) {
   }
 }
 
-template <class T> T sig_y(const Ctx<T>& c, T z) { return c.sy0 + c.sy1 * tabs(z) / c.zmax; }
-template <class T> T sig_z(const Ctx<T>& c, T z) { return c.sz0 + c.sz1 * tabs(z) / c.zmax; }
+// cluster errors sigma(z) = sigma_0 + sigma_1 |z| / z_max, with sigma_1 / z_max
+// formed once
+template <class T> T sig_y(const Ctx<T>& c, T z) { return c.sy0 + c.sy1z * tabs(z); }
+template <class T> T sig_z(const Ctx<T>& c, T z) { return c.sz0 + c.sz1z * tabs(z); }
 
 struct Tracklet {
   int32_t start_id = -1;

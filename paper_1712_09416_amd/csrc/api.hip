@@ -532,6 +532,10 @@ int tpc_init_geometry(tpc_ctx** out, const tpc_geometry* g, const tpc_params* p,
   k.sy1 = g->sigma_y1;
   k.sz0 = g->sigma_z0;
   k.sz1 = g->sigma_z1;
+  k.sy1z = k.sy1 / k.z_max;
+  k.sz1z = k.sz1 / k.z_max;
+  k.sy1zd = (double)k.sy1 / (double)k.z_max;
+  k.sz1zd = (double)k.sz1 / (double)k.z_max;
   // curvature per unit q/pT: d(phi)/dl = b q/pT, b = -c Bz, c = 0.00299792458 GeV/(T cm)
   k.bd = -0.00299792458 * (double)g->bz_tesla;
   k.b = (float)k.bd;

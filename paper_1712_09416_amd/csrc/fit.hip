@@ -150,9 +150,9 @@ __device__ __forceinline__ void refit_pass(const Slot& S, const DevConst& K, con
   st.s = s0;
   st.t = t0;
   st.q = q0;
-  const double sy0 = K.sy0, sy1 = K.sy1, sz0 = K.sz0, sz1 = K.sz1, zmax = K.z_max;
+  const double sy0 = K.sy0, sy1z = K.sy1zd, sz0 = K.sz0, sz1z = K.sz1zd;
   {
-    const double sy = sy0 + sy1 * fabs(st.z) / zmax, sz = sz0 + sz1 * fabs(st.z) / zmax;
+    const double sy = sy0 + sy1z * fabs(st.z), sz = sz0 + sz1z * fabs(st.z);
     reset_cov(st, sy * sy, sz * sz, (double)K.cs0, (double)K.ct0, (double)K.cq0);
   }
   o.st = st;
@@ -172,7 +172,7 @@ __device__ __forceinline__ void refit_pass(const Slot& S, const DevConst& K, con
     if (!transport(st, (double)K.row_x[r] - (double)K.row_x[r + 1], K.bd, smax, K.kkd, K.m2d)) break;
     if (r != rn) continue;
     const Hit xh = xn;
-    const double sy = sy0 + sy1 * fabs(st.z) / zmax, sz = sz0 + sz1 * fabs(st.z) / zmax;
+    const double sy = sy0 + sy1z * fabs(st.z), sz = sz0 + sz1z * fabs(st.z);
     double ch = 0.0;
     kalman_update(st, (double)xh.y, (double)xh.z, sy * sy, sz * sz, chi2max, smax, false, &ch);
     o.chi2 = o.chi2 + ch;

@@ -39,16 +39,16 @@ constexpr int kMaxChain = 16;    // segments of one chain (each holds >= 10 of t
 __device__ __forceinline__ double xrow(const DevConst& K, int r) { return (double)K.row_x[r]; }
 
 __device__ __forceinline__ void prior_d(const DevConst& K, Helix<double>& st, double zv) {
-  const double sy = (double)K.sy0 + (double)K.sy1 * fabs(zv) / (double)K.z_max;
-  const double sz = (double)K.sz0 + (double)K.sz1 * fabs(zv) / (double)K.z_max;
+  const double sy = (double)K.sy0 + K.sy1zd * fabs(zv);
+  const double sz = (double)K.sz0 + K.sz1zd * fabs(zv);
   reset_cov(st, sy * sy, sz * sz, (double)K.cs0, (double)K.ct0, (double)K.cq0);
 }
 
 // ungated update with a measured (y, z); returns its chi2
 __device__ __forceinline__ double update_yz(const DevConst& K, Helix<double>& st, float y,
                                             float z) {
-  const double sy = (double)K.sy0 + (double)K.sy1 * fabs(st.z) / (double)K.z_max;
-  const double sz = (double)K.sz0 + (double)K.sz1 * fabs(st.z) / (double)K.z_max;
+  const double sy = (double)K.sy0 + K.sy1zd * fabs(st.z);
+  const double sz = (double)K.sz0 + K.sz1zd * fabs(st.z);
   double ch = 0.0;
   kalman_update(st, (double)y, (double)z, sy * sy, sz * sz, (double)K.chi2max, (double)K.smax,
                 false, &ch);

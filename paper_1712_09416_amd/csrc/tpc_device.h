@@ -32,6 +32,10 @@ struct DevConst {
   float tanh_half;
   float z_max;
   float sy0, sy1, sz0, sz1;
+  // error model sigma(z) = sigma_0 + sigma_1 |z| / z_max with sigma_1 / z_max
+  // formed once, in float and in double
+  float sy1z, sz1z;
+  double sy1zd, sz1zd;
   float b;          // curvature per unit q/pT, float
   double bd;        // same, double (refit)
   float nf_w, nf_mmax, chi2max, kwin, wmax, smax, cs0, ct0, cq0, medge, mz;
@@ -245,10 +249,10 @@ __device__ __forceinline__ void for_window_hits(const RowBins& b, const uint32_t
 }
 
 __device__ __forceinline__ float sigma_y(const DevConst& k, float z) {
-  return k.sy0 + k.sy1 * fabsf(z) / k.z_max;
+  return k.sy0 + k.sy1z * fabsf(z);
 }
 __device__ __forceinline__ float sigma_z(const DevConst& k, float z) {
-  return k.sz0 + k.sz1 * fabsf(z) / k.z_max;
+  return k.sz0 + k.sz1z * fabsf(z);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,9 +304,13 @@ __device__ __forceinline__ bool transport(Helix<F>& h, F dx, F b, F smax, F kk =
   const F c1 = sqrt_(fma_(-s1, s1, one));
   const F N = s0 + s1;
   const F D = c0 + c1;
-  const F iD = one / D;
-  const F ic0 = one / c0;
-  const F ic1 = one / c1;
+  // one division: the reciprocals of D, c0 and c1 are products with
+  // 1/(c0 c1 D)
+  const F c01 = c0 * c1;
+  const F inv = one / (c01 * D);
+  const F iD = c01 * inv;
+  const F ic0 = (c1 * D) * inv;
+  const F ic1 = (c0 * D) * inv;
   const F tmid = N * iD;
   const F chord = fabs_(dx) * sqrt_(fma_(tmid, tmid, one));
   const F u = half * bq * chord;

@@ -87,8 +87,8 @@ def test_neighbours_are_global_best_pair(oracle_lib):
             cand[d] = idx[ok]
         best = None
         f = f32((x[rr] - x[rr - 1]) / (x[rr + 1] - x[rr - 1]))
-        sy = f32(ev.sigma[0]) + f32(ev.sigma[1]) * np.abs(ev.z[h]) / f32(250.0)
-        sz = f32(ev.sigma[2]) + f32(ev.sigma[3]) * np.abs(ev.z[h]) / f32(250.0)
+        sy = f32(ev.sigma[0]) + f32(ev.sigma[1]) / f32(250.0) * np.abs(ev.z[h])
+        sz = f32(ev.sigma[2]) + f32(ev.sigma[3]) / f32(250.0) * np.abs(ev.z[h])
         wy = f32(1.0) / (f32(1.5) * (sy * sy))
         wz = f32(1.0) / (f32(1.5) * (sz * sz))
         for dd in cand[-1]:
