@@ -15,7 +15,7 @@ import torch
 
 from .tracker import Tracker
 
-DEFAULT_CANDIDATES = [(t, e) for t in (1.0, 2.0, 4.0) for e in (1.0, 2.0, 3.0)]
+DEFAULT_CANDIDATES = [(t, e) for t in (0.25, 0.5, 1.0) for e in (1.0, 2.0, 3.0)]
 
 
 def _digest(trk: Tracker, n_events: int) -> str:

@@ -125,7 +125,7 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   s.row_off = c.take<uint32_t>(SR + 1);
   s.bins = c.take<RowBins>(SR);
   s.row_bin = c.take<uint32_t>(SR + 1);
-  s.bin_off = c.take<uint32_t>(N + SR + 1);
+  s.bin_off = c.take<uint32_t>(kBinsPerHit * N + SR + 1);
   s.rank = c.take<uint32_t>(N);
   s.hit = c.take<Hit>(N);
   s.up = c.take<int32_t>(N);
@@ -463,8 +463,8 @@ int tpc_params_default(tpc_params* p) {
   p->n_gap = 6;
   p->n_min_tracklet = 10;
   p->n_min_track = 10;
-  p->bin_target = 2.0f;
-  p->bin_min_edge = 2.0f;
+  p->bin_target = 0.25f;
+  p->bin_min_edge = 1.0f;
   p->max_slots = 1;
   p->max_events = 1;
   p->max_clusters = 4 << 20;

@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(kCountThreads) k_count(Slot S) {
 }
 
 // Bin layout of one row with n hits: ~bin_target hits per bin, edges at
-// least bin_min_edge, at most max(n, 1) bins.
+// least bin_min_edge, at most kBinsPerHit * max(n, 1) bins.
 __device__ RowBins make_bins(const DevConst& K, int row, bool side_c, uint32_t n) {
   RowBins b;
   const float ymax = K.row_x[row] * K.tanh_half + K.medge;
@@ -123,15 +123,16 @@ __device__ RowBins make_bins(const DevConst& K, int row, bool side_c, uint32_t n
   float edge = sqrtf(wy * wz * K.bin_target / nn);
   if (edge < K.bin_min_edge) edge = K.bin_min_edge;
   int ny = 1, nz = 1;
+  const uint32_t nmax = (uint32_t)kBinsPerHit * (n > 0 ? n : 1u);
   for (int it = 0; it < 32; ++it) {
     ny = (int)ceilf(wy / edge);
     nz = (int)ceilf(wz / edge);
     ny = ny < 1 ? 1 : (ny > 128 ? 128 : ny);
     nz = nz < 1 ? 1 : (nz > 128 ? 128 : nz);
-    if ((uint32_t)(ny * nz) <= (n > 0 ? n : 1u)) break;
+    if ((uint32_t)(ny * nz) <= nmax) break;
     edge *= 1.25f;
   }
-  if ((uint32_t)(ny * nz) > (n > 0 ? n : 1u)) { ny = 1; nz = 1; }
+  if ((uint32_t)(ny * nz) > nmax) { ny = 1; nz = 1; }
   b.ny = ny;
   b.nz = nz;
   b.iby = (float)ny / wy;
@@ -224,7 +225,7 @@ __global__ void k_scatter(Slot S) {
 
 // a2: one block per (sector, row): order the row's hits by (bin, cluster
 // index) — counting sort by bin in LDS, then an insertion sort by index
-// inside each bin (bins hold ~2 hits) — write them as Hit records and fill
+// inside each bin (bins hold a hit or two) — write them as Hit records and fill
 // the row's bin offsets.  CAP is the largest row the instance handles; the
 // instance for rows up to kMaxRowHits also handles the over-full rows.
 template <int CAP>
@@ -235,7 +236,7 @@ __device__ __forceinline__ void row_sort(Slot& S, int sr, bool small) {
   __shared__ uint16_t lbin[CAP];
   __shared__ uint16_t lrank[CAP];
   __shared__ uint16_t perm[CAP];
-  __shared__ uint32_t hist[CAP + 1];
+  __shared__ uint32_t hist[kBinsPerHit * CAP + 1];
   __shared__ uint32_t wsum[4];
   const uint32_t off = S.row_off[sr];
   const uint32_t n = S.row_off[sr + 1] - off;

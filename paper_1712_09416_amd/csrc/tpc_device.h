@@ -22,6 +22,7 @@ namespace tpc {
 constexpr int kRows = 159;
 constexpr int kSectorsPerEvent = 36;
 constexpr int kMaxRowHits = 4096;         // LDS sort capacity of one pad row
+constexpr int kBinsPerHit = 2;            // a row has at most this many bins per hit
 constexpr uint32_t kNoHit = 0xFFFFFFFFu;
 
 // ---------------------------------------------------------------------------
