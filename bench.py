@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes of the tracklet kernel (one launch): per tracklet, the
 # start hit, the seed pair and the tracklet record (64 B); per row visit,
 # the hit index written, the chain link, one hit's (y, z) and the bin range
-# (24 B); per hit examined in a search window, its (y, z, id) (12 B)
+# (24 B); per hit inside a search window, its (y, z, id) (12 B)
 BYTES_PER_TRACKLET = 64
 BYTES_PER_ROW_VISIT = 24
 BYTES_PER_WINDOW_HIT = 12

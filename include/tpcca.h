@@ -314,8 +314,8 @@ int tpc_poll(tpc_ctx* ctx, int slot);
  * and returns, for the last tracked slot, the milliseconds of each step
  * (ms[TPC_N_STAGES]: grid, neighbours, clean+starts, tracklets,
  * weights+selection, refit, output) and the slot's work counters
- * (counters[8]: tracklets, tracklet row visits, search-window hits
- * examined, tracks, clusters, sorted hits, 0, 0).  Either pointer may be
+ * (counters[8]: tracklets, tracklet row visits, hits inside the
+ * tracklet search windows, tracks, clusters, sorted hits, 0, 0).  Either pointer may be
  * NULL.  Errors: TPC_EINVAL, TPC_ESTATE (nothing profiled yet), TPC_EDEVICE. */
 #define TPC_N_STAGES 7
 int tpc_set_profiling(tpc_ctx* ctx, int enable);

@@ -33,9 +33,9 @@ __device__ __forceinline__ int32_t search_row(const Slot& S, const DevConst& K, 
   float bchi = 0.0f;
   uint32_t bid = 0;
   for_window_hits(rb, S.bin_off + rb.base, S.hit, yc, zc, wy, wz, [&](uint32_t p, const Hit& x) {
-    ++examined;
     const float ry = x.y - yc, rz = x.z - zc;
     if (!(fabsf(ry) <= wy && fabsf(rz) <= wz)) return;
+    ++examined;                 // hits inside the window (independent of the binning)
     const float ch = chi2_of(w, ry, rz);
     const uint32_t id = x.id;
     if (best < 0 || ch < bchi || (ch == bchi && id < bid)) {
