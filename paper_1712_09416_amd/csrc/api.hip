@@ -360,7 +360,7 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
   const int64_t tl_bound = std::min<int64_t>(s.cap_tl, h.n / 3 + ns);
   const int nb_lane = std::max(8, grid_stride_blocks(tl_bound, 64, 16384) / 8 * 8);
   const int nb_sel = grid_stride_blocks(tl_bound, 256, 4096);
-  k_neighbours<<<dim3(kRows, ns), 256, 0, st>>>(s, ctx->k, g0);
+  k_neighbours<<<((ns * kRows + 7) / 8) * 8, 256, 0, st>>>(s, ctx->k, g0, ns);
   if (marks) mark(ctx, 2);
   k_clean_rows<<<dim3(kRows, ns), 256, 0, st>>>(s, g0);
   scan_u32(st, s.row_nstart + (size_t)g0 * kRows, nullptr, (int64_t)ns * kRows, s.scan_b,

@@ -50,10 +50,18 @@ constexpr int kNfCand = 32;      // up-row candidates listed per hit before a ne
 // are read through the caches with the batched window reads (measured
 // faster than staging the rows in LDS, and than holding the candidates in
 // registers, whose fixed-length pairing loop costs more than it saves).
-__global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, int g0) {
+// Blocks are dealt round-robin over the 8 XCDs; block b serves the
+// (sector, row) pair number (b % 8) * per + b / 8 of the launched range, so
+// each XCD works through one contiguous stretch of sectors, row after row,
+// and the rows r-1, r+1 that neighbouring blocks read stay in its L2.
+__global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, int g0, int ns) {
   __shared__ uint32_t cand[kNfCand * kNfThreads];
-  const int row = blockIdx.x;
-  const int g = g0 + blockIdx.y;
+  const int total = ns * kRows;
+  const int per = (total + 7) / 8;
+  const int v = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (v >= total) return;
+  const int row = v % kRows;
+  const int g = g0 + v / kRows;
   const int sr = g * kRows + row;
   const uint32_t h0 = S.row_off[sr], h1 = S.row_off[sr + 1];
   if (row == 0 || row == kRows - 1) {
