@@ -182,6 +182,8 @@ class Tracker:
         on the device; asynchronous on the tracker's stream)."""
         assert hist.is_cuda and hist.dim() == 2 and hist.shape[0] == 2 and hist.is_contiguous()
         assert hist.dtype in (torch.int32,)
+        # hist may have been written on torch's stream (e.g. zeroed)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         check(self.L.tpc_calib_accumulate(self.ctx, slot, hist.data_ptr(), hist.shape[1], z_lo,
                                           z_hi), self.ctx)
 
@@ -189,6 +191,8 @@ class Tracker:
         """Correct device cluster z in place for a drift-velocity error eps."""
         assert sector.is_cuda and z.is_cuda and sector.dtype == torch.uint8
         assert z.dtype == torch.float32 and z.is_contiguous() and sector.is_contiguous()
+        # z and sector may have been written on torch's stream
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         check(self.L.tpc_calib_correct_z(self.ctx, sector.data_ptr(), z.data_ptr(), z.numel(),
                                          float(eps)), self.ctx)
 
