@@ -294,7 +294,10 @@ __device__ __forceinline__ void for_neighbours(const uint32_t* off, const int32_
   }
 }
 
-// M2 + M3: best outer partner of each A
+// M2 + M3: best outer partner of each A.  Every compatible pair is
+// evaluated here once: its chi2 also lowers B's smallest chi2 (the bit
+// pattern of a non-negative double orders like its value), and the first
+// kMgPairs pairs of A are kept for the pass that picks B's best A.
 __global__ void __launch_bounds__(64) k_mg_best_out(Slot S, DevConst K, MergeSlot M,
                                                     MergeConst C) {
   const uint32_t ntk = S.out_count[0];
@@ -302,6 +305,7 @@ __global__ void __launch_bounds__(64) k_mg_best_out(Slot S, DevConst K, MergeSlo
   for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
     int32_t best = -1;
     double bc = 0.0;
+    int32_t np = 0;
     if (M.ok[a]) {
       const tpc_track& A = S.out_tracks[a];
       const double* op = M.op + (size_t)a * 5;
@@ -309,6 +313,12 @@ __global__ void __launch_bounds__(64) k_mg_best_out(Slot S, DevConst K, MergeSlo
       for_neighbours(M.in_off, M.in_list, A, A.row_out + 1, A.row_out + C.row_gap, [&](int32_t b) {
         double ch;
         if (!pair_chi2(K, C, A, op, oc, S.out_tracks[b], ch)) return;
+        atomicMin(&M.in_key[b], (unsigned long long)__double_as_longlong(ch));
+        if (np < kMgPairs) {
+          M.pr_b[(size_t)a * kMgPairs + np] = b;
+          M.pr_chi[(size_t)a * kMgPairs + np] = ch;
+        }
+        ++np;
         if (best < 0 || ch < bc || (ch == bc && b < best)) {
           best = b;
           bc = ch;
@@ -317,30 +327,48 @@ __global__ void __launch_bounds__(64) k_mg_best_out(Slot S, DevConst K, MergeSlo
     }
     M.best_out[a] = best;
     M.chi_out[a] = bc;
+    M.pr_n[a] = np;
   }
 }
 
-// M2 + M3: best inner partner of each B
+// M2 + M3: best inner partner of each B: among the A whose pair reaches B's
+// smallest chi2, the smaller track position (lane per A, over the pairs the
+// previous pass kept; an A with more than kMgPairs pairs evaluates them again).
 __global__ void __launch_bounds__(64) k_mg_best_in(Slot S, DevConst K, MergeSlot M,
                                                    MergeConst C) {
   const uint32_t ntk = S.out_count[0];
   const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
+    const int32_t np = M.pr_n[a];
+    if (np == 0) continue;
+    auto offer = [&](int32_t b, double ch) {
+      if ((unsigned long long)__double_as_longlong(ch) == M.in_key[b])
+        atomicMin(&M.best_in[b], (int32_t)a);
+    };
+    if (np <= kMgPairs) {
+      for (int k = 0; k < np; ++k)
+        offer(M.pr_b[(size_t)a * kMgPairs + k], M.pr_chi[(size_t)a * kMgPairs + k]);
+    } else {
+      const tpc_track& A = S.out_tracks[a];
+      const double* op = M.op + (size_t)a * 5;
+      const double* oc = M.oc + (size_t)a * 15;
+      for_neighbours(M.in_off, M.in_list, A, A.row_out + 1, A.row_out + C.row_gap, [&](int32_t b) {
+        double ch;
+        if (pair_chi2(K, C, A, op, oc, S.out_tracks[b], ch)) offer(b, ch);
+      });
+    }
+  }
+}
+
+// B without a compatible A: -1 and chi2 0
+__global__ void k_mg_in_final(Slot S, MergeSlot M) {
+  const uint32_t ntk = S.out_count[0];
+  const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < ntk; b += stride) {
-    const tpc_track& B = S.out_tracks[b];
-    int32_t best = -1;
-    double bc = 0.0;
-    for_neighbours(M.out_off, M.out_list, B, B.row_in - C.row_gap, B.row_in - 1, [&](int32_t a) {
-      if (!M.ok[a]) return;
-      double ch;
-      if (!pair_chi2(K, C, S.out_tracks[a], M.op + (size_t)a * 5, M.oc + (size_t)a * 15, B, ch))
-        return;
-      if (best < 0 || ch < bc || (ch == bc && a < best)) {
-        best = a;
-        bc = ch;
-      }
-    });
-    M.best_in[b] = best;
-    M.chi_in[b] = bc;
+    const unsigned long long key = M.in_key[b];
+    const bool none = key == ~0ull;
+    M.chi_in[b] = none ? 0.0 : __longlong_as_double((long long)key);
+    if (none) M.best_in[b] = -1;
   }
 }
 

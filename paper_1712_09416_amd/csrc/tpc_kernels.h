@@ -42,6 +42,7 @@ __global__ void k_mg_scatter(Slot S, MergeSlot M);
 __global__ void k_mg_outer(Slot S, DevConst K, MergeSlot M, MergeConst C);
 __global__ void k_mg_best_out(Slot S, DevConst K, MergeSlot M, MergeConst C);
 __global__ void k_mg_best_in(Slot S, DevConst K, MergeSlot M, MergeConst C);
+__global__ void k_mg_in_final(Slot S, MergeSlot M);
 __global__ void k_mg_link(Slot S, MergeSlot M);
 __global__ void k_mg_chain(Slot S, DevConst K, MergeSlot M, MergeConst C);
 __global__ void k_mg_emit(Slot S, MergeSlot M);
