@@ -541,6 +541,18 @@ __global__ void k_mg_event_off(Slot S, MergeSlot M) {
   M.ev_hit_off[e] = M.nh[k];
 }
 
+// n hit IDs from src to dst, eight loads in flight before their stores
+__device__ __forceinline__ void copy_hits(int32_t* dst, const int32_t* src, int n) {
+  for (int i0 = 0; i0 < n; i0 += 8) {
+    int32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = i0 + u < n ? src[i0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u < n) dst[i0 + u] = v[u];
+  }
+}
+
 __global__ void __launch_bounds__(64) k_mg_write(Slot S, DevConst K, MergeSlot M) {
   const uint32_t ntk = S.out_count[0];
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -561,7 +573,7 @@ __global__ void __launch_bounds__(64) k_mg_write(Slot S, DevConst K, MergeSlot M
       for (int32_t p = h; p >= 0; p = M.link_out[p]) {
         const tpc_track T = S.out_tracks[p];
         const int32_t* src_h = track_hits(S, T);
-        for (int i = 0; i < T.n_hits; ++i) dst[nh + i] = src_h[i];
+        copy_hits(dst + nh, src_h, T.n_hits);
         nh += T.n_hits;
         last = p;
       }
@@ -574,7 +586,7 @@ __global__ void __launch_bounds__(64) k_mg_write(Slot S, DevConst K, MergeSlot M
       M.out_nseg[pos] = M.nseg[h];
     } else {
       const int32_t* src_h = track_hits(S, o);
-      for (int i = 0; i < o.n_hits; ++i) dst[i] = src_h[i];
+      copy_hits(dst, src_h, o.n_hits);
       M.out_nseg[pos] = 1;
     }
     o.hit_off = (int64_t)(hpos - M.ev_hit_off[e]);
