@@ -34,15 +34,13 @@ __global__ void __launch_bounds__(64) k_cal_accumulate(Slot S, DevConst K, uint3
   for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
     const tpc_track& t = S.out_tracks[a];
     if (t.n_hits < kCalNmin) continue;
-    Helix<double> st;
+    Helix<double> st;              // parameters only: z0 needs no covariance
     st.y = t.par[0];
     st.z = t.par[1];
     st.s = t.par[2];
     st.t = t.par[3];
     st.q = t.par[4];
-#pragma unroll
-    for (int i = 0; i < 15; ++i) st.c[i] = 0.0;
-    if (!transport_to_x(st, t.x_ref, 0.0, K.bd, kCalSmax, kCalStep)) continue;
+    if (!transport_to_x<false>(st, t.x_ref, 0.0, K.bd, kCalSmax, kCalStep)) continue;
     if (!(fabs(st.y) <= kCalY0)) continue;
     const double f = (st.z - z_lo) / w;
     if (!(f >= 0.0 && f < (double)n_bins)) continue;

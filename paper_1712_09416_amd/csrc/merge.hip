@@ -73,15 +73,23 @@ __device__ __forceinline__ HitRec load_hit(const Slot& S, int64_t gid) {
   return h;
 }
 
+// kCov = false turns the parameters only (the same arithmetic for them).
+template <bool kCov = true>
 __device__ bool rotate_frame(Helix<double>& h, double& x, double ca, double sa, double b,
                              double smax) {
   const double y = h.y, s = h.s, tl = h.t, q = h.q;
   const double c = sqrt(1.0 - s * s);
   const double s1 = s * ca - c * sa;
   if (!(fabs(s1) <= smax)) return false;
-  const double c1 = sqrt(1.0 - s1 * s1);
   const double x1 = x * ca + y * sa;
   const double y1 = -x * sa + y * ca;
+  if (!kCov) {
+    h.y = y1;
+    h.s = s1;
+    x = x1;
+    return true;
+  }
+  const double c1 = sqrt(1.0 - s1 * s1);
   double J[5][5];
 #pragma unroll
   for (int i = 0; i < 5; ++i)
@@ -453,11 +461,11 @@ __device__ bool carry_out(const Slot& S, const DevConst& K, const MergeConst& C,
   for (int j = 0; j < ch.n; ++j) {
     const tpc_track T = S.out_tracks[ch.pos[j]];
     const double xo = xrow(K, S.row[S.ev_off[T.event] + track_hits(S, T)[T.n_hits - 1]]);
-    if (!transport_to_x(st, x, xo, K.bd, C.smax, C.step_max, K.kkd, K.m2d)) return false;
+    if (!transport_to_x<false>(st, x, xo, K.bd, C.smax, C.step_max, K.kkd, K.m2d)) return false;
     x = xo;
     if (j + 1 < ch.n) {
       const int dir = neighbour(T.sector, S.out_tracks[ch.pos[j + 1]].sector);
-      if (!rotate_frame(st, x, C.ca, (double)dir * C.sa, K.bd, C.smax)) return false;
+      if (!rotate_frame<false>(st, x, C.ca, (double)dir * C.sa, K.bd, C.smax)) return false;
     }
   }
   s0 = st.s;

@@ -299,7 +299,9 @@ template <> __device__ __forceinline__ double fma_(double a, double b, double c)
 // (N/D below); z advances by T times the arc, the arc being the chord
 // times asin(u)/u = 1 + u^2/6 + 3u^4/40 (u = half chord * curvature).
 // Returns false, leaving the state untouched, if |sin phi| would pass smax.
-template <class F>
+// kCov = false moves the parameters only (the same arithmetic for them),
+// for callers that discard the covariance.
+template <class F, bool kCov = true>
 __device__ __forceinline__ bool transport(Helix<F>& h, F dx, F b, F smax, F kk = F(0),
                                           F m2 = F(0)) {
   const F one = F(1), half = F(0.5), two = F(2);
@@ -340,6 +342,7 @@ __device__ __forceinline__ bool transport(Helix<F>& h, F dx, F b, F smax, F kk =
   h.y = fma_(dx, tmid, h.y);
   h.z = fma_(h.t, arc, h.z);
   h.s = s1;
+  if (!kCov) return true;
 
   F* c = h.c;
   const F yy = c[0], zy = c[1], zz = c[2], sy = c[3], sz = c[4], ss = c[5];
@@ -477,6 +480,7 @@ __device__ __forceinline__ void reset_cov(Helix<F>& h, F vy, F vz, F cs0, F ct0,
 
 // From x to xt in equal steps of at most step_max (refused beyond 1000 cm,
 // longer than any path in the chamber, which also bounds the step count).
+template <bool kCov = true>
 __device__ __forceinline__ bool transport_to_x(Helix<double>& h, double x, double xt, double b,
                                                double smax, double step_max, double kk = 0.0,
                                                double m2 = 0.0) {
@@ -485,7 +489,7 @@ __device__ __forceinline__ bool transport_to_x(Helix<double>& h, double x, doubl
   const int n = max(1, (int)ceil(fabs(d) / step_max));
   const double dx = d / (double)n;
   for (int i = 0; i < n; ++i)
-    if (!transport(h, dx, b, smax, kk, m2)) return false;
+    if (!transport<double, kCov>(h, dx, b, smax, kk, m2)) return false;
   return true;
 }
 
