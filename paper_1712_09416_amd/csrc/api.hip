@@ -125,7 +125,8 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   s.row_off = c.take<uint32_t>(SR + 1);
   s.bins = c.take<RowBins>(SR);
   s.row_bin = c.take<uint32_t>(SR + 1);
-  s.bin_off = c.take<uint32_t>(kBinsPerHit * N + SR + 1);
+  // a row of n hits has at most kBinsPerHit * max(n, 1) bins, plus one end entry
+  s.bin_off = c.take<uint32_t>(kBinsPerHit * (N + SR) + SR + 1);
   s.rank = c.take<uint32_t>(N);
   s.hit = c.take<Hit>(N);
   s.up = c.take<int32_t>(N);

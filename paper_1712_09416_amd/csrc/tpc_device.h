@@ -80,7 +80,7 @@ struct Slot {
   uint32_t* row_off;        // [SR+1] first sorted hit of each (sector, row)
   RowBins* bins;            // [SR]
   uint32_t* row_bin;        // [SR+1] bins per row, then the rows' first bin
-  uint32_t* bin_off;        // [n + SR + 1]
+  uint32_t* bin_off;        // [2 (n + SR) + SR + 1] per row: its bins' first hits, then the end
   uint32_t* rank;           // [n]
   Hit* hit;                 // [n] sorted by (sector, row, bin, id)
   // links (sorted-hit indices, -1 none); the cleaned up-link lives in hit[].upc

@@ -255,6 +255,16 @@ def test_edge_cases(dev):
     # the context is still usable afterwards
     t, h = run(sec, np.arange(159), 0.05 * x, -0.5 * x)
     assert len(t) == 1
+    # capacity of one cluster: every pad row empty or nearly so, each with
+    # its largest number of bins (the bin table's worst case per cluster)
+    small = Tracker(geo, max_clusters=1)
+    for args in (([], [], [], []), ([7], [80], [2.0], [30.0])):
+        small.load(0, *[torch.from_numpy(np.asarray(a, d)).to(dev) for a, d in
+                        zip(args, (np.uint8, np.uint8, np.float32, np.float32))])
+        small.track_event(0)
+        t, h = small.get_tracks(0)
+        assert len(t) == 0 and len(h) == 0
+    small.close()
     trk.close()
 
 
