@@ -271,7 +271,9 @@ int tpc_get_merge_links(tpc_ctx* ctx, int slot, int event, int32_t* link_out, in
  * cm, 1 is added to bin floor((z0 - z_lo) / w) (w = (z_hi - z_lo) / n_bins,
  * in range only) of hist[side][n_bins] (device memory, uint32, side 0 = A;
  * the caller zeroes it; integer atomics, so counts do not depend on order).
- * Asynchronous on the context stream (covered by tpc_poll).  Errors:
+ * Asynchronous on the context stream (covered by tpc_poll); the context
+ * stream does not wait for other streams, so writes of hist queued
+ * elsewhere must be ordered before the call by the caller.  Errors:
  * TPC_EINVAL, TPC_ESTATE (slot not tracked).
  *
  * tpc_calib_fit: on the given stream (device hist and out), each side's
@@ -281,8 +283,9 @@ int tpc_get_merge_links(tpc_ctx* ctx, int slot, int event, int32_t* link_out, in
  * stream of its own.  Errors: TPC_EINVAL, TPC_EDEVICE.
  *
  * tpc_calib_correct_z: z[i] <- (z[i] + side eps z_max) / (1 + eps) for n
- * device clusters (side from sector[i]); |eps| < 0.5.  Asynchronous on the
- * context stream.  Errors: TPC_EINVAL. */
+ * device clusters (side from sector[i]), in place; |eps| < 0.5.
+ * Asynchronous on the context stream (same ordering rule as above).
+ * Errors: TPC_EINVAL. */
 int tpc_calib_accumulate(tpc_ctx* ctx, int slot, uint32_t* hist, int n_bins, float z_lo,
                          float z_hi);
 int tpc_calib_fit(const uint32_t* hist, int n_bins, float z_lo, float z_hi, float z_max,
