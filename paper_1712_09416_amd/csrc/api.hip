@@ -393,7 +393,8 @@ int finalize(tpc_ctx* ctx, SlotHost& h) {
   k_order<<<std::max(nbn, (h.n_events + 256) / 256), 256, 0, st>>>(s);
   scan_u32(st, s.out_ntk, s.out_count, s.cap_tk, s.scan_b, s.out_count + 1);
   k_event_hits<<<(h.n_events + 1 + 255) / 256, 256, 0, st>>>(s);
-  k_write_out<<<grid_stride_blocks(std::max<int64_t>(1, h.n / 50), 64), 64, 0, st>>>(s, ctx->k);
+  // 8 lanes per track (tracks <= clusters / 10 + sectors)
+  k_write_out<<<grid_stride_blocks(std::max<int64_t>(1, h.n / 50) * 8, 256, 16384), 256, 0, st>>>(s, ctx->k);
   mark(ctx, 7);
   TPC_LAUNCHED();
   h.state = 4;

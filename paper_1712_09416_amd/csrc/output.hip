@@ -177,20 +177,25 @@ __global__ void k_event_hits(Slot S) {
   if (e <= S.n_events) S.ev_hit_off[e] = S.out_ntk[S.ev_track_off[e]];
 }
 
+// Track records and hit lists (hit offsets relative to the event).  A group
+// of kOutLanes lanes per track: its first lane writes the record, the group
+// copies the hit IDs (lane u of the group takes every kOutLanes-th hit, up
+// to kOutBatch of them per memory round trip).
+constexpr int kOutLanes = 8;
 constexpr int kOutBatch = 8;
 
-// Track records and hit lists (hit offsets relative to the event).
 __global__ void k_write_out(Slot S, DevConst K) {
   const uint32_t ntk = S.out_count[0];
-  const uint32_t stride = gridDim.x * blockDim.x;
-  const uint32_t t0 = blockIdx.x * blockDim.x + threadIdx.x;
-  for (uint32_t pos = t0; pos < ntk; pos += stride) {
+  const uint32_t ngroups = gridDim.x * blockDim.x / kOutLanes;
+  const uint32_t gid = (blockIdx.x * blockDim.x + threadIdx.x) / kOutLanes;
+  const int sub = (int)(threadIdx.x % kOutLanes);
+  for (uint32_t pos = gid; pos < ntk; pos += ngroups) {
     const int32_t k = S.out_order[pos];
     const int32_t* ti = S.tk_info + (size_t)k * 4;
-    const int32_t T = S.tk_tracklet[k];
     const int nown = S.tk_nown[k];
     const int32_t* own = S.tk_own + (size_t)k * kRows;
-    const int j0 = nown - ti[1];          // the fitted hits are the last n_hits owned ones
+    const int nh = ti[1];
+    const int j0 = nown - nh;             // the fitted hits are the last n_hits owned ones
     const uint32_t gidx = S.hit[own[j0]].id;
     int e = 0;
     {
@@ -203,37 +208,43 @@ __global__ void k_write_out(Slot S, DevConst K) {
     }
     const int64_t ev0 = S.ev_off[e];
     const uint32_t hoff = S.out_ntk[pos];
-    const uint32_t ehoff = S.ev_hit_off[e];
-    tpc_track o;
-    o.sector = (int32_t)S.sector[gidx];
-    o.n_hits = ti[1];
-    o.row_in = ti[2];
-    o.row_out = ti[3];
-    o.hit_off = (int64_t)(hoff - ehoff);
-    o.inner_id = (int32_t)((int64_t)gidx - ev0);
-    o.start_id = (int32_t)((int64_t)S.hit[S.start_hit[T]].id - ev0);
-    o.x_ref = (double)K.row_x[ti[2]];
-    o.ndf = 2 * ti[1] - 5;
-    o.event = e;
-    const double* par = S.tk_par + (size_t)k * 5;
-    const double* cov = S.tk_cov + (size_t)k * 15;
-    for (int i = 0; i < 5; ++i) o.par[i] = par[i];
-    for (int i = 0; i < 15; ++i) o.cov[i] = cov[i];
-    o.chi2 = S.tk_chi2[k];
-    S.out_tracks[pos] = o;
-    // hit IDs kOutBatch at a time: the batch's positions, then their
-    // records, are loaded together before any store
+    if (sub == 0) {
+      const int32_t T = S.tk_tracklet[k];
+      const uint32_t ehoff = S.ev_hit_off[e];
+      tpc_track o;
+      o.sector = (int32_t)S.sector[gidx];
+      o.n_hits = nh;
+      o.row_in = ti[2];
+      o.row_out = ti[3];
+      o.hit_off = (int64_t)(hoff - ehoff);
+      o.inner_id = (int32_t)((int64_t)gidx - ev0);
+      o.start_id = (int32_t)((int64_t)S.hit[S.start_hit[T]].id - ev0);
+      o.x_ref = (double)K.row_x[ti[2]];
+      o.ndf = 2 * nh - 5;
+      o.event = e;
+      const double* par = S.tk_par + (size_t)k * 5;
+      const double* cov = S.tk_cov + (size_t)k * 15;
+      for (int i = 0; i < 5; ++i) o.par[i] = par[i];
+      for (int i = 0; i < 15; ++i) o.cov[i] = cov[i];
+      o.chi2 = S.tk_chi2[k];
+      S.out_tracks[pos] = o;
+    }
     int32_t* dst = S.out_hits + hoff;
-    for (int jb = j0; jb < nown; jb += kOutBatch) {
+    for (int ib = sub; ib < nh; ib += kOutLanes * kOutBatch) {
       int32_t pv[kOutBatch];
 #pragma unroll
-      for (int u = 0; u < kOutBatch; ++u) pv[u] = jb + u < nown ? own[jb + u] : -1;
+      for (int u = 0; u < kOutBatch; ++u) {
+        const int i = ib + u * kOutLanes;
+        pv[u] = i < nh ? own[j0 + i] : -1;
+      }
       uint32_t iv[kOutBatch];
 #pragma unroll
       for (int u = 0; u < kOutBatch; ++u) iv[u] = pv[u] >= 0 ? S.hit[pv[u]].id : 0u;
 #pragma unroll
-      for (int u = 0; u < kOutBatch; ++u)
-        if (jb + u < nown) dst[jb + u - j0] = (int32_t)((int64_t)iv[u] - ev0);
+      for (int u = 0; u < kOutBatch; ++u) {
+        const int i = ib + u * kOutLanes;
+        if (i < nh) dst[i] = (int32_t)((int64_t)iv[u] - ev0);
+      }
     }
   }
 }
