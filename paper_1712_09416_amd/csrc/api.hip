@@ -135,7 +135,7 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   s.tl_base = c.take<uint32_t>(S + 1);
   s.tk_base = c.take<uint32_t>(S + 1);
   s.row_nstart = c.take<uint32_t>(SR + 1);
-  s.range_cnt = c.take<uint32_t>(4);
+  s.range_cnt = c.take<uint32_t>(16);
   s.big_rows = c.take<uint32_t>(N / 1024 + 1);
   s.start_hit = c.take<int32_t>(cap_tl);
   s.start_sr = c.take<int32_t>(cap_tl);
@@ -224,7 +224,7 @@ void carve_lanes(Carver& c, const tpc_params& p, Lane* lanes) {
   const int64_t SR = S * kRows;
   const int64_t cap_tl = N / 3 + S;
   for (int i = 0; i < kMaxLanes; ++i) {
-    uint32_t* a = c.take<uint32_t>(4);
+    uint32_t* a = c.take<uint32_t>(16);
     uint32_t* b = c.take<uint32_t>(std::max<int64_t>(std::max<int64_t>(N, SR), cap_tl) / kScanTile + 4);
     uint32_t* t = c.take<uint32_t>(cap_tl + 1);
     if (lanes) {
@@ -365,7 +365,8 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
   const int64_t tl_bound = std::min<int64_t>(s.cap_tl, h.n / 3 + ns);
   const int nb_lane = std::max(8, grid_stride_blocks(tl_bound, 64, 16384) / 8 * 8);
   const int nb_sel = grid_stride_blocks(tl_bound, 256, 4096);
-  k_neighbours<<<((ns * kRows + 7) / 8) * 8, 256, 0, st>>>(s, ctx->k, g0, ns);
+  k_nf_split<<<1, 64, 0, st>>>(s, g0, ns);
+  k_neighbours<<<((ns * kRows + 7) / 8) * 8, 256, 0, st>>>(s, ctx->k, g0);
   if (marks) mark(ctx, 2);
   k_clean_rows<<<dim3(kRows, ns), 256, 0, st>>>(s, g0);
   scan_u32(st, s.row_nstart + (size_t)g0 * kRows, nullptr, (int64_t)ns * kRows, s.scan_b,

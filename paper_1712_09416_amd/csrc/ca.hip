@@ -37,7 +37,7 @@ struct PairBest {
 
 constexpr int kNfCand = 32;      // up-row candidates listed per hit before a nested scan
 
-// a3: one block per (sector, row).  For each hit h of row r (1..157), the
+// a3: for each hit h of row r (1..157), the
 // pair (d in row r-1, u in row r+1) inside the origin-pointing windows
 // |y - y_h x_r'/x_r| <= W, |z - z_h x_r'/x_r| <= W whose straight line passes
 // closest to h, measured by m = dy^2 / (1.5 sy^2) + dz^2 / (1.5 sz^2);
@@ -50,18 +50,10 @@ constexpr int kNfCand = 32;      // up-row candidates listed per hit before a ne
 // are read through the caches with the batched window reads (measured
 // faster than staging the rows in LDS, and than holding the candidates in
 // registers, whose fixed-length pairing loop costs more than it saves).
-// Blocks are dealt round-robin over the 8 XCDs; block b serves the
-// (sector, row) pair number (b % 8) * per + b / 8 of the launched range, so
-// each XCD works through one contiguous stretch of sectors, row after row,
-// and the rows r-1, r+1 that neighbouring blocks read stay in its L2.
-__global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, int g0, int ns) {
-  __shared__ uint32_t cand[kNfCand * kNfThreads];
-  const int total = ns * kRows;
-  const int per = (total + 7) / 8;
-  const int v = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (v >= total) return;
-  const int row = v % kRows;
-  const int g = g0 + v / kRows;
+// This function: the hits of pad row `row` of sector g, `my` the thread's
+// candidate slots in LDS.
+__device__ __forceinline__ void nf_row(const Slot& S, const DevConst& K, int g, int row,
+                                       uint32_t* my) {
   const int sr = g * kRows + row;
   const uint32_t h0 = S.row_off[sr], h1 = S.row_off[sr + 1];
   if (row == 0 || row == kRows - 1) {
@@ -79,7 +71,6 @@ __global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, i
   const float rho_u = K.row_x[row + 1] / xr;
   const float f = (xr - K.row_x[row - 1]) / (K.row_x[row + 1] - K.row_x[row - 1]);
   const float W = K.nf_w;
-  uint32_t* my = cand + threadIdx.x;
   for (uint32_t h = h0 + threadIdx.x; h < h1; h += blockDim.x) {
     const Hit x = S.hit[h];
     const float yh = x.y, zh = x.z;
@@ -118,6 +109,41 @@ __global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, i
     S.up[h] = ok ? best.u : -1;
     S.dn[h] = ok ? best.d : -1;
   }
+}
+
+// Split of the launched rows over the 8 XCDs, balanced by hits: XCD x takes
+// the rows [split[x], split[x+1]) (indices from the range's first row), those
+// whose first hit lies in the x-th eighth of the range's hits.  Stored in
+// range_cnt[4 .. 12].
+__global__ void k_nf_split(Slot S, int g0, int ns) {
+  const int x = threadIdx.x;
+  if (x > 8) return;
+  const uint32_t* ro = S.row_off + (size_t)g0 * kRows;
+  const int nr = ns * kRows;
+  int v = x == 0 ? 0 : nr;
+  if (x > 0 && x < 8) {
+    const uint64_t hits = ro[nr] - ro[0];
+    const uint32_t target = ro[0] + (uint32_t)(hits * (uint64_t)x / 8u);
+    int lo = 0, hi = nr;            // first row whose first hit is at or after target
+    while (lo < hi) {
+      const int mid = (lo + hi) / 2;
+      if (ro[mid] < target) lo = mid + 1; else hi = mid;
+    }
+    v = lo;
+  }
+  S.range_cnt[4 + x] = (uint32_t)v;
+}
+
+// Blocks are dealt round-robin over the 8 XCDs; the blocks of XCD x stride
+// over its contiguous stretch of rows (k_nf_split), so the rows r-1, r+1
+// that neighbouring blocks read stay in its L2 and every XCD gets the same
+// number of hits however different the sectors' sizes are.
+__global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, int g0) {
+  __shared__ uint32_t cand[kNfCand * kNfThreads];
+  const int x = (int)(blockIdx.x % 8), nbx = (int)(gridDim.x / 8);
+  const int v1 = (int)S.range_cnt[5 + x];
+  for (int v = (int)S.range_cnt[4 + x] + (int)(blockIdx.x / 8); v < v1; v += nbx)
+    nf_row(S, K, g0 + v / kRows, v % kRows, cand + threadIdx.x);
 }
 
 // Start of a cleaned chain of >= 3 hits, from the links of a3 only.
