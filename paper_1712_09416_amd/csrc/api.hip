@@ -368,10 +368,12 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
   k_nf_split<<<1, 64, 0, st>>>(s, g0, ns);
   k_neighbours<<<((ns * kRows + 7) / 8) * 8, 256, 0, st>>>(s, ctx->k, g0);
   if (marks) mark(ctx, 2);
-  k_clean_rows<<<dim3(kRows, ns), 256, 0, st>>>(s, g0);
+  // a wave per pad row
+  const int nb_rows = grid_stride_blocks((int64_t)ns * kRows * 64, 256, 16384);
+  k_clean_rows<<<nb_rows, 256, 0, st>>>(s, g0, ns);
   scan_u32(st, s.row_nstart + (size_t)g0 * kRows, nullptr, (int64_t)ns * kRows, s.scan_b,
            s.range_cnt + 0, false);
-  k_start_write<<<dim3(kRows, ns), 256, 0, st>>>(s, g0);
+  k_start_write<<<nb_rows, 256, 0, st>>>(s, g0, ns);
   if (marks) mark(ctx, 3);
   k_tracklets<<<nb_lane, 64, 0, st>>>(s, ctx->k, g0);
   if (marks) mark(ctx, 4);

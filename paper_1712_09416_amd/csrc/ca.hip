@@ -157,68 +157,59 @@ __device__ __forceinline__ bool is_start(const Slot& S, uint32_t h, int32_t& uc,
 }
 
 // a4: keep a link only if it is mutual; count the start hits of each row.
-// Also clears the hit weights used by the tracklet selection.
-__global__ void __launch_bounds__(256) k_clean_rows(Slot S, int g0) {
-  __shared__ uint32_t count;
-  const int row = blockIdx.x;
-  const int g = g0 + blockIdx.y;
-  const int sr = g * kRows + row;
-  const uint32_t h0 = S.row_off[sr], h1 = S.row_off[sr + 1];
-  if (threadIdx.x == 0) count = 0;
-  __syncthreads();
-  for (uint32_t base = h0; base < h1; base += blockDim.x) {
-    const uint32_t h = base + threadIdx.x;
-    bool start = false;
-    if (h < h1) {
-      int32_t uc, dc;
-      start = is_start(S, h, uc, dc);
-      S.hit[h].upc = uc;
-      S.dnc[h] = dc;
-      S.weight[h] = 0u;
+// Also clears the hit weights used by the tracklet selection.  One wave per
+// row (rows hold ~100 hits), 64 hits at a time.
+__global__ void __launch_bounds__(256) k_clean_rows(Slot S, int g0, int ns) {
+  const int lane = threadIdx.x & 63;
+  const int nwaves = (int)(gridDim.x * blockDim.x / 64);
+  const int nr = ns * kRows;
+  for (int v = (int)((blockIdx.x * blockDim.x + threadIdx.x) / 64); v < nr; v += nwaves) {
+    const int sr = g0 * kRows + v;
+    const uint32_t h0 = S.row_off[sr], h1 = S.row_off[sr + 1];
+    uint32_t count = 0;
+    for (uint32_t base = h0; base < h1; base += 64) {
+      const uint32_t h = base + lane;
+      bool start = false;
+      if (h < h1) {
+        int32_t uc, dc;
+        start = is_start(S, h, uc, dc);
+        S.hit[h].upc = uc;
+        S.dnc[h] = dc;
+        S.weight[h] = 0u;
+      }
+      count += (uint32_t)__popcll(__ballot(start));
     }
-    const unsigned long long m = __ballot(start);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&count, (uint32_t)__popcll(m));
+    if (lane == 0) S.row_nstart[sr] = count;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) S.row_nstart[sr] = count;
 }
 
 // a4: write the start hits in (sector, row, position) order at the offsets
 // given by the scan of the per-row counts over the launched sector range.
-__global__ void __launch_bounds__(256) k_start_write(Slot S, int g0) {
-  __shared__ uint32_t wcount[4];
-  __shared__ uint32_t running;
-  const int row = blockIdx.x;
-  const int g = g0 + blockIdx.y;
-  const int sr = g * kRows + row;
-  const uint32_t h0 = S.row_off[sr], h1 = S.row_off[sr + 1];
-  const uint32_t base_out = S.tl_base[g0] + S.row_nstart[sr];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (threadIdx.x == 0) running = 0;
-  __syncthreads();
-  for (uint32_t base = h0; base < h1; base += blockDim.x) {
-    const uint32_t h = base + threadIdx.x;
-    bool start = false;
-    if (h < h1) {
-      int32_t uc, dc;
-      start = is_start(S, h, uc, dc);
+// One wave per row, as in k_clean_rows.
+__global__ void __launch_bounds__(256) k_start_write(Slot S, int g0, int ns) {
+  const int lane = threadIdx.x & 63;
+  const int nwaves = (int)(gridDim.x * blockDim.x / 64);
+  const int nr = ns * kRows;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int v = (int)((blockIdx.x * blockDim.x + threadIdx.x) / 64); v < nr; v += nwaves) {
+    const int sr = g0 * kRows + v;
+    const uint32_t h0 = S.row_off[sr], h1 = S.row_off[sr + 1];
+    uint32_t out = S.tl_base[g0] + S.row_nstart[sr];
+    for (uint32_t base = h0; base < h1; base += 64) {
+      const uint32_t h = base + lane;
+      bool start = false;
+      if (h < h1) {
+        int32_t uc, dc;
+        start = is_start(S, h, uc, dc);
+      }
+      const unsigned long long m = __ballot(start);
+      if (start) {
+        const uint32_t k = out + (uint32_t)__popcll(m & below);
+        S.start_hit[k] = (int32_t)h;
+        S.start_sr[k] = sr;
+      }
+      out += (uint32_t)__popcll(m);
     }
-    const unsigned long long m = __ballot(start);
-    if (lane == 0) wcount[w] = (uint32_t)__popcll(m);
-    __syncthreads();
-    uint32_t before = running, tot = 0;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
-      if (i < w) before += wcount[i];
-      tot += wcount[i];
-    }
-    if (start) {
-      const uint32_t k = base_out + before + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-      S.start_hit[k] = (int32_t)h;
-      S.start_sr[k] = sr;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) running += tot;
-    __syncthreads();
   }
 }
 

@@ -15,8 +15,8 @@ __global__ void k_row_sort_large(Slot S);
 // cellular automaton
 __global__ void k_nf_split(Slot S, int g0, int ns);
 __global__ void k_neighbours(Slot S, DevConst K, int g0);
-__global__ void k_clean_rows(Slot S, int g0);
-__global__ void k_start_write(Slot S, int g0);
+__global__ void k_clean_rows(Slot S, int g0, int ns);
+__global__ void k_start_write(Slot S, int g0, int ns);
 // Kalman filter
 __global__ void k_tracklets(Slot S, DevConst K, int g0);
 __global__ void k_select(Slot S, DevConst K, int g0);
