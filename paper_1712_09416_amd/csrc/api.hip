@@ -344,6 +344,7 @@ int build_grid(tpc_ctx* ctx, SlotHost& h) {
   scan_u32(st, s.tl_base, nullptr, s.n_sectors, s.scan_b, nullptr);
   scan_u32(st, s.tk_base, nullptr, s.n_sectors, s.scan_b, nullptr);
   k_scatter<<<grid_stride_blocks(h.n, 256), 256, 0, st>>>(s);
+  k_row_sort_tiny<<<(unsigned)SR, 64, 0, st>>>(s);
   k_row_sort_small<<<(unsigned)SR, 256, 0, st>>>(s);
   k_row_sort_large<<<64, 256, 0, st>>>(s);
   TPC_LAUNCHED();

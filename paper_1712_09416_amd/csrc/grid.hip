@@ -229,7 +229,7 @@ __global__ void k_scatter(Slot S) {
 // the row's bin offsets.  CAP is the largest row the instance handles; the
 // instance for rows up to kMaxRowHits also handles the over-full rows.
 template <int CAP>
-__device__ __forceinline__ void row_sort(Slot& S, int sr, bool small) {
+__device__ __forceinline__ void row_sort(Slot& S, int sr, uint32_t skip_upto, bool small) {
   __shared__ float ly[CAP];
   __shared__ float lz[CAP];
   __shared__ uint32_t lid[CAP];
@@ -240,6 +240,7 @@ __device__ __forceinline__ void row_sort(Slot& S, int sr, bool small) {
   __shared__ uint32_t wsum[4];
   const uint32_t off = S.row_off[sr];
   const uint32_t n = S.row_off[sr + 1] - off;
+  if (n <= skip_upto && skip_upto > 0) return;   // a smaller instance's row
   if (small && n > (uint32_t)CAP) {          // left to the large instance
     if (threadIdx.x == 0) S.big_rows[atomicAdd(&S.range_cnt[2], 1u)] = sr;
     return;
@@ -325,13 +326,23 @@ __device__ __forceinline__ void row_sort(Slot& S, int sr, bool small) {
   for (int bb = threadIdx.x; bb <= nb; bb += blockDim.x) S.bin_off[b.base + bb] = off + hist[bb];
 }
 
-// every row; rows over 1024 hits are listed for the large instance
-__global__ void __launch_bounds__(256) k_row_sort_small(Slot S) { row_sort<1024>(S, blockIdx.x, true); }
+// rows of at most kTinyRow hits (most rows of a batch of small events):
+// one wave per row, so many rows share a CU
+constexpr int kTinyRow = 256;
+__global__ void __launch_bounds__(64) k_row_sort_tiny(Slot S) {
+  const int sr = blockIdx.x;
+  if (S.row_off[sr + 1] - S.row_off[sr] > (uint32_t)kTinyRow) return;
+  row_sort<kTinyRow>(S, sr, 0, false);
+}
+// rows of kTinyRow+1 .. 1024 hits; larger ones are listed for the large instance
+__global__ void __launch_bounds__(256) k_row_sort_small(Slot S) {
+  row_sort<1024>(S, blockIdx.x, kTinyRow, true);
+}
 // the listed rows (1025..4096 hits, and the over-full ones)
 __global__ void __launch_bounds__(256) k_row_sort_large(Slot S) {
   const uint32_t nbig = S.range_cnt[2];
   for (uint32_t i = blockIdx.x; i < nbig; i += gridDim.x) {
-    row_sort<kMaxRowHits>(S, (int)S.big_rows[i], false);
+    row_sort<kMaxRowHits>(S, (int)S.big_rows[i], 0, false);
     __syncthreads();
   }
 }

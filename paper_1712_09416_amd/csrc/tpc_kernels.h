@@ -10,6 +10,7 @@ __global__ void k_count(Slot S);
 __global__ void k_row_layout(Slot S, DevConst K);
 __global__ void k_row_finish(Slot S);
 __global__ void k_scatter(Slot S);
+__global__ void k_row_sort_tiny(Slot S);
 __global__ void k_row_sort_small(Slot S);
 __global__ void k_row_sort_large(Slot S);
 // cellular automaton
