@@ -163,29 +163,23 @@ def test_pbpb_small_events(dev, oracle_lib, seed_off):
     compare_replay(tracks, ref.replay)
 
 
-def test_central_event_sampled_sectors(dev, oracle_lib):
+def test_central_event_all_sectors(dev, oracle_lib):
     """The central Pb-Pb-shaped event at full size on the GPU (all sectors in
-    one launch per step); the oracle tracks four of its sectors (sectors are
-    independent), and those must agree exactly."""
+    one launch per step, the bench's configuration) against the oracle on the
+    whole event: links, hit lists, parameters and covariances identical, and
+    within the bar of the double replay."""
+    import os
     ev = tpcgen.central_event()
     say(f"central event: {ev.n} clusters")
     tracks, hits, lk = gpu_run(ev, dev)
-    secs = [0, 17, 18, 35]
-    sel = np.nonzero(np.isin(ev.sector, secs))[0]
-    ref = oracle_lib.run(ev.sector[sel], ev.row[sel], ev.y[sel], ev.z[sel], ev.geometry(),
-                         precision=32, replay=True, nthreads=4)
-    compare_links(lk, ref, sel)
-    m = np.isin(tracks["sector"], secs)
-    sub = tracks[m]
-    sub_hits = np.concatenate([hits[t["hit_off"]: t["hit_off"] + t["n_hits"]] for t in sub])
-    sub = sub.copy()
-    sub["hit_off"] = np.concatenate([[0], np.cumsum(sub["n_hits"])[:-1]])
-    compare_tracks(sub, sub_hits, ref, sel)
-    compare_replay(sub, ref.replay)
-    # whole event: every track is well formed
+    ref = oracle_lib.run_event(ev, precision=32, replay=True,
+                               nthreads=max(1, min(16, os.cpu_count() or 1)))
+    compare_links(lk, ref)
+    compare_tracks(tracks, hits, ref)
+    compare_replay(tracks, ref.replay)
     assert np.all(np.diff(tracks["inner_id"]) > 0)
     assert len(np.unique(hits)) == len(hits)
-    say(f"central event: {len(tracks)} tracks, {len(hits)} hits")
+    say(f"central event: {len(tracks)} tracks, {len(hits)} hits, identical to the oracle")
 
 
 def test_batch_equals_single_events(dev, oracle_lib):
