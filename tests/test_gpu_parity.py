@@ -208,6 +208,41 @@ def test_batch_equals_single_events(dev, oracle_lib):
     trk.close()
 
 
+def test_full_batch_graph_equals_single_events(dev):
+    """The bench's batch at full size (64 Pb-Pb-shaped events of
+    multiplicity 50-15000, 31.5M clusters, 2304 sectors in one launch per
+    step), replayed from a HIP graph: every event's tracks equal those of
+    the event tracked alone."""
+    from paper_1712_09416_amd import Tracker
+    from tpcgen import parallel
+    mult = tpcgen.batch_multiplicities(64)
+    gen = parallel.generate([("batch", (e, int(m))) for e, m in enumerate(mult)])
+    offs = np.concatenate([[0], np.cumsum([len(d["y"]) for d in gen])]).astype(np.int64)
+    say(f"batch: {len(gen)} events, {offs[-1]} clusters")
+    cat = [torch.from_numpy(np.concatenate([d[k] for d in gen])).to(dev)
+           for k in ("sector", "row", "y", "z")]
+    geo = tpcgen.geometry.geometry_dict(gen[0]["sigma"])
+    trk = Tracker(geo, max_events=len(gen), max_clusters=int(offs[-1]))
+    trk.load_batch(0, offs, *cat)
+    trk.capture(0)
+    trk.launch(0)
+    trk.launch(0)
+    one = Tracker(geo, max_clusters=int(np.diff(offs).max()))
+    for e in range(len(gen)):
+        tb, hb = trk.get_tracks(0, e)
+        sl = slice(int(offs[e]), int(offs[e + 1]))
+        one.load(0, *[c[sl] for c in cat])
+        one.track_event(0)
+        ts, hs = one.get_tracks(0)
+        assert np.array_equal(hb, hs), e
+        for k in ("n_hits", "inner_id", "hit_off", "par", "cov", "chi2", "sector"):
+            assert np.array_equal(tb[k], ts[k]), (e, k)
+    say(f"batch: {sum(len(trk.get_tracks(0, e)[0]) for e in range(len(gen)))} tracks, "
+        "each event identical to its single run")
+    one.close()
+    trk.close()
+
+
 def test_edge_cases(dev):
     from paper_1712_09416_amd import Tracker, TpcError
     geo = tpcgen.geometry.geometry_dict()
