@@ -293,8 +293,8 @@ def main() -> int:
                     help="requests of the serving workload (0: skip it)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the tracker "
-              "shards by events/sectors with no exchange, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for {args.gpus}); events and sectors are "
+              "independent, so more GPUs would each take whole events", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -439,6 +439,9 @@ def main() -> int:
             "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_tracklets",
             "algorithmic_bytes": tracklet_bytes(counters),
             "launch_ms": stage_ms["tracklets"], "copy_kernel_gbs": copy_gbs}
+    if traffic is not None:
+        # the measured L2-miss traffic per launch over the same launch time
+        roof["traffic_gbs"] = traffic / t_tl / 1e9
 
     out = {
         "metric": METRIC,
