@@ -139,7 +139,7 @@ struct PassOut {
 // One inward pass over the owned hits own[jmin .. n-1] (ascending rows):
 // state reset to the outermost hit with the prior covariance, transport row
 // by row, update with every owned hit (no gate).  A failed transport ends
-// the pass.  The next hit is loaded one step ahead of its use.
+// the pass.  Memory reads are issued ahead of their use.
 __device__ __forceinline__ void refit_pass(const Slot& S, const DevConst& K, const int32_t* own,
                            const uint8_t* own_row, int n, int jmin, double s0, double t0,
                            double q0, PassOut& o) {
@@ -161,17 +161,27 @@ __device__ __forceinline__ void refit_pass(const Slot& S, const DevConst& K, con
   o.n = 1;
   o.chi2 = 0.0;
   const double smax = K.smax, chi2max = K.chi2max;
-  // row-synchronous walk (every lane moves one row per iteration); the next
-  // owned hit is loaded one hit ahead
+  // row-synchronous walk (every lane moves one row per iteration).  Every
+  // memory read of a step is issued at its top and used after the
+  // transport: the radius of the next row, the record of the next owned
+  // hit (own[j]) and the list entry after it (own[j - 1]); indices clamped
+  // into [jmin, n) and row 0 so the reads stay inside the lists.
   int j = n - 2;
   int rn = j >= jmin ? (int)own_row[j] : -1;
-  Hit xn;
-  if (j >= jmin) xn = S.hit[own[j]];
+  int32_t pn = own[max(j, jmin)];
   const int rstop = j >= jmin ? (int)own_row[jmin] : o.rlast;
+  double x_hi = (double)K.row_x[o.rlast];
+  float x_next = K.row_x[max(o.rlast - 1, 0)];
   for (int r = o.rlast - 1; r >= rstop; --r) {
-    if (!transport(st, (double)K.row_x[r] - (double)K.row_x[r + 1], K.bd, smax, K.kkd, K.m2d)) break;
+    const double x_lo = (double)x_next;
+    x_next = K.row_x[max(r - 1, 0)];
+    const Hit xh = S.hit[pn];
+    const int ja = max(j - 1, jmin);
+    const int32_t p_after = own[ja];
+    const int r_after = own_row[ja];
+    if (!transport(st, x_lo - x_hi, K.bd, smax, K.kkd, K.m2d)) break;
+    x_hi = x_lo;
     if (r != rn) continue;
-    const Hit xh = xn;
     const double sy = sy0 + sy1z * fabs(st.z), sz = sz0 + sz1z * fabs(st.z);
     double ch = 0.0;
     kalman_update(st, (double)xh.y, (double)xh.z, sy * sy, sz * sz, chi2max, smax, false, &ch);
@@ -181,12 +191,8 @@ __device__ __forceinline__ void refit_pass(const Slot& S, const DevConst& K, con
     o.rlast = r;
     o.jlast = j;
     --j;
-    if (j >= jmin) {
-      rn = own_row[j];
-      xn = S.hit[own[j]];
-    } else {
-      rn = -1;
-    }
+    pn = p_after;
+    rn = j >= jmin ? r_after : -1;
   }
 }
 

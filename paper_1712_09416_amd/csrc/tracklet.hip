@@ -7,10 +7,10 @@
 
 namespace tpc {
 
-// Stop rules after a transport to row r: left the sector sideways, crossed
-// the membrane, or left the drift volume.
-__device__ __forceinline__ bool inside(const DevConst& K, const Helix<float>& h, int r, bool side_c) {
-  if (!(fabsf(h.y) <= K.row_x[r] * K.tanh_half + K.medge)) return false;
+// Stop rules after a transport to the row at radius xr: left the sector
+// sideways, crossed the membrane, or left the drift volume.
+__device__ __forceinline__ bool inside(const DevConst& K, const Helix<float>& h, float xr, bool side_c) {
+  if (!(fabsf(h.y) <= xr * K.tanh_half + K.medge)) return false;
   if (!(fabsf(h.z) <= K.z_max + K.mz)) return false;
   if (side_c ? (h.z > K.mz) : (h.z < -K.mz)) return false;
   return true;
@@ -89,9 +89,12 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
     const Hit x1 = S.hit[x0.upc];
     const TlRow hits = tl_row(S, T);
 
+    // radii of the start row and the next one (r0 <= 157: a start hit has
+    // an up link)
+    const float x_r0 = K.row_x[r0], x_r1 = K.row_x[r0 + 1];
     Helix<float> st;
     {
-      const float dx = K.row_x[r0 + 1] - K.row_x[r0];
+      const float dx = x_r1 - x_r0;
       const float dy = x1.y - x0.y;
       const float dz = x1.z - x0.z;
       const float L = sqrtf(dx * dx + dy * dy);
@@ -108,15 +111,27 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
     // outward
     Helix<float> last = st;
     int rout = r0;
+    float x_rout = x_r0;
     int32_t next = x0.upc;     // cleaned chain link of the last accepted hit
-    Hit xnext = x1;            // that hit, loaded ahead of the transport
     bool chain = true;
     int miss = 0;
+    // row radii: the current one carried in a register, the next one read
+    // a step ahead (index clamped to the last row); both start from values
+    // the seed has used, so no read before the loop is waited for inside it
+    float x_prev = x_r0;
+    float x_ahead = x_r1;
     for (int r = r0 + 1; r < kRows; ++r) {
       ++visits;
-      const RowBins rb = S.bins[g * kRows + r];   // independent of the state: issued early
-      if (!transport(st, K.row_x[r] - K.row_x[r - 1], K.b, K.smax, K.kk, K.m2)) break;
-      if (!inside(K, st, r, side_c)) break;
+      const float xr = x_ahead;
+      x_ahead = K.row_x[min(r + 1, kRows - 1)];
+      // reads independent of the state, issued before the transport: the
+      // row's bin range and the hit the chain link points to
+      const RowBins rb = S.bins[g * kRows + r];
+      Hit xnext;
+      if (chain && next >= 0) xnext = S.hit[next];
+      if (!transport(st, xr - x_prev, K.b, K.smax, K.kk, K.m2)) break;
+      x_prev = xr;
+      if (!inside(K, st, xr, side_c)) break;
       const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
       const float vy = sy * sy, vz = sz * sz;
       int32_t got = -1;
@@ -135,10 +150,10 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
       hits[r] = got;
       if (got >= 0) {
         next = xg.upc;
-        if (chain && next >= 0) xnext = S.hit[next];
         miss = 0;
         last = st;
         rout = r;
+        x_rout = xr;
       } else if (++miss >= K.n_gap) {
         break;
       }
@@ -157,23 +172,30 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
     int rin = rout;
     last = st;
     miss = 0;
-    // the outward hit of the next row down, loaded one step ahead
+    // the outward hit of the next row down loaded one step ahead, the
+    // hit-list entry of the row below it two steps ahead
     int32_t uh_next = rout - 1 >= r0 && rout >= 1 ? hits[rout - 1] : -1;
     Hit xu_next;
     if (uh_next >= 0) xu_next = S.hit[uh_next];
+    int32_t uh_next2 = rout - 2 >= r0 ? hits[rout - 2] : -1;
+    x_prev = x_rout;
+    x_ahead = K.row_x[max(rout - 1, 0)];
+    // wait for this read here, once: a read still in flight at the loop's
+    // entry would make the compiler wait inside every step
+    asm volatile("" : "+v"(x_ahead));
     for (int r = rout - 1; r >= 0; --r) {
       ++visits;
+      const float xr = x_ahead;
+      x_ahead = K.row_x[max(r - 1, 0)];
       const RowBins rb = S.bins[g * kRows + r];
       const int32_t uh = uh_next;
       const Hit xu = xu_next;
-      if (r - 1 >= r0) {
-        uh_next = hits[r - 1];
-        if (uh_next >= 0) xu_next = S.hit[uh_next];
-      } else {
-        uh_next = -1;
-      }
-      if (!transport(st, K.row_x[r] - K.row_x[r + 1], K.b, K.smax, K.kk, K.m2)) break;
-      if (!inside(K, st, r, side_c)) break;
+      uh_next = uh_next2;
+      if (uh_next >= 0) xu_next = S.hit[uh_next];
+      uh_next2 = r - 2 >= r0 ? hits[r - 2] : -1;
+      if (!transport(st, xr - x_prev, K.b, K.smax, K.kk, K.m2)) break;
+      x_prev = xr;
+      if (!inside(K, st, xr, side_c)) break;
       const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
       const float vy = sy * sy, vz = sz * sz;
       int32_t got = -1;
