@@ -435,17 +435,37 @@ __device__ bool chain_pass(const Slot& S, const DevConst& K, const MergeConst& C
       cur_row = r;
       --k;
     }
-    // the segment's remaining hits, inward, each loaded one hit ahead
-    HitRec nx;
-    if (k >= 0) nx = load_hit(S, ev0 + h[k]);
-    for (; k >= 0; --k) {
-      const HitRec hr = nx;
-      if (k > 0) nx = load_hit(S, ev0 + h[k - 1]);
-      for (int rr = cur_row - 1; rr >= hr.row; --rr)
-        if (!transport(st, xrow(K, rr) - xrow(K, rr + 1), K.bd, C.smax, K.kkd, K.m2d)) return false;
-      chi2 = chi2 + update_yz(K, st, hr.y, hr.z);
-      ++n;
-      cur_row = hr.row;
+    // the segment's remaining hits h[k..0], inward (one hit per row, rows
+    // strictly descending), as a walk of row steps.  Every read of a step
+    // is issued at its top and used after the transport: the radius of the
+    // next row (the current one carried in a register), the next hit's
+    // coordinates, the row of the hit after it and the list entry after
+    // that (indices clamped to h[0]).
+    if (k >= 0) {
+      int64_t gn = ev0 + h[k];
+      int rn = S.row[gn];
+      int32_t h_after = h[max(k - 1, 0)];
+      const int rstop = S.row[ev0 + h[0]];
+      double x_hi = xrow(K, cur_row);
+      float x_next = K.row_x[max(cur_row - 1, 0)];
+      for (int r = cur_row - 1; r >= rstop; --r) {
+        const double x_lo = (double)x_next;
+        x_next = K.row_x[max(r - 1, 0)];
+        const float hy = S.y[gn], hz = S.z[gn];
+        const int64_t g_after = ev0 + h_after;
+        const int r_after = S.row[g_after];
+        const int32_t h_after2 = h[max(k - 2, 0)];
+        if (!transport(st, x_lo - x_hi, K.bd, C.smax, K.kkd, K.m2d)) return false;
+        x_hi = x_lo;
+        if (r != rn) continue;
+        chi2 = chi2 + update_yz(K, st, hy, hz);
+        ++n;
+        cur_row = r;
+        --k;
+        gn = g_after;
+        rn = k >= 0 ? r_after : -1;
+        h_after = h_after2;
+      }
     }
   }
   out = st;
