@@ -201,19 +201,37 @@ __global__ void __launch_bounds__(64) k_mg_outer(Slot S, DevConst K, MergeSlot M
     st.q = t.par[4];
     prior_d(K, st, st.z);
     bool ok = true;
+    // outward over rows row_in+1 .. row_out, updating with hits h[1..]
+    // (one per row, rows ascending).  Every read of a step is issued at its
+    // top and used after the transport: the next row's radius (the current
+    // one carried in a register), the next hit's coordinates, the row of the
+    // hit after it and the list entry after that (indices clamped to the
+    // last hit).
+    const int nlast = t.n_hits - 1;
     int k = 1;
+    int64_t gn = ev0 + h[min(k, nlast)];
+    int rn = k <= nlast ? (int)S.row[gn] : -1;
+    int32_t h_after = h[min(k + 1, nlast)];
+    double x_lo = xrow(K, t.row_in);
+    float x_next = K.row_x[min(t.row_in + 1, kRows - 1)];
     for (int r = t.row_in + 1; r <= t.row_out; ++r) {
-      if (!transport(st, xrow(K, r) - xrow(K, r - 1), K.bd, C.smax, K.kkd, K.m2d)) {
+      const double x_hi = (double)x_next;
+      x_next = K.row_x[min(r + 1, kRows - 1)];
+      const float hy = S.y[gn], hz = S.z[gn];
+      const int64_t g_after = ev0 + h_after;
+      const int r_after = S.row[g_after];
+      const int32_t h_after2 = h[min(k + 2, nlast)];
+      if (!transport(st, x_hi - x_lo, K.bd, C.smax, K.kkd, K.m2d)) {
         ok = false;
         break;
       }
-      if (k < t.n_hits) {
-        const int64_t gid = ev0 + h[k];
-        if ((int)S.row[gid] == r) {
-          update_hit(S, K, st, gid);
-          ++k;
-        }
-      }
+      x_lo = x_hi;
+      if (r != rn) continue;
+      update_yz(K, st, hy, hz);
+      ++k;
+      gn = g_after;
+      rn = k <= nlast ? r_after : -1;
+      h_after = h_after2;
     }
     M.ok[a] = ok ? 1 : 0;
     double* op = M.op + (size_t)a * 5;
