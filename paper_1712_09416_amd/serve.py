@@ -109,7 +109,10 @@ class _Worker:
         else:
             self.trk.track_event(0)
         if calib:
-            calib.on_tracked(self.trk, self.tag)
+            # on the tracker's stream: the histogram's zeroing is already
+            # ordered by on_submit, and nothing else needs torch's stream
+            with torch.cuda.stream(self.trk.stream):
+                calib.on_tracked(self.trk, self.tag)
         self.batch = list(ids)
 
     def close(self):
