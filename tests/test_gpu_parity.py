@@ -297,6 +297,67 @@ def test_edge_cases(dev):
     trk.close()
 
 
+def edge_rows_event(seed=20261203):
+    """Straight tracks placed at the row range's ends, plus seeded uniform
+    noise in their sectors: one ending at the last pad row, one starting at
+    pad row 0, one of exactly ten hits, one of runs of five hits with an
+    empty row between (steps without a hit in every fit), and a nine-hit one
+    on the C side that is too short to become a track."""
+    from tpcgen.events import Event
+    rng = np.random.default_rng(seed)
+    x = tpcgen.geometry.row_x()
+    S, R, Y, Z = [], [], [], []
+
+    def line(sec, rows, a, b):
+        rows = np.asarray(rows)
+        S.append(np.full(len(rows), sec))
+        R.append(rows)
+        Y.append(a * x[rows])
+        Z.append(b * x[rows])
+
+    line(4, np.arange(145, 159), 0.02, 0.3)
+    line(5, np.arange(0, 15), -0.03, 0.2)
+    line(6, np.arange(60, 70), 0.01, 0.5)
+    line(7, [r for r in range(20, 110) if (r - 20) % 6 != 5], 0.04, 0.4)
+    line(24, np.arange(150, 159), -0.01, -0.6)
+    for sec in (4, 5, 6, 7, 24):
+        rr = rng.integers(0, 159, 300)
+        S.append(np.full(300, sec))
+        R.append(rr)
+        Y.append(rng.uniform(-0.15, 0.15, 300) * x[rr])
+        Z.append(rng.uniform(0, 250, 300) * (-1.0 if sec >= 18 else 1.0))
+    p = rng.permutation(sum(len(a) for a in S))
+    s, r, y, z = (np.concatenate(a)[p] for a in (S, R, Y, Z))
+    n = len(s)
+    return Event("edge_rows", seed, s.astype(np.uint8), r.astype(np.uint8), y.astype(np.float32),
+                 z.astype(np.float32), np.ones(n, np.float32), np.full(n, -1, np.int32),
+                 np.full(n, -1, np.int32), np.full((n, 5), np.nan), (0.1, 0.0, 0.15, 0.0))
+
+
+def test_tracks_at_row_range_ends(dev, oracle_lib):
+    """Tracklets that run to the last pad row or down to row 0, a track of
+    the minimum length and fits with empty rows between hits: links, hit
+    lists and parameters identical to the oracle's, in the fused and the
+    per-sector launch sequences."""
+    ev = edge_rows_event()
+    say(f"edge-rows event: {ev.n} clusters")
+    ref = oracle_lib.run_event(ev, precision=32, replay=True)
+    rows = sorted(zip(ref.tracks["n_hits"].tolist(), ref.tracks["row_in"].tolist(),
+                      ref.tracks["row_out"].tolist()))
+    assert rows == [(10, 60, 69), (14, 145, 158), (15, 0, 14), (75, 20, 108)], rows
+    from paper_1712_09416_amd import Tracker
+    for mode in ("event", "sectors"):
+        trk = Tracker(ev.geometry(), max_clusters=4096)
+        tracks, hits, lk = gpu_run(ev, dev, mode=mode, tracker=trk)
+        compare_links(lk, ref)
+        compare_tracks(tracks, hits, ref)
+        compare_replay(tracks, ref.replay)
+        # the merger's outward walk over these tracks (empty rows included)
+        trk.merge(0)
+        merge_case(trk, 0, 0, ev, oracle_lib)
+        trk.close()
+
+
 def test_repeat_runs_identical(dev):
     ev = tpcgen.pbpb_event(tpcgen.seed_for(2) + 77, 2000)
     a = gpu_run(ev, dev, links=False)
