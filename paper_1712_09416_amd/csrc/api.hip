@@ -382,7 +382,9 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
   scan_u32(st, s.tl_sel, s.range_cnt + 0, tl_bound, s.scan_b, s.range_cnt + 1, false);
   k_track_write<<<nb_sel, 256, 0, st>>>(s, g0);
   if (marks) mark(ctx, 5);
-  k_refit<<<grid_stride_blocks(std::max<int64_t>(1, tl_bound / 4), 64, 4096), 64, 0, st>>>(s, ctx->k, g0);
+  // four waves per block: a block's waves go to the four SIMDs of one CU,
+  // so the few hundred working waves of an event do not share SIMDs
+  k_refit<<<grid_stride_blocks(std::max<int64_t>(1, tl_bound / 4), 256, 1024), 256, 0, st>>>(s, ctx->k, g0);
   if (marks) mark(ctx, 6);
   TPC_LAUNCHED();
   return TPC_OK;

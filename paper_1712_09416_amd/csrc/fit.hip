@@ -203,7 +203,7 @@ __device__ __forceinline__ void refit_pass(const Slot& S, const DevConst& K, con
 // same way, so the Jacobians are evaluated along the fitted track.  Output
 // at the innermost fitted hit; its cluster is marked for the canonical
 // ordering.
-__global__ void __launch_bounds__(64) k_refit(Slot S, DevConst K, int g0) {
+__global__ void __launch_bounds__(256) k_refit(Slot S, DevConst K, int g0) {
   const uint32_t total = S.range_cnt[1];
   const uint32_t tk0 = S.tk_base[g0];
   const uint32_t stride = gridDim.x * blockDim.x;
