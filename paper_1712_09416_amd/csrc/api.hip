@@ -710,7 +710,9 @@ int tpc_merge(tpc_ctx* ctx, int slot, const tpc_merge_params* mp) {
   hipStream_t st = ctx->stream;
   const int64_t K = s.cap_tk;
   const int64_t ns = s.n_sectors;
-  const int nbt = grid_stride_blocks(K, 64, 8192);
+  // lane-per-track kernels in four-wave blocks: a block's waves go to the
+  // four SIMDs of one CU, so the working waves do not share SIMDs
+  const int nbt = grid_stride_blocks(K, 256, 2048);
   const int nb = grid_stride_blocks(K, 256);
   const int64_t nsr = ns * kRows;
   for (uint32_t* p : {m.in_off, m.out_off}) k_zero_u32<<<grid_stride_blocks(nsr + 1, 256), 256, 0, st>>>(p, nsr + 1);
@@ -724,17 +726,17 @@ int tpc_merge(tpc_ctx* ctx, int slot, const tpc_merge_params* mp) {
   scan_u32(st, m.in_off, nullptr, nsr, s.scan_b, nullptr);
   scan_u32(st, m.out_off, nullptr, nsr, s.scan_b, nullptr);
   k_mg_scatter<<<nb, 256, 0, st>>>(s, m);
-  k_mg_outer<<<nbt, 64, 0, st>>>(s, ctx->k, m, C);
-  k_mg_best_out<<<nbt, 64, 0, st>>>(s, ctx->k, m, C);
-  k_mg_best_in<<<nbt, 64, 0, st>>>(s, ctx->k, m, C);
+  k_mg_outer<<<nbt, 256, 0, st>>>(s, ctx->k, m, C);
+  k_mg_best_out<<<nbt, 256, 0, st>>>(s, ctx->k, m, C);
+  k_mg_best_in<<<nbt, 256, 0, st>>>(s, ctx->k, m, C);
   k_mg_in_final<<<nb, 256, 0, st>>>(s, m);
   k_mg_link<<<nb, 256, 0, st>>>(s, m);
-  k_mg_chain<<<nbt, 64, 0, st>>>(s, ctx->k, m, C);
+  k_mg_chain<<<nbt, 256, 0, st>>>(s, ctx->k, m, C);
   k_mg_emit<<<nb, 256, 0, st>>>(s, m);
   scan_u32(st, m.emit, s.out_count, K, s.scan_b, nullptr);
   scan_u32(st, m.nh, s.out_count, K, s.scan_b, nullptr);
   k_mg_event_off<<<(h.n_events + 1 + 255) / 256, 256, 0, st>>>(s, m);
-  k_mg_write<<<nbt, 64, 0, st>>>(s, ctx->k, m);
+  k_mg_write<<<nbt, 256, 0, st>>>(s, ctx->k, m);
   TPC_LAUNCHED();
   h.merged = true;
   return record_done(ctx, h);

@@ -186,7 +186,7 @@ __device__ __forceinline__ const int32_t* track_hits(const Slot& S, const tpc_tr
 }
 
 // M1
-__global__ void __launch_bounds__(64) k_mg_outer(Slot S, DevConst K, MergeSlot M, MergeConst C) {
+__global__ void __launch_bounds__(256) k_mg_outer(Slot S, DevConst K, MergeSlot M, MergeConst C) {
   const uint32_t ntk = S.out_count[0];
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
@@ -324,7 +324,7 @@ __device__ __forceinline__ void for_neighbours(const uint32_t* off, const int32_
 // evaluated here once: its chi2 also lowers B's smallest chi2 (the bit
 // pattern of a non-negative double orders like its value), and the first
 // kMgPairs pairs of A are kept for the pass that picks B's best A.
-__global__ void __launch_bounds__(64) k_mg_best_out(Slot S, DevConst K, MergeSlot M,
+__global__ void __launch_bounds__(256) k_mg_best_out(Slot S, DevConst K, MergeSlot M,
                                                     MergeConst C) {
   const uint32_t ntk = S.out_count[0];
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -360,7 +360,7 @@ __global__ void __launch_bounds__(64) k_mg_best_out(Slot S, DevConst K, MergeSlo
 // M2 + M3: best inner partner of each B: among the A whose pair reaches B's
 // smallest chi2, the smaller track position (lane per A, over the pairs the
 // previous pass kept; an A with more than kMgPairs pairs evaluates them again).
-__global__ void __launch_bounds__(64) k_mg_best_in(Slot S, DevConst K, MergeSlot M,
+__global__ void __launch_bounds__(256) k_mg_best_in(Slot S, DevConst K, MergeSlot M,
                                                    MergeConst C) {
   const uint32_t ntk = S.out_count[0];
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -513,7 +513,7 @@ __device__ bool carry_out(const Slot& S, const DevConst& K, const MergeConst& C,
 }
 
 // M4: refit of each chain (lane per chain head)
-__global__ void __launch_bounds__(64) k_mg_chain(Slot S, DevConst K, MergeSlot M, MergeConst C) {
+__global__ void __launch_bounds__(256) k_mg_chain(Slot S, DevConst K, MergeSlot M, MergeConst C) {
   const uint32_t ntk = S.out_count[0];
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
@@ -599,7 +599,7 @@ __device__ __forceinline__ void copy_hits(int32_t* dst, const int32_t* src, int 
   }
 }
 
-__global__ void __launch_bounds__(64) k_mg_write(Slot S, DevConst K, MergeSlot M) {
+__global__ void __launch_bounds__(256) k_mg_write(Slot S, DevConst K, MergeSlot M) {
   const uint32_t ntk = S.out_count[0];
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
