@@ -182,3 +182,15 @@ def test_every_package_module_imports():
             if info.name.startswith("lib"):          # the built shared library itself
                 continue
             importlib.import_module(f"{mod.__name__}.{info.name}")
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it says so and exits
+    non-zero before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in r.stdout + r.stderr
