@@ -816,7 +816,7 @@ int tpc_calib_accumulate(tpc_ctx* ctx, int slot, uint32_t* hist, int n_bins, flo
   }
   if (h.state != 4) return ctx->fail(TPC_ESTATE, "slot not tracked");
   const double w = ((double)z_hi - (double)z_lo) / (double)n_bins;
-  k_cal_accumulate<<<grid_stride_blocks(h.d.cap_tk, 64, 4096), 64, 0, ctx->stream>>>(
+  k_cal_accumulate<<<grid_stride_blocks(h.d.cap_tk, 256, 1024), 256, 0, ctx->stream>>>(
       h.d, ctx->k, hist, n_bins, (double)z_lo, w);
   TPC_LAUNCHED();
   return record_done(ctx, h);

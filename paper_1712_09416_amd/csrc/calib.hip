@@ -27,7 +27,7 @@ constexpr double kCalY0 = 2.0;
 constexpr double kCalStep = 2.0;
 constexpr double kCalSmax = 0.999;
 
-__global__ void __launch_bounds__(64) k_cal_accumulate(Slot S, DevConst K, uint32_t* hist,
+__global__ void __launch_bounds__(256) k_cal_accumulate(Slot S, DevConst K, uint32_t* hist,
                                                        int n_bins, double z_lo, double w) {
   const uint32_t ntk = S.out_count[0];
   const uint32_t stride = gridDim.x * blockDim.x;
