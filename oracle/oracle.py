@@ -102,6 +102,7 @@ def lib():
         L.orc_update_f.argtypes = [P, P, f32, f32, f32, f32, f32, f32, ctypes.c_int, P]
         L.orc_predict_ms_d.argtypes = [P, P, f64, f64, f64, f64, f64]
         L.orc_update_d.argtypes = [P, P, f64, f64, f64, f64, f64, f64, ctypes.c_int, P]
+        L.orc_kf_steps_f.argtypes = [P, P, P, P, P, ctypes.c_int64, f32, f32, f32]
         L.orc_merge.restype = P
         L.orc_merge.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(Params),
                                 ctypes.POINTER(MergeParams), P, ctypes.c_int64, P, P, P, P]
@@ -242,6 +243,20 @@ def update(p, C, my, mz, vy, vz, chi2max=16.0, smax=0.95, gated=True, precision=
     return bool(ok), p, C, float(chi2[0])
 
 
+def kf_steps_f32(state, dx, meas, b, smax=0.95, chi2max=16.0):
+    """Float transport + gated update of n states (state[n, 20] = p, C;
+    meas[n, 4] = y, z, var_y, var_z).  Returns (state', bits, chi2); bits =
+    transport ok | accepted << 1, chi2 as computed by the update."""
+    st = np.ascontiguousarray(state, np.float32).copy()
+    dx = np.ascontiguousarray(dx, np.float32)
+    meas = np.ascontiguousarray(meas, np.float32)
+    n = len(st)
+    bits = np.zeros(n, np.int32)
+    chi2 = np.zeros(n, np.float32)
+    lib().orc_kf_steps_f(_ptr(st), _ptr(dx), _ptr(meas), _ptr(bits), _ptr(chi2), n, b, smax, chi2max)
+    return st, bits, chi2
+
+
 def curvature_b(bz_tesla: float) -> float:
     """b = -c Bz in cm^-1 per (c/GeV); d(phi)/dl = b * q/pT."""
     return -0.00299792458 * float(bz_tesla)
@@ -351,8 +366,12 @@ def calib_histogram(tracks, geo: dict, n_bins=None, z_lo=None, z_hi=None):
     return h
 
 
-def calib_fit(hist, z_max: float, z_lo=None, z_hi=None):
-    """(median z0 of side A, of side C, eps); NaN where a side is empty."""
+def calib_fit(hist, z_max: float, z_lo=None, z_hi=None, eps_tracked: float = 0.0):
+    """(median z0 of side A, of side C, eps_r, E); NaN where a side is empty.
+    eps_r is the drift error measured on the histogram's events; they were
+    tracked after a correction with eps_tracked, which leaves the error
+    eps_r = (E - eps_tracked) / (1 + eps_tracked) of a true error E, so the
+    estimate to adopt is E = eps_tracked + eps_r (1 + eps_tracked)."""
     n_bins = hist.shape[1]
     z_lo = CALIB["z_lo"] if z_lo is None else z_lo
     z_hi = CALIB["z_hi"] if z_hi is None else z_hi
@@ -370,7 +389,8 @@ def calib_fit(hist, z_max: float, z_lo=None, z_hi=None):
         b = int(np.nonzero(cum[1:] >= half)[0][0])
         med.append(lo + (b + (half - float(cum[b])) / float(c[b])) * w)
     zm = float(np.float32(z_max))
-    return med[0], med[1], (med[1] - med[0]) / (2.0 * zm)
+    eps_r = (med[1] - med[0]) / (2.0 * zm)
+    return med[0], med[1], eps_r, eps_tracked + eps_r * (1.0 + eps_tracked)
 
 
 def drift_correct(sector, z, eps: float, z_max: float):

@@ -403,14 +403,15 @@ void refit_pass(const Ctx<R>& c, const float* Y, const float* Z, const int32_t* 
   }
 }
 
-// ---- O7: refit over the owned hits, inward, twice ---------------------------
+// ---- O7: refit over the owned hits, inward, in `passes` passes (3) ---------
 // Pass 1 seeds (s, T, Q) from the tracklet's inner state, with s carried to
 // the outermost owned row along the circle (sin phi is linear in x) and the
 // covariance reset; every owned hit updates the state (no gate); a failed
-// transport ends the pass early.  Pass 2 repeats the same inward fit seeded
-// from pass 1's result carried back to the outermost row the same way, so the
-// transport Jacobians are evaluated along the fitted track rather than along
-// the seed.  Output: pass 2's state at the innermost fitted hit.
+// transport ends the pass early.  Each later pass repeats the same inward
+// fit seeded from the previous pass's result carried back to the outermost
+// row the same way, so the transport Jacobians are evaluated along the
+// fitted track rather than along the seed.  Output: the last pass's state at
+// the innermost fitted hit.
 // The refit takes no decision that changes which hits are tried, so it runs
 // in double whatever the precision of the tracklet phases (a float covariance
 // update loses too much precision when the wide prior collapses over a long
@@ -1512,6 +1513,30 @@ int orc_update_f(float* p, float* C, float my, float mz, float vy, float vz, flo
   std::memcpy(p, st.p, 20);
   std::memcpy(C, st.C, 60);
   return ok ? 1 : 0;
+}
+
+// n independent float steps, each a transport by dx[i] then a gated update
+// with meas[i] = (y, z, var_y, var_z): state[i] = (p[5], C[15]) in/out,
+// result[i] = (bits: transport ok | update accepted << 1, chi2 of the update
+// or 0).  The same primitives as orc_predict_f / orc_update_f, looped here.
+void orc_kf_steps_f(float* state, const float* dx, const float* meas, int32_t* bits,
+                    float* chi2, int64_t n, float b, float smax, float chi2max) {
+  for (int64_t i = 0; i < n; ++i) {
+    State<float> st;
+    std::memcpy(st.p, state + 20 * i, 20);
+    std::memcpy(st.C, state + 20 * i + 5, 60);
+    int32_t r = 0;
+    float ch = 0.0f;
+    if (predict(st, dx[i], b, smax)) {
+      r = 1;
+      const float* m = meas + 4 * i;
+      if (update(st, m[0], m[1], m[2], m[3], chi2max, smax, true, &ch)) r |= 2;
+    }
+    std::memcpy(state + 20 * i, st.p, 20);
+    std::memcpy(state + 20 * i + 5, st.C, 60);
+    bits[i] = r;
+    chi2[i] = ch;
+  }
 }
 
 int orc_update_d(double* p, double* C, double my, double mz, double vy, double vz,

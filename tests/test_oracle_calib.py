@@ -40,8 +40,9 @@ def test_fit_recovers_the_drift_error(oracle_lib, eps):
     r = oracle_lib.run_event(ev, precision=32, nthreads=8)
     h = oracle_lib.calib_histogram(r.tracks, ev.geometry())
     assert h.sum() > 2000
-    med_a, med_c, e = oracle_lib.calib_fit(h, 250.0)
+    med_a, med_c, e, est = oracle_lib.calib_fit(h, 250.0)
     assert abs(e - eps) < 1e-4, (e, eps)
+    assert est == e                 # tracked without correction: the estimate is the measurement
     assert abs(med_a + eps * 250.0) < 0.05 and abs(med_c - eps * 250.0) < 0.05
 
 
@@ -65,7 +66,7 @@ def test_median_is_the_sample_median(oracle_lib):
     sel &= (z0 >= c["z_lo"]) & (z0 < c["z_hi"])
     h = oracle_lib.calib_histogram(r.tracks, geo)
     assert h.sum() == sel.sum()
-    med_a, med_c, _ = oracle_lib.calib_fit(h, 250.0)
+    med_a, med_c, _, _ = oracle_lib.calib_fit(h, 250.0)
     w = (c["z_hi"] - c["z_lo"]) / c["n_bins"]
     side = r.tracks["sector"] // 18
     assert abs(med_a - np.median(z0[sel & (side == 0)])) <= w
@@ -75,5 +76,23 @@ def test_median_is_the_sample_median(oracle_lib):
 def test_empty_side_gives_nan(oracle_lib):
     h = np.zeros((2, 4000), np.uint32)
     h[0, 2000] = 3
-    a, c, e = oracle_lib.calib_fit(h, 250.0)
-    assert a == pytest.approx(0.005, abs=1e-12) and np.isnan(c) and np.isnan(e)
+    a, c, e, est = oracle_lib.calib_fit(h, 250.0, eps_tracked=0.001)
+    assert a == pytest.approx(0.005, abs=1e-12) and np.isnan(c) and np.isnan(e) and np.isnan(est)
+
+
+@pytest.mark.parametrize("eps_true,eps_used", [(0.004, 0.0015), (-0.002, 0.001)])
+def test_estimate_composes_a_residual_after_correction(oracle_lib, eps_true, eps_used):
+    """Events with a drift error eps_true, corrected with a wrong eps_used
+    before tracking, leave the residual (eps_true - eps_used) / (1 + eps_used)
+    (closed form of correcting z (1 + E) - side E z_max with eps_used); the
+    fit measures that residual and its composed estimate gives back eps_true
+    to the statistical error of the medians."""
+    ev0 = tpcgen.pbpb_event(tpcgen.seed_for(4, 100), 2000)
+    d = tpcgen.distort_drift(ev0, eps_true)
+    import dataclasses
+    ev = dataclasses.replace(d, z=oracle_lib.drift_correct(d.sector, d.z, eps_used, 250.0))
+    r = oracle_lib.run_event(ev, precision=32, nthreads=8)
+    h = oracle_lib.calib_histogram(r.tracks, ev.geometry())
+    _, _, e_r, est = oracle_lib.calib_fit(h, 250.0, eps_tracked=eps_used)
+    assert abs(e_r - (eps_true - eps_used) / (1.0 + eps_used)) < 1e-4, e_r
+    assert abs(est - eps_true) < 1e-4, est
