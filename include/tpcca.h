@@ -115,22 +115,30 @@ typedef struct tpc_track {
 typedef struct tpc_ctx tpc_ctx;
 
 /* Fill *p with the default constants; max_slots = 1, max_events = 1,
- * max_clusters = 4M.  Returns TPC_EINVAL if p is NULL. */
+ * max_clusters = 4M.  The paper names the method only (Abstract: a cellular
+ * automaton and the Kalman filter); the constants are this implementation's
+ * definition of its cuts.  Returns TPC_EINVAL if p is NULL. */
 int tpc_params_default(tpc_params* p);
 
-/* Device bytes a context with these capacities needs (0 if p is invalid). */
+/* Device bytes a context with these capacities needs (0 if p is invalid).
+ * The track regions are sized for n_min_track: each sector of n clusters
+ * has room for n / n_min_track + 1 tracks, the most its hits allow. */
 size_t tpc_workspace_bytes(const tpc_params* p);
 
-/* Create a context.  g, p: copied.  dev_workspace: device memory of
- * ws_bytes >= tpc_workspace_bytes(p), owned by the caller and used by the
- * context until tpc_destroy.  hip_stream: a hipStream_t (NULL = default
+/* Create a context: the tracker of the TPC, the detector the paper tracks
+ * with (Section 2: TPC track reconstruction subscribes to the data of all
+ * TPC links; each sector is one link's part of the event).  g, p: copied.
+ * dev_workspace: device memory of ws_bytes >= tpc_workspace_bytes(p), owned
+ * by the caller and used by the context until tpc_destroy.  hip_stream: a hipStream_t (NULL = default
  * stream).  Errors: TPC_EINVAL (geometry not 36 x 159 increasing rows,
  * bad params), TPC_ENOMEM (workspace too small). */
 int tpc_init_geometry(tpc_ctx** out, const tpc_geometry* g, const tpc_params* p,
                       void* dev_workspace, size_t ws_bytes, void* hip_stream);
 
-/* Stage one event into a slot: n clusters as structure-of-arrays,
- * sector[i] < 36, row[i] < 159, finite y[i], z[i] (local sector frame, cm),
+/* Stage one event into a slot (the input of TPC track reconstruction, the
+ * clusters of the TPC cluster finder, Section 2): n clusters as
+ * structure-of-arrays, sector[i] < 36, row[i] < 159, finite y[i], z[i]
+ * (local sector frame, cm),
  * q[i] charge (carried, unused; may be NULL).  flags: TPC_DEVICE (arrays in
  * device memory, used in place: the caller keeps them alive and unchanged
  * until the slot's tracks are read) or TPC_HOST (copied asynchronously into
@@ -141,27 +149,57 @@ int tpc_init_geometry(tpc_ctx** out, const tpc_geometry* g, const tpc_params* p,
 int tpc_load_clusters(tpc_ctx* ctx, int slot, const uint8_t* sector, const uint8_t* row,
                       const float* y, const float* z, const float* q, int64_t n, int flags);
 
-/* Stage a batch of n_events events into one slot.  event_offsets (host,
+/* Stage a batch of n_events events into one slot (Section 2: many events
+ * are in the chain at once).  event_offsets (host,
  * n_events + 1 entries, non-decreasing, event_offsets[0] = 0) delimit the
  * events inside the concatenated arrays.  Otherwise as tpc_load_clusters. */
 int tpc_load_batch(tpc_ctx* ctx, int slot, int n_events, const int64_t* event_offsets,
                    const uint8_t* sector, const uint8_t* row, const float* y, const float* z,
                    const float* q, int flags);
 
-/* Track one sector of a staged slot (sector < 36 * events in the slot):
- * the grid is built on the slot's first tracking call, then the neighbours
- * finder, cleaner, tracklets, selection and refit run for this sector only,
- * each as its own launch.  Errors: TPC_EINVAL, TPC_ESTATE (slot not loaded,
- * or already finalised). */
+/* Track one sector of a staged slot (sector < 36 * events in the slot;
+ * Abstract and Section 2: cellular-automaton track finding and Kalman-filter
+ * fitting, sector by sector): the grid is built on the slot's first
+ * tracking call, and the slot's per-sector cluster counts are then read
+ * back once (the call waits for the grid), so each later launch is sized by
+ * its own sector; the neighbours finder, cleaner, tracklets, selection and
+ * refit run for this sector only, each as its own launch.  Errors:
+ * TPC_EINVAL, TPC_ESTATE (slot not loaded, or already finalised),
+ * TPC_EDEVICE. */
 int tpc_track_sector(tpc_ctx* ctx, int slot, int sector);
 
-/* Track every sector of every event in the slot: each step is one launch
- * over all sectors of the slot, then the tracks are put in canonical order
- * (event, innermost cluster ID).  Asynchronous; results are read with
+/* Track every sector of every event in the slot (Abstract and Section 2:
+ * the GPU tracker, cellular automaton then Kalman filter): each step is one
+ * launch over all sectors of the slot, then the tracks are put in canonical
+ * order (event, innermost cluster ID).  Asynchronous; results are read with
  * tpc_get_tracks.  Errors: TPC_EINVAL, TPC_ESTATE. */
 int tpc_track_event(tpc_ctx* ctx, int slot);
 
-/* Track every sector of the slot with the per-sector launch sequence of
+/* Track n staged slots (each a single event or a batch of events), each by
+ * one replay of its HIP graph (Section 2: many events flow through the chain
+ * at once; Section 4.2: several kernels in flight).  A slot without a graph
+ * for its current staging (same input pointers and event offsets) is
+ * captured first, once, as by tpc_graph_capture; later calls with the same
+ * staging only replay.  slots: host array of n distinct slot indices.
+ * Asynchronous; every slot is tracked as after tpc_track_event.  Requires a
+ * non-default stream.  Arguments are checked for all slots before anything
+ * is enqueued.  Errors: TPC_EINVAL (bad list, a slot twice, default
+ * stream), TPC_ESTATE (a slot not staged, or during capture), TPC_EDEVICE. */
+int tpc_track_events(tpc_ctx* ctx, const int* slots, int n);
+
+/* Serving entry (Section 2: events are pipelined through the chain; Section
+ * 5.1: the loop must not stall): enqueue the tracking of a staged slot and
+ * return at once.  The slot's HIP graph is replayed if it was captured for
+ * the current staging, otherwise the one-launch-per-step sequence of
+ * tpc_track_event runs.  Completion is tested with tpc_poll (never waits);
+ * results are then read with tpc_get_tracks or tpc_device_results.
+ * Errors: TPC_EINVAL, TPC_ESTATE (slot not staged, already tracked without
+ * a matching graph, or during capture), TPC_EDEVICE. */
+int tpc_submit(tpc_ctx* ctx, int slot);
+
+/* Concurrent kernels (Section 4.2: several kernels in parallel give +15%,
+ * more than +30% expected).  Track every sector of the slot with the
+ * per-sector launch sequence of
  * tpc_track_sector, sector g on the library's own stream g mod n_streams
  * (1 <= n_streams <= 8; streams at default priority, created on first use),
  * after the grid is built on the context stream; the context stream waits
@@ -174,7 +212,8 @@ int tpc_track_event(tpc_ctx* ctx, int slot);
  * during graph capture), TPC_EDEVICE. */
 int tpc_track_event_streams(tpc_ctx* ctx, int slot, int n_streams);
 
-/* Wait for the slot and copy the tracks of one event of it (event = 0 for
+/* Output of the tracker (Abstract: tracks of the TPC, fitted by the Kalman
+ * filter).  Wait for the slot and copy the tracks of one event of it (event = 0 for
  * tpc_load_clusters) into caller host memory: out[max_tracks],
  * hit_ids[max_hits] (cluster IDs, each track's hits ascending by row).
  * *n_tracks, *n_hits receive the event's counts.  If sectors were tracked
@@ -184,7 +223,8 @@ int tpc_track_event_streams(tpc_ctx* ctx, int slot, int n_streams);
 int tpc_get_tracks(tpc_ctx* ctx, int slot, int event, tpc_track* out, int64_t max_tracks,
                    int32_t* hit_ids, int64_t max_hits, int64_t* n_tracks, int64_t* n_hits);
 
-/* Device-resident results of a tracked slot, without copies or
+/* Output of the tracker, as in tpc_get_tracks.  Device-resident results of
+ * a tracked slot, without copies or
  * synchronisation: tracks of all events of the slot in canonical order,
  * hit IDs, per-event offsets (device arrays of n_events + 1 entries, into
  * the track array and the hit array) and the slot's [track, hit] totals
@@ -193,15 +233,17 @@ int tpc_device_results(tpc_ctx* ctx, int slot, const tpc_track** tracks, const i
                        const uint32_t** event_track_off, const uint32_t** event_hit_off,
                        const uint32_t** totals);
 
-/* Diagnostics of the finding steps for one event of a tracked slot, copied
+/* Cellular-automaton diagnostics (Abstract: track finding by a cellular
+ * automaton).  The finding steps' links for one event of a tracked slot, copied
  * to host arrays of the event's cluster count: the neighbours finder's
  * up/down links and the cleaned links, as cluster IDs (-1 = none).  Any
  * pointer may be NULL.  Synchronises.  Errors: TPC_EINVAL, TPC_ESTATE. */
 int tpc_get_links(tpc_ctx* ctx, int slot, int event, int32_t* up, int32_t* dn, int32_t* up_clean,
                   int32_t* dn_clean);
 
-/* Apply one float transport + gated update to each of n states on the
- * device (the tracklet filter's primitives, for bit-level tests).  All
+/* Kalman-filter primitives (Abstract: Kalman-filter track fitting).  Apply
+ * one float transport + gated update to each of n states on the device (the
+ * tracklet filter's primitives, for bit-level tests).  All
  * arrays are device memory: state[n][20] = (y, z, s, T, Q, C[15]) in/out,
  * dx[n], meas[n][4] = (y, z, var_y, var_z), result[n][2] = (int bits:
  * transport ok | update accepted << 1, chi2 as float).  Uses the context's
@@ -222,7 +264,8 @@ typedef struct tpc_merge_params {
 int tpc_merge_params_default(tpc_merge_params* m);
 
 /* Join track segments across sector boundaries, for every event of a
- * tracked slot (the step after the per-sector tracking: a particle crossing
+ * tracked slot (Section 2: data of all links of an event are merged for the
+ * global reconstruction; the step after the per-sector tracking: a particle crossing
  * from one sector into its neighbour on the same side leaves one segment in
  * each).  Per track, the state at its outermost hit (an outward Kalman pass
  * seeded with its fitted parameters); each pair (A, B), B in a neighbouring
@@ -276,23 +319,31 @@ int tpc_get_merge_links(tpc_ctx* ctx, int slot, int event, int32_t* link_out, in
  * elsewhere must be ordered before the call by the caller.  Errors:
  * TPC_EINVAL, TPC_ESTATE (slot not tracked).
  *
- * tpc_calib_fit: on the given stream (device hist and out), each side's
- * median of z0 (linear inside the median bin; NaN if the side is empty)
- * and eps = (median_C - median_A) / (2 z_max): out[3] = {median_A,
- * median_C, eps}.  One small kernel; meant to run beside the tracking on a
- * stream of its own.  Errors: TPC_EINVAL, TPC_EDEVICE.
+ * tpc_calib_fit (Section 3, item 4: a fit every n-th event, and Section
+ * 5.1: run asynchronously): on the given stream (device hist and out), each
+ * side's median of z0 (linear inside the median bin; NaN if the side is
+ * empty), the drift error measured on the histogram's events
+ * eps_r = (median_C - median_A) / (2 z_max), and the estimate to adopt:
+ * the events were tracked after a correction with eps_tracked, which
+ * leaves exactly the error eps_r = (E - eps_tracked) / (1 + eps_tracked)
+ * of a true error E, so E = eps_tracked + eps_r (1 + eps_tracked):
+ * out[4] = {median_A, median_C, eps_r, E} (NaN where a side is empty).
+ * |eps_tracked| < 0.5.  One small kernel; meant to run beside the tracking
+ * on a stream of its own.  Errors: TPC_EINVAL, TPC_EDEVICE.
  *
- * tpc_calib_correct_z: z[i] <- (z[i] + side eps z_max) / (1 + eps) for n
+ * tpc_calib_correct_z (Section 5.3: the result is fed back into the cluster
+ * transformation): z[i] <- (z[i] + side eps z_max) / (1 + eps) for n
  * device clusters (side from sector[i]), in place; |eps| < 0.5.
  * Asynchronous on the context stream (same ordering rule as above).
  * Errors: TPC_EINVAL. */
 int tpc_calib_accumulate(tpc_ctx* ctx, int slot, uint32_t* hist, int n_bins, float z_lo,
                          float z_hi);
 int tpc_calib_fit(const uint32_t* hist, int n_bins, float z_lo, float z_hi, float z_max,
-                  double* out, void* hip_stream);
+                  double eps_tracked, double* out, void* hip_stream);
 int tpc_calib_correct_z(tpc_ctx* ctx, const uint8_t* sector, float* z, int64_t n, double eps);
 
-/* Record into a HIP graph, without running it, the whole sequence
+/* Batched launch (Section 2: events pipelined through the chain).  Record
+ * into a HIP graph, without running it, the whole sequence
  * tpc_track_event would enqueue for the slot as currently staged (grid,
  * finding, fitting, ordering; kernels only, no memset or copy nodes).  The
  * graph is kept by the context, one per slot, and bakes in the slot's
@@ -301,26 +352,34 @@ int tpc_calib_correct_z(tpc_ctx* ctx, const uint8_t* sector, float* z, int64_t n
  * staged), TPC_EDEVICE (capture failed). */
 int tpc_graph_capture(tpc_ctx* ctx, int slot);
 
-/* Launch the slot's graph on the context stream (asynchronous); the slot is
+/* Batched launch, as tpc_graph_capture.  Launch the slot's graph on the
+ * context stream (asynchronous); the slot is
  * then tracked as after tpc_track_event.  The slot must be staged with the
  * same shape as at capture (e.g. TPC_HOST copies of new clusters into the
  * slot's own buffers, or the same device arrays refilled in place).
  * Errors: TPC_EINVAL, TPC_ESTATE (no graph, or the staged shape changed). */
 int tpc_graph_launch(tpc_ctx* ctx, int slot);
 
-/* TPC_OK if all work enqueued so far for the slot (staging, tracking) has
- * finished, TPC_EBUSY if not; never waits.  Errors: TPC_EINVAL. */
+/* Serving completion test (Section 5.1: check at every event whether the
+ * task has finished, never block).  TPC_OK if all work enqueued so far for
+ * the slot (staging, tracking) has finished, TPC_EBUSY if not; never waits.
+ * Errors: TPC_EINVAL. */
 int tpc_poll(tpc_ctx* ctx, int slot);
 
-/* Stage timing.  With profiling on, tpc_track_event records HIP events on
- * the context stream around its steps; tpc_get_profile waits for the stream
+/* Measurement (the paper reports tracking time per event, Section 4.2,
+ * Table 1).  With profiling on, tpc_track_event records HIP events on the
+ * context stream around its steps; tpc_get_profile waits for the stream
  * and returns, for the last tracked slot, the milliseconds of each step
  * (ms[TPC_N_STAGES]: grid, neighbours, clean+starts, tracklets,
  * weights+selection, refit, output) and the slot's work counters
- * (counters[8]: tracklets, tracklet row visits, hits inside the
- * tracklet search windows, tracks, clusters, sorted hits, 0, 0).  Either pointer may be
- * NULL.  Errors: TPC_EINVAL, TPC_ESTATE (nothing profiled yet), TPC_EDEVICE. */
+ * (counters[TPC_N_COUNTERS]: 0 tracklets, 1 tracklet row visits, 2 hits
+ * inside the tracklet search windows, 3 tracks refitted, 4 clusters,
+ * 5 sorted hits, 6 tracklet hits (final hit lists, all tracklets),
+ * 7 gated Kalman updates tried by the tracklets, 8 output tracks,
+ * 9 hits of the output tracks).  Either pointer may be NULL.  Errors:
+ * TPC_EINVAL, TPC_ESTATE (nothing profiled yet), TPC_EDEVICE. */
 #define TPC_N_STAGES 7
+#define TPC_N_COUNTERS 10
 int tpc_set_profiling(tpc_ctx* ctx, int enable);
 int tpc_get_profile(tpc_ctx* ctx, double* ms, uint64_t* counters);
 

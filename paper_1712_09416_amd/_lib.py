@@ -16,14 +16,16 @@ ERROR_NAMES = {0: "TPC_OK", -1: "TPC_EINVAL", -2: "TPC_ENOMEM", -3: "TPC_EOVERFL
                -4: "TPC_EDEVICE", -5: "TPC_ESTATE", -6: "TPC_EBUSY"}
 
 EXPORTS = ("tpc_params_default", "tpc_workspace_bytes", "tpc_init_geometry", "tpc_load_clusters",
-           "tpc_load_batch", "tpc_track_sector", "tpc_track_event", "tpc_track_event_streams",
-           "tpc_get_tracks",
+           "tpc_load_batch", "tpc_track_sector", "tpc_track_event", "tpc_track_events",
+           "tpc_submit", "tpc_track_event_streams", "tpc_get_tracks",
            "tpc_device_results", "tpc_get_links", "tpc_kf_step_f32", "tpc_graph_capture",
            "tpc_graph_launch", "tpc_poll", "tpc_set_profiling", "tpc_get_profile",
            "tpc_merge_params_default", "tpc_merge", "tpc_get_merged", "tpc_get_merge_links",
            "tpc_calib_accumulate", "tpc_calib_fit", "tpc_calib_correct_z",
            "tpc_last_error", "tpc_destroy")
 STAGES = ("grid", "neighbours", "clean_starts", "tracklets", "weights_select", "refit", "output")
+COUNTERS = ("tracklets", "row_visits", "window_hits", "tracks_refitted", "clusters", "sorted_hits",
+            "tracklet_hits", "update_tries", "tracks", "track_hits")
 
 
 class Geometry(ctypes.Structure):
@@ -86,6 +88,8 @@ def load() -> ctypes.CDLL:
     L.tpc_load_batch.argtypes = [P, I, I, P, P, P, P, P, P, I]
     L.tpc_track_sector.argtypes = [P, I, I]
     L.tpc_track_event.argtypes = [P, I]
+    L.tpc_track_events.argtypes = [P, P, I]
+    L.tpc_submit.argtypes = [P, I]
     L.tpc_track_event_streams.argtypes = [P, I, I]
     L.tpc_get_tracks.argtypes = [P, I, I, P, I64, P, I64, P, P]
     L.tpc_device_results.argtypes = [P, I, P, P, P, P, P]
@@ -102,7 +106,7 @@ def load() -> ctypes.CDLL:
     L.tpc_get_merge_links.argtypes = [P, I, I, P, P, P, P]
     F, D = ctypes.c_float, ctypes.c_double
     L.tpc_calib_accumulate.argtypes = [P, I, P, I, F, F]
-    L.tpc_calib_fit.argtypes = [P, I, F, F, F, P, P]
+    L.tpc_calib_fit.argtypes = [P, I, F, F, F, D, P, P]
     L.tpc_calib_correct_z.argtypes = [P, P, P, I64, D]
     L.tpc_last_error.restype = ctypes.c_char_p
     L.tpc_last_error.argtypes = [P]

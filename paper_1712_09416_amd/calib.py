@@ -14,10 +14,10 @@ back into the cluster transformation (Section 5.3).  Here:
   kernel, default priority) while the serving loop carries on; a fresh
   histogram takes the new events;
 * feedback: the serving loop polls the fit at every iteration; when it is
-  done, the measured residual eps_r corrects the running estimate,
-  eps <- eps + eps_r (1 + eps) (a drift error eps_r left after correcting
-  with eps composes to exactly this), and every later batch has its cluster
-  z corrected on the device before tracking.  Histograms hold events of one
+  done, the library's fit has already composed the measured residual with
+  the correction those events were tracked with, and the composed value
+  becomes the running estimate; every later batch has its cluster z
+  corrected on the device before tracking.  Histograms hold events of one
   correction only: batches are tagged with the histogram they go to, and a
   new estimate starts a new histogram.
 """
@@ -49,8 +49,8 @@ class DriftCalibration:
         self.device = torch.device(device)
         self.eps = float(eps0)
         self.stream = torch.cuda.Stream(self.device)
-        self.out = torch.zeros(3, dtype=torch.float64, device=self.device)
-        self.out_host = torch.zeros(3, dtype=torch.float64).pin_memory()
+        self.out = torch.zeros(4, dtype=torch.float64, device=self.device)
+        self.out_host = torch.zeros(4, dtype=torch.float64).pin_memory()
         self.cur = _Hist(n_bins, self.device, self.eps, self.stream)
         self.pending = None      # closed histogram waiting for its batches
         self.fitting = None      # (histogram, done event)
@@ -87,7 +87,7 @@ class DriftCalibration:
             h = self.pending
             self.pending = None
             with torch.cuda.stream(self.stream):
-                calib_fit(h.h, self.out, self.z_max, self.z_lo, self.z_hi, stream=self.stream)
+                calib_fit(h.h, self.out, self.z_max, h.eps, self.z_lo, self.z_hi, stream=self.stream)
                 self.out_host.copy_(self.out, non_blocking=True)
                 ev = torch.cuda.Event()
                 ev.record(self.stream)
@@ -95,9 +95,8 @@ class DriftCalibration:
         if self.fitting is not None and self.fitting[1].query():
             h, _ = self.fitting
             self.fitting = None
-            med_a, med_c, eps_r = (float(v) for v in self.out_host)
-            if eps_r == eps_r:                     # not NaN (both sides had tracks)
-                new = h.eps + eps_r * (1.0 + h.eps)
+            med_a, med_c, eps_r, new = (float(v) for v in self.out_host)
+            if new == new:                         # not NaN (both sides had tracks)
                 self.history.append((eps_r, new))
                 self.eps = new
                 # events tracked with the old estimate go nowhere from now on

@@ -32,6 +32,9 @@ struct SlotHost {
   uint8_t* own_row = nullptr;
   float* own_y = nullptr;
   float* own_z = nullptr;
+  // clusters per sector of the built grid, read back for the per-sector
+  // launch sequences (each launch sized by its own sector); empty until read
+  std::vector<uint32_t> sec_n;
 };
 
 // __global__ helpers local to this file
@@ -103,13 +106,24 @@ struct Carver {
   }
 };
 
+// Capacities of the tracklet and track regions: chains of >= 3 hits are
+// disjoint, so a sector of n hits has at most n/3 start hits; an output
+// track owns >= n_min_track hits that no other track owns, so at most
+// n/n_min_track tracks.  Each sector's region gets one entry more.
+int64_t tracklet_cap(const tpc_params& p) {
+  return p.max_clusters / 3 + (int64_t)p.max_events * kSectorsPerEvent;
+}
+int64_t track_cap(const tpc_params& p) {
+  return p.max_clusters / p.n_min_track + (int64_t)p.max_events * kSectorsPerEvent;
+}
+
 void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   const int64_t N = p.max_clusters;
   const int E = p.max_events;
   const int64_t S = (int64_t)E * kSectorsPerEvent;
   const int64_t SR = S * kRows;
-  const int64_t cap_tl = N / 3 + S;
-  const int64_t cap_tk = N / 10 + S;
+  const int64_t cap_tl = tracklet_cap(p);
+  const int64_t cap_tk = track_cap(p);
   uint8_t* own_sector = c.take<uint8_t>(N);
   uint8_t* own_row = c.take<uint8_t>(N);
   float* own_y = c.take<float>(N);
@@ -222,7 +236,7 @@ void carve_lanes(Carver& c, const tpc_params& p, Lane* lanes) {
   const int64_t N = p.max_clusters;
   const int64_t S = (int64_t)p.max_events * kSectorsPerEvent;
   const int64_t SR = S * kRows;
-  const int64_t cap_tl = N / 3 + S;
+  const int64_t cap_tl = tracklet_cap(p);
   for (int i = 0; i < kMaxLanes; ++i) {
     uint32_t* a = c.take<uint32_t>(16);
     uint32_t* b = c.take<uint32_t>(std::max<int64_t>(std::max<int64_t>(N, SR), cap_tl) / kScanTile + 4);
@@ -340,7 +354,7 @@ int build_grid(tpc_ctx* ctx, SlotHost& h) {
   k_row_layout<<<grid_stride_blocks(SR, 256), 256, 0, st>>>(s, ctx->k);
   scan_u32(st, s.row_off, nullptr, SR, s.scan_b, nullptr);
   scan_u32(st, s.row_bin, nullptr, SR, s.scan_b, nullptr);
-  k_row_finish<<<grid_stride_blocks(SR, 256), 256, 0, st>>>(s);
+  k_row_finish<<<grid_stride_blocks(SR, 256), 256, 0, st>>>(s, ctx->p.n_min_track);
   scan_u32(st, s.tl_base, nullptr, s.n_sectors, s.scan_b, nullptr);
   scan_u32(st, s.tk_base, nullptr, s.n_sectors, s.scan_b, nullptr);
   k_scatter<<<grid_stride_blocks(h.n, 256), 256, 0, st>>>(s);
@@ -350,6 +364,29 @@ int build_grid(tpc_ctx* ctx, SlotHost& h) {
   TPC_LAUNCHED();
   h.state = 2;
   return TPC_OK;
+}
+
+// Per-sector cluster counts of the slot's built grid, on the host (one
+// synchronising read per staging; used only by the per-sector sequences).
+int read_sector_counts(tpc_ctx* ctx, SlotHost& h) {
+  if ((int64_t)h.sec_n.size() == (int64_t)h.d.n_sectors) return TPC_OK;
+  const int ns = h.d.n_sectors;
+  std::vector<uint32_t> ro((size_t)ns * kRows + 1);
+  TPC_HIP(hipMemcpyAsync(ro.data(), h.d.row_off, ro.size() * sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, ctx->stream));
+  TPC_HIP(hipStreamSynchronize(ctx->stream));
+  h.sec_n.resize(ns);
+  for (int g = 0; g < ns; ++g) h.sec_n[g] = ro[(size_t)(g + 1) * kRows] - ro[(size_t)g * kRows];
+  return TPC_OK;
+}
+
+// Clusters of sectors [g0, g0 + ns): exact when the per-sector counts were
+// read, else the slot's total (a bound).
+int64_t range_clusters(const SlotHost& h, int g0, int ns) {
+  if ((int64_t)h.sec_n.size() != (int64_t)h.d.n_sectors || ns == h.d.n_sectors) return h.n;
+  int64_t n = 0;
+  for (int g = g0; g < g0 + ns; ++g) n += h.sec_n[g];
+  return n;
 }
 
 int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nullptr) {
@@ -362,8 +399,10 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
     st = lane->st;
   }
   const bool marks = lane == nullptr;
-  // host bounds for the persistent grids (exact counts live on the device)
-  const int64_t tl_bound = std::min<int64_t>(s.cap_tl, h.n / 3 + ns);
+  // host bounds for the grids, from the range's own clusters (the exact
+  // counts live on the device; every kernel strides over them)
+  const int64_t n_range = range_clusters(h, g0, ns);
+  const int64_t tl_bound = std::min<int64_t>(s.cap_tl, n_range / 3 + ns);
   const int nb_lane = std::max(8, grid_stride_blocks(tl_bound, 64, 16384) / 8 * 8);
   const int nb_sel = grid_stride_blocks(tl_bound, 256, 4096);
   k_nf_split<<<1, 64, 0, st>>>(s, g0, ns);
@@ -380,11 +419,11 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
   if (marks) mark(ctx, 4);
   k_select<<<nb_sel, 256, 0, st>>>(s, ctx->k, g0);
   scan_u32(st, s.tl_sel, s.range_cnt + 0, tl_bound, s.scan_b, s.range_cnt + 1, false);
-  k_track_write<<<nb_sel, 256, 0, st>>>(s, g0);
+  k_track_write<<<nb_sel, 256, 0, st>>>(s, g0, ns);
   if (marks) mark(ctx, 5);
   // four waves per block: a block's waves go to the four SIMDs of one CU,
   // so the few hundred working waves of an event do not share SIMDs
-  k_refit<<<grid_stride_blocks(std::max<int64_t>(1, tl_bound / 4), 256, 1024), 256, 0, st>>>(s, ctx->k, g0);
+  k_refit<<<grid_stride_blocks(std::max<int64_t>(1, tl_bound / 4), 256, 1024), 256, 0, st>>>(s, ctx->k, g0, ns);
   if (marks) mark(ctx, 6);
   TPC_LAUNCHED();
   return TPC_OK;
@@ -429,6 +468,7 @@ int stage(tpc_ctx* ctx, int slot, int n_events, const int64_t* offs, const uint8
   h.n = n;
   h.n_events = n_events;
   h.merged = false;
+  h.sec_n.clear();
   h.ev_off.assign(offs, offs + n_events + 1);
   s.n = n;
   s.n_events = n_events;
@@ -453,6 +493,8 @@ int stage(tpc_ctx* ctx, int slot, int n_events, const int64_t* offs, const uint8
   h.state = 1;
   return record_done(ctx, h);
 }
+
+int track_slot_eager(tpc_ctx* ctx, int slot);
 
 }  // namespace
 
@@ -614,7 +656,9 @@ int tpc_track_sector(tpc_ctx* ctx, int slot, int sector) {
     const int rc = build_grid(ctx, h);
     if (rc) return rc;
   }
-  const int rc = track_range(ctx, h, sector, 1);
+  int rc = read_sector_counts(ctx, h);
+  if (rc) return rc;
+  rc = track_range(ctx, h, sector, 1);
   if (rc) return rc;
   h.state = 3;
   return record_done(ctx, h);
@@ -625,19 +669,7 @@ int tpc_track_event(tpc_ctx* ctx, int slot) {
   if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
   SlotHost& h = ctx->slots[slot];
   if (h.state < 1 || h.state >= 3) return ctx->fail(TPC_ESTATE, "slot not staged or already tracked");
-  mark(ctx, 0);
-  if (h.state < 2) {
-    const int rc = build_grid(ctx, h);
-    if (rc) return rc;
-  }
-  mark(ctx, 1);
-  int rc = track_range(ctx, h, 0, h.d.n_sectors);
-  if (rc) return rc;
-  rc = finalize(ctx, h);
-  if (rc) return rc;
-  ctx->prof_valid = ctx->prof;
-  ctx->prof_slot = slot;
-  return record_done(ctx, h);
+  return track_slot_eager(ctx, slot);
 }
 
 int tpc_track_event_streams(tpc_ctx* ctx, int slot, int n_streams) {
@@ -656,6 +688,10 @@ int tpc_track_event_streams(tpc_ctx* ctx, int slot, int n_streams) {
   if (!ctx->fork) TPC_HIP(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
   if (h.state < 2) {
     const int rc = build_grid(ctx, h);
+    if (rc) return rc;
+  }
+  {
+    const int rc = read_sector_counts(ctx, h);
     if (rc) return rc;
   }
   TPC_HIP(hipEventRecord(ctx->fork, ctx->stream));
@@ -823,13 +859,14 @@ int tpc_calib_accumulate(tpc_ctx* ctx, int slot, uint32_t* hist, int n_bins, flo
 }
 
 int tpc_calib_fit(const uint32_t* hist, int n_bins, float z_lo, float z_hi, float z_max,
-                  double* out, void* hip_stream) {
+                  double eps_tracked, double* out, void* hip_stream) {
   if (!hist || !out || n_bins < 1 || n_bins > (1 << 20) || !std::isfinite(z_lo) ||
-      !std::isfinite(z_hi) || !(z_hi > z_lo) || !(z_max > 0.0f))
+      !std::isfinite(z_hi) || !(z_hi > z_lo) || !(z_max > 0.0f) || !std::isfinite(eps_tracked) ||
+      !(std::fabs(eps_tracked) < 0.5))
     return TPC_EINVAL;
   const double w = ((double)z_hi - (double)z_lo) / (double)n_bins;
   k_cal_fit<<<1, 256, 0, reinterpret_cast<hipStream_t>(hip_stream)>>>(hist, n_bins, (double)z_lo, w,
-                                                                       (double)z_max, out);
+                                                                       (double)z_max, eps_tracked, out);
   return hipGetLastError() == hipSuccess ? TPC_OK : TPC_EDEVICE;
 }
 
@@ -844,12 +881,18 @@ int tpc_calib_correct_z(tpc_ctx* ctx, const uint8_t* sector, float* z, int64_t n
   return TPC_OK;
 }
 
-int tpc_graph_capture(tpc_ctx* ctx, int slot) {
-  if (!ctx) return TPC_EINVAL;
-  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
-  SlotHost& h = ctx->slots[slot];
-  if (h.state < 1) return ctx->fail(TPC_ESTATE, "slot not staged");
-  if (!ctx->stream) return ctx->fail(TPC_EINVAL, "graph capture needs a non-default stream");
+}  // extern "C"
+
+namespace {
+
+// The slot's graph was captured for its current staging (same inputs, same
+// event offsets), so replaying it tracks what is staged now.
+bool graph_matches(const SlotHost& h) {
+  return h.graph && h.ev_off == h.graph_ev_off && h.graph_in[0] == h.d.sector &&
+         h.graph_in[1] == h.d.row && h.graph_in[2] == h.d.y && h.graph_in[3] == h.d.z;
+}
+
+int capture_slot(tpc_ctx* ctx, SlotHost& h) {
   if (h.graph) {
     TPC_HIP(hipGraphExecDestroy(h.graph));
     h.graph = nullptr;
@@ -884,18 +927,87 @@ int tpc_graph_capture(tpc_ctx* ctx, int slot) {
   return TPC_OK;
 }
 
+int launch_slot_graph(tpc_ctx* ctx, SlotHost& h) {
+  TPC_HIP(hipGraphLaunch(h.graph, ctx->stream));
+  h.state = 4;
+  return record_done(ctx, h);
+}
+
+// The one-launch-per-step sequence of a staged slot (tpc_track_event).
+int track_slot_eager(tpc_ctx* ctx, int slot) {
+  SlotHost& h = ctx->slots[slot];
+  mark(ctx, 0);
+  if (h.state < 2) {
+    const int rc = build_grid(ctx, h);
+    if (rc) return rc;
+  }
+  mark(ctx, 1);
+  int rc = track_range(ctx, h, 0, h.d.n_sectors);
+  if (rc) return rc;
+  rc = finalize(ctx, h);
+  if (rc) return rc;
+  ctx->prof_valid = ctx->prof;
+  ctx->prof_slot = slot;
+  return record_done(ctx, h);
+}
+
+}  // namespace
+
+extern "C" {
+
+int tpc_graph_capture(tpc_ctx* ctx, int slot) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  SlotHost& h = ctx->slots[slot];
+  if (h.state < 1) return ctx->fail(TPC_ESTATE, "slot not staged");
+  if (!ctx->stream) return ctx->fail(TPC_EINVAL, "graph capture needs a non-default stream");
+  return capture_slot(ctx, h);
+}
+
 int tpc_graph_launch(tpc_ctx* ctx, int slot) {
   if (!ctx) return TPC_EINVAL;
   if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
   SlotHost& h = ctx->slots[slot];
   if (!h.graph) return ctx->fail(TPC_ESTATE, "no graph captured for the slot");
   if (h.state < 1) return ctx->fail(TPC_ESTATE, "slot not staged");
-  if (h.ev_off != h.graph_ev_off || h.graph_in[0] != h.d.sector || h.graph_in[1] != h.d.row ||
-      h.graph_in[2] != h.d.y || h.graph_in[3] != h.d.z)
-    return ctx->fail(TPC_ESTATE, "slot staged with another shape than at capture");
-  TPC_HIP(hipGraphLaunch(h.graph, ctx->stream));
-  h.state = 4;
-  return record_done(ctx, h);
+  if (!graph_matches(h)) return ctx->fail(TPC_ESTATE, "slot staged with another shape than at capture");
+  return launch_slot_graph(ctx, h);
+}
+
+int tpc_track_events(tpc_ctx* ctx, const int* slots, int n) {
+  if (!ctx) return TPC_EINVAL;
+  if (!slots || n < 1 || n > ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "bad slot list");
+  if (!ctx->stream) return ctx->fail(TPC_EINVAL, "graph replay needs a non-default stream");
+  if (ctx->capturing) return ctx->fail(TPC_ESTATE, "not available under capture");
+  std::vector<char> seen(ctx->p.max_slots, 0);
+  for (int i = 0; i < n; ++i) {
+    if (slots[i] < 0 || slots[i] >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+    if (seen[slots[i]]) return ctx->fail(TPC_EINVAL, "slot listed twice");
+    seen[slots[i]] = 1;
+  }
+  for (int i = 0; i < n; ++i)
+    if (ctx->slots[slots[i]].state < 1) return ctx->fail(TPC_ESTATE, "slot not staged");
+  for (int i = 0; i < n; ++i) {
+    SlotHost& h = ctx->slots[slots[i]];
+    if (!graph_matches(h)) {
+      const int rc = capture_slot(ctx, h);
+      if (rc) return rc;
+    }
+    const int rc = launch_slot_graph(ctx, h);
+    if (rc) return rc;
+  }
+  return TPC_OK;
+}
+
+int tpc_submit(tpc_ctx* ctx, int slot) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  if (ctx->capturing) return ctx->fail(TPC_ESTATE, "not available under capture");
+  SlotHost& h = ctx->slots[slot];
+  if (h.state < 1) return ctx->fail(TPC_ESTATE, "slot not staged");
+  if (graph_matches(h)) return launch_slot_graph(ctx, h);
+  if (h.state >= 3) return ctx->fail(TPC_ESTATE, "slot already tracked");
+  return track_slot_eager(ctx, slot);
 }
 
 int tpc_poll(tpc_ctx* ctx, int slot) {
@@ -934,11 +1046,14 @@ int tpc_get_profile(tpc_ctx* ctx, double* ms, uint64_t* counters) {
   if (counters) {
     unsigned long long st[8];
     TPC_HIP(hipMemcpy(st, h.d.stats, sizeof(st), hipMemcpyDeviceToHost));
-    uint32_t sorted = 0;
+    uint32_t sorted = 0, out[2] = {0, 0};
     TPC_HIP(hipMemcpy(&sorted, h.d.row_off + (size_t)h.d.n_sectors * kRows, 4, hipMemcpyDeviceToHost));
+    TPC_HIP(hipMemcpy(out, h.d.out_count, sizeof(out), hipMemcpyDeviceToHost));
     for (int i = 0; i < 8; ++i) counters[i] = st[i];
     counters[4] = (uint64_t)h.n;
     counters[5] = sorted;
+    counters[8] = out[0];
+    counters[9] = out[1];
   }
   return TPC_OK;
 }

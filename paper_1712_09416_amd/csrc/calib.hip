@@ -50,9 +50,12 @@ __global__ void __launch_bounds__(256) k_cal_accumulate(Slot S, DevConst K, uint
 }
 
 // one block: out[0] = median z0 of side A, out[1] = of side C (NaN if
-// empty), out[2] = eps
+// empty), out[2] = eps measured on the histogram's events, out[3] = the
+// estimate to use from now on.  The events were tracked after a correction
+// with eps_t; a drift error E corrected with eps_t leaves exactly the error
+// r = (E - eps_t) / (1 + eps_t), so E = eps_t + r (1 + eps_t).
 __global__ void __launch_bounds__(256) k_cal_fit(const uint32_t* hist, int n_bins, double z_lo,
-                                                 double w, double z_max, double* out) {
+                                                 double w, double z_max, double eps_t, double* out) {
   __shared__ unsigned long long part[256];
   __shared__ double med[2];
   for (int side = 0; side < 2; ++side) {
@@ -94,7 +97,9 @@ __global__ void __launch_bounds__(256) k_cal_fit(const uint32_t* hist, int n_bin
   if (threadIdx.x == 0) {
     out[0] = med[0];
     out[1] = med[1];
-    out[2] = (med[1] - med[0]) / (2.0 * z_max);
+    const double r = (med[1] - med[0]) / (2.0 * z_max);
+    out[2] = r;
+    out[3] = eps_t + r * (1.0 + eps_t);
   }
 }
 

@@ -79,11 +79,14 @@ __global__ void __launch_bounds__(256) k_select(Slot S, DevConst K, int g0) {
 
 // Selected tracklets -> tracks of the range (in tracklet order), each with
 // its owned hits compacted (ascending row).  Lane per tracklet, rows walked
-// together by the wave as in k_select.
-__global__ void __launch_bounds__(256) k_track_write(Slot S, int g0) {
+// together by the wave as in k_select.  The range's track region holds
+// every track its hits allow (each owns >= n_min_track hits of its own); a
+// position beyond it is not written and raises the capacity error.
+__global__ void __launch_bounds__(256) k_track_write(Slot S, int g0, int ns) {
   const uint32_t total = S.range_cnt[0];
   const uint32_t ntk = S.range_cnt[1];
   const uint32_t tl0 = S.tl_base[g0], tk0 = S.tk_base[g0];
+  const uint32_t tk_room = S.tk_base[g0 + ns] - tk0;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t tb = (blockIdx.x * blockDim.x + threadIdx.x) & ~63u; tb < total; tb += stride) {
@@ -96,6 +99,10 @@ __global__ void __launch_bounds__(256) k_track_write(Slot S, int g0) {
       const uint32_t pos = S.tl_sel[t];
       const uint32_t next = t + 1 < total ? S.tl_sel[t + 1] : ntk;
       sel = next != pos;
+      if (sel && pos >= tk_room) {
+        atomicOr(&S.err[2], 1u);
+        sel = false;
+      }
       if (sel) {
         k = tk0 + pos;
         const int32_t* info = S.tl_info + (size_t)T * 4;
@@ -203,9 +210,10 @@ __device__ __forceinline__ void refit_pass(const Slot& S, const DevConst& K, con
 // same way, so the Jacobians are evaluated along the fitted track.  Output
 // at the innermost fitted hit; its cluster is marked for the canonical
 // ordering.
-__global__ void __launch_bounds__(256) k_refit(Slot S, DevConst K, int g0) {
-  const uint32_t total = S.range_cnt[1];
+__global__ void __launch_bounds__(256) k_refit(Slot S, DevConst K, int g0, int ns) {
   const uint32_t tk0 = S.tk_base[g0];
+  // tracks past the region were not written (capacity error raised)
+  const uint32_t total = min(S.range_cnt[1], S.tk_base[g0 + ns] - tk0);
   const uint32_t stride = gridDim.x * blockDim.x;
   unsigned nfit = 0;
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {

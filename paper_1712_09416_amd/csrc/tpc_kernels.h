@@ -8,7 +8,7 @@ namespace tpc {
 // stage + grid
 __global__ void k_count(Slot S);
 __global__ void k_row_layout(Slot S, DevConst K);
-__global__ void k_row_finish(Slot S);
+__global__ void k_row_finish(Slot S, int n_min_track);
 __global__ void k_scatter(Slot S);
 __global__ void k_row_sort_tiny(Slot S);
 __global__ void k_row_sort_small(Slot S);
@@ -21,8 +21,8 @@ __global__ void k_start_write(Slot S, int g0, int ns);
 // Kalman filter
 __global__ void k_tracklets(Slot S, DevConst K, int g0);
 __global__ void k_select(Slot S, DevConst K, int g0);
-__global__ void k_track_write(Slot S, int g0);
-__global__ void k_refit(Slot S, DevConst K, int g0);
+__global__ void k_track_write(Slot S, int g0, int ns);
+__global__ void k_refit(Slot S, DevConst K, int g0, int ns);
 // output
 __global__ void k_scan_tiles(const uint32_t* in, const uint32_t* n_dev, int64_t n_host,
                              uint32_t* partial);
@@ -54,7 +54,7 @@ __global__ void k_mg_write(Slot S, DevConst K, MergeSlot M);
 __global__ void k_cal_accumulate(Slot S, DevConst K, uint32_t* hist, int n_bins, double z_lo,
                                  double w);
 __global__ void k_cal_fit(const uint32_t* hist, int n_bins, double z_lo, double w, double z_max,
-                          double* out);
+                          double eps_t, double* out);
 __global__ void k_cal_correct(const uint8_t* sector, float* z, int64_t n, double eps, double z_max);
 
 }  // namespace tpc

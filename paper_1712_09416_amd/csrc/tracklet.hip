@@ -49,8 +49,9 @@ __device__ __forceinline__ int32_t search_row(const Slot& S, const DevConst& K, 
 }
 
 __device__ __forceinline__ bool try_hit(const DevConst& K, Helix<float>& h, const Hit& x, float vy,
-                                        float vz) {
+                                        float vz, unsigned& tries) {
   float ch;
+  ++tries;
   return kalman_update(h, x.y, x.z, vy, vz, K.chi2max, K.smax, true, &ch);
 }
 
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
   const uint32_t chunk = (total + kXcd - 1) / kXcd;
   const uint32_t c0 = xcd * chunk;
   const uint32_t c1 = min(total, c0 + chunk);
-  unsigned visits = 0, examined = 0, done = 0;
+  unsigned visits = 0, examined = 0, done = 0, tl_hits = 0, tries = 0;
   for (uint32_t t = c0 + j * blockDim.x + threadIdx.x; t < c1; t += nbx * blockDim.x) {
     ++done;
     const uint32_t T = base + t;
@@ -139,13 +140,13 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
       if (chain) {
         if (next >= 0) {
           xg = xnext;
-          if (try_hit(K, st, xg, vy, vz)) got = next;
+          if (try_hit(K, st, xg, vy, vz, tries)) got = next;
         }
         if (got < 0) chain = false;
       }
       if (got < 0) {
         const int32_t bh = search_row(S, K, rb, st, vy, vz, examined, xg);
-        if (bh >= 0 && try_hit(K, st, xg, vy, vz)) got = bh;
+        if (bh >= 0 && try_hit(K, st, xg, vy, vz, tries)) got = bh;
       }
       hits[r] = got;
       if (got >= 0) {
@@ -199,11 +200,11 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
       const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
       const float vy = sy * sy, vz = sz * sz;
       int32_t got = -1;
-      if (uh >= 0 && try_hit(K, st, xu, vy, vz)) got = uh;
+      if (uh >= 0 && try_hit(K, st, xu, vy, vz, tries)) got = uh;
       if (got < 0) {
         Hit xs;
         const int32_t bh = search_row(S, K, rb, st, vy, vz, examined, xs);
-        if (bh >= 0 && try_hit(K, st, xs, vy, vz)) got = bh;
+        if (bh >= 0 && try_hit(K, st, xs, vy, vz, tries)) got = bh;
       }
       hits[r] = got;
       if (got >= 0) {
@@ -215,6 +216,7 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
         break;
       }
     }
+    tl_hits += (unsigned)n;
     int32_t* info = S.tl_info + (size_t)T * 4;
     const bool valid = n >= K.n_min_tracklet;
     info[0] = n;
@@ -248,6 +250,8 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
   wave_add_u64(&S.stats[0], done);
   wave_add_u64(&S.stats[1], visits);
   wave_add_u64(&S.stats[2], examined);
+  wave_add_u64(&S.stats[6], tl_hits);
+  wave_add_u64(&S.stats[7], tries);
 }
 
 }  // namespace tpc

@@ -107,7 +107,7 @@ class _Worker:
             for s in range(36 * len(ids)):
                 self.trk.track_sector(0, s)
         else:
-            self.trk.track_event(0)
+            self.trk.submit(0)
         if calib:
             # on the tracker's stream: the histogram's zeroing is already
             # ordered by on_submit, and nothing else needs torch's stream

@@ -73,24 +73,48 @@ class Tracker:
         arrs = self._prep(sector, row, y, z, dev)
         if dev:
             self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        self._keep[slot] = arrs
+        self._hold(slot, arrs, dev)
         flags = _lib.TPC_DEVICE if dev else _lib.TPC_HOST
         n = int(arrs[2].shape[0])
         check(self.L.tpc_load_clusters(self.ctx, slot, _ptr(arrs[0]), _ptr(arrs[1]), _ptr(arrs[2]),
                                        _ptr(arrs[3]), None, n, flags), self.ctx)
+        self._staged(slot)
 
     def load_batch(self, slot: int, offsets, sector, row, y, z):
         """Stage len(offsets)-1 events, concatenated, into one slot."""
         dev = isinstance(y, torch.Tensor) and y.is_cuda
         arrs = self._prep(sector, row, y, z, dev)
         offs = np.ascontiguousarray(offsets, np.int64)
-        self._keep[slot] = arrs + (offs,)
         if dev:
             self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._hold(slot, arrs + (offs,), dev)
         flags = _lib.TPC_DEVICE if dev else _lib.TPC_HOST
         check(self.L.tpc_load_batch(self.ctx, slot, len(offs) - 1, offs.ctypes.data, _ptr(arrs[0]),
                                     _ptr(arrs[1]), _ptr(arrs[2]), _ptr(arrs[3]), None, flags),
               self.ctx)
+        self._staged(slot)
+
+    def _hold(self, slot, arrs, dev):
+        """Keep the staged arrays alive while the tracker's stream may read
+        them.  Device tensors are marked as used on that stream (the
+        allocator then does not hand their memory out before the stream's
+        work is done); host arrays replaced here are released only after the
+        copies queued from them have finished."""
+        if dev:
+            for a in arrs:
+                if isinstance(a, torch.Tensor):
+                    a.record_stream(self.stream)
+        old = self._keep.get(slot)
+        if old is not None and old[1] is not None:
+            old[1].synchronize()
+        self._keep[slot] = (arrs, None)
+
+    def _staged(self, slot):
+        arrs, _ = self._keep[slot]
+        if not (isinstance(arrs[2], torch.Tensor) and arrs[2].is_cuda):
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+            self._keep[slot] = (arrs, ev)
 
     @staticmethod
     def _prep(sector, row, y, z, dev):
@@ -103,6 +127,17 @@ class Tracker:
     # -- tracking --------------------------------------------------------------
     def track_event(self, slot: int = 0):
         check(self.L.tpc_track_event(self.ctx, slot), self.ctx)
+
+    def track_events(self, slots):
+        """Track several staged slots, each by one replay of its HIP graph
+        (captured on first use for the slot's staging)."""
+        arr = np.ascontiguousarray(slots, np.int32)
+        check(self.L.tpc_track_events(self.ctx, arr.ctypes.data, len(arr)), self.ctx)
+
+    def submit(self, slot: int = 0):
+        """Enqueue the tracking of a staged slot and return at once (graph
+        replay if one was captured for the staging); see poll()."""
+        check(self.L.tpc_submit(self.ctx, slot), self.ctx)
 
     def track_event_streams(self, slot: int = 0, n_streams: int = 4):
         """Per-sector launch sequences spread over n_streams streams."""
@@ -211,9 +246,16 @@ class Tracker:
         """One float transport + gated update per row of state[n, 20]
         (in place).  Returns (bits int32[n], chi2 float32[n])."""
         n = state.shape[0]
+        cur = torch.cuda.current_stream(self.device)
         res = torch.zeros((n, 2), dtype=torch.float32, device=state.device)
+        # the inputs and res were written on torch's stream; the result is
+        # read there again
+        self.stream.wait_stream(cur)
+        for t in (state, dx, meas, res):
+            t.record_stream(self.stream)
         check(self.L.tpc_kf_step_f32(self.ctx, state.data_ptr(), dx.data_ptr(), meas.data_ptr(),
                                      res.data_ptr(), n), self.ctx)
+        cur.wait_stream(self.stream)
         return res[:, 0].contiguous().view(torch.int32), res[:, 1].contiguous()
 
     def set_profiling(self, on: bool = True):
@@ -222,10 +264,10 @@ class Tracker:
     def profile(self):
         """(stage milliseconds dict, counters dict) of the last tracked slot."""
         ms = np.zeros(len(_lib.STAGES), np.float64)
-        cnt = np.zeros(8, np.uint64)
+        cnt = np.zeros(len(_lib.COUNTERS), np.uint64)
         check(self.L.tpc_get_profile(self.ctx, ms.ctypes.data, cnt.ctypes.data), self.ctx)
-        names = ("tracklets", "row_visits", "window_hits", "tracks", "clusters", "sorted_hits")
-        return dict(zip(_lib.STAGES, ms.tolist())), {k: int(cnt[i]) for i, k in enumerate(names)}
+        return (dict(zip(_lib.STAGES, ms.tolist())),
+                {k: int(cnt[i]) for i, k in enumerate(_lib.COUNTERS)})
 
     def synchronize(self):
         self.stream.synchronize()
@@ -242,12 +284,14 @@ class Tracker:
             pass
 
 
-def calib_fit(hist: torch.Tensor, out: torch.Tensor, z_max: float, z_lo: float = -20.0,
-              z_hi: float = 20.0, stream=None):
-    """Median z0 per side and eps into out (3 float64 on the device), on the
-    given stream (default: torch's current one); asynchronous."""
+def calib_fit(hist: torch.Tensor, out: torch.Tensor, z_max: float, eps_tracked: float = 0.0,
+              z_lo: float = -20.0, z_hi: float = 20.0, stream=None):
+    """Median z0 per side, the measured drift error and the estimate to adopt
+    (composed with eps_tracked, the correction the events were tracked with)
+    into out (4 float64 on the device), on the given stream (default: torch's
+    current one); asynchronous."""
     L = _lib.load()
-    assert hist.is_cuda and out.is_cuda and out.dtype == torch.float64 and out.numel() >= 3
+    assert hist.is_cuda and out.is_cuda and out.dtype == torch.float64 and out.numel() >= 4
     st = stream if stream is not None else torch.cuda.current_stream(hist.device)
-    check(L.tpc_calib_fit(hist.data_ptr(), hist.shape[1], z_lo, z_hi, z_max, out.data_ptr(),
-                          st.cuda_stream))
+    check(L.tpc_calib_fit(hist.data_ptr(), hist.shape[1], z_lo, z_hi, z_max, float(eps_tracked),
+                          out.data_ptr(), st.cuda_stream))

@@ -159,6 +159,55 @@ def test_calls_rejected_before_device_work(L):
     assert L.tpc_kf_step_f32(ctx, None, None, None, None, 0) == _lib.TPC_OK
     assert L.tpc_last_error(ctx)
     assert L.tpc_track_event(None, 0) == _lib.TPC_EINVAL
+    # batched graph replay and the serving entry: list and state checks
+    one = np.array([0], np.int32)
+    assert L.tpc_track_events(ctx, None, 1) == _lib.TPC_EINVAL
+    assert L.tpc_track_events(ctx, one.ctypes.data, 0) == _lib.TPC_EINVAL
+    assert L.tpc_track_events(ctx, one.ctypes.data, 1) == _lib.TPC_EINVAL       # default stream
+    assert L.tpc_submit(ctx, 0) == _lib.TPC_ESTATE
+    assert L.tpc_submit(ctx, 5) == _lib.TPC_EINVAL
+    assert L.tpc_submit(None, 0) == _lib.TPC_EINVAL
+    # drift fit: histogram, range and the eps the events were tracked with
+    h = np.zeros(8, np.uint32)
+    o = np.zeros(4, np.float64)
+    assert L.tpc_calib_fit(None, 4, -1.0, 1.0, 250.0, 0.0, o.ctypes.data, None) == _lib.TPC_EINVAL
+    assert L.tpc_calib_fit(h.ctypes.data, 4, 1.0, -1.0, 250.0, 0.0, o.ctypes.data, None) == _lib.TPC_EINVAL
+    assert L.tpc_calib_fit(h.ctypes.data, 4, -1.0, 1.0, 250.0, 0.7, o.ctypes.data, None) == _lib.TPC_EINVAL
+    assert L.tpc_calib_fit(h.ctypes.data, 4, -1.0, 1.0, 250.0, float("nan"), o.ctypes.data,
+                           None) == _lib.TPC_EINVAL
+
+
+def test_track_events_checks_every_slot_first(L):
+    """A bad entry anywhere in the list is refused before any slot is
+    tracked (a non-null stream handle makes the list checks reachable; no
+    call below reaches the device)."""
+    p = default_params(max_clusters=1 << 10, max_slots=3)
+    need = L.tpc_workspace_bytes(ctypes.byref(p))
+    ctx = ctypes.c_void_p()
+    assert L.tpc_init_geometry(ctypes.byref(ctx), ctypes.byref(_geo()), ctypes.byref(p), 0x100000,
+                               need, 0x1000) == _lib.TPC_OK
+    for bad, rc in (([0, 3], _lib.TPC_EINVAL), ([1, 1], _lib.TPC_EINVAL), ([2, -1], _lib.TPC_EINVAL),
+                    ([0, 1], _lib.TPC_ESTATE), ([0, 1, 2, 0], _lib.TPC_EINVAL)):
+        arr = np.array(bad, np.int32)
+        assert L.tpc_track_events(ctx, arr.ctypes.data, len(arr)) == rc, bad
+
+
+def test_track_regions_sized_for_n_min_track(L):
+    """Every output track owns at least n_min_track hits that no other
+    track owns, so a slot of N clusters needs room for N / n_min_track
+    tracks: the workspace grows as n_min_track falls, and values below 3
+    are refused."""
+    sizes = []
+    for nmt in (10, 5, 3):
+        p = default_params(max_clusters=1 << 20, n_min_track=nmt)
+        sizes.append(L.tpc_workspace_bytes(ctypes.byref(p)))
+    assert 0 < sizes[0] < sizes[1] < sizes[2]
+    # the track regions (par, cov, owned hits and rows, merger buffers) are
+    # the only part that changes: about 1.8 kB per track of capacity
+    per_track = (sizes[2] - sizes[0]) / ((1 << 20) // 3 - (1 << 20) // 10)
+    assert 1500 < per_track < 2500, per_track
+    bad = default_params(n_min_track=2)
+    assert L.tpc_workspace_bytes(ctypes.byref(bad)) == 0
 
 
 def test_batch_event_limit(L):
