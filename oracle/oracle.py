@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
                 ("m_edge", ctypes.c_float), ("m_z", ctypes.c_float),
                 ("n_gap", ctypes.c_int32), ("n_min_tracklet", ctypes.c_int32),
                 ("n_min_track", ctypes.c_int32), ("x0_cm", ctypes.c_float),
-                ("ms_mass", ctypes.c_float)]
+                ("ms_mass", ctypes.c_float), ("n_min_chain", ctypes.c_int32)]
 
 
 # The oracle's own constants for the tracker (the values this project
@@ -63,7 +63,8 @@ DEFAULT_MERGE = dict(chi2_max=30.0, row_gap=12, step_max=2.0, passes=3, s_max=0.
 
 DEFAULT_PARAMS = dict(nf_window=3.0, nf_mmax=16.0, chi2_max=16.0, k_win=4.0, w_max=5.0,
                       s_max=0.95, c_s0=1.0, c_t0=1.0, c_q0=100.0, m_edge=1.0, m_z=1.0,
-                      n_gap=6, n_min_tracklet=10, n_min_track=10, x0_cm=0.0, ms_mass=0.13957)
+                      n_gap=6, n_min_tracklet=10, n_min_track=10, x0_cm=0.0, ms_mass=0.13957,
+                      n_min_chain=4)
 
 TRACK_DTYPE = np.dtype([("sector", "<i4"), ("n_hits", "<i4"), ("row_in", "<i4"),
                         ("row_out", "<i4"), ("hit_off", "<i8"), ("inner_id", "<i4"),

@@ -55,6 +55,7 @@ struct orc_params {
   int32_t n_min_track;
   float x0_cm;          // radiation length of the gas for the scattering noise (0: none)
   float ms_mass;        // particle mass assumed by the scattering law (GeV)
+  int32_t n_min_chain;  // hits of a cleaned chain that starts a tracklet (>= 3)
 };
 
 // One output track.  Values of a float run are stored exactly in double.
@@ -558,12 +559,20 @@ struct Sector {
       }
   }
 
-  // ---- O4: start hits: chain of >= 3 hits begins here ------------------------
+  // ---- O4: start hits: a cleaned chain of >= n_min_chain hits begins here ----
+  // (no cleaned down link; following the cleaned up links reaches
+  // n_min_chain hits in all)
   void starts(std::vector<int32_t>& out) const {
     for (int r = 0; r < kRows; ++r)
       for (int32_t h : rows[r]) {
-        const int32_t u = (*upc)[h];
-        if (u >= 0 && (*dnc)[h] < 0 && (*upc)[u] >= 0) out.push_back(h);
+        if ((*dnc)[h] >= 0 || (*upc)[h] < 0) continue;
+        int n = 1;
+        int32_t k = h;
+        while (n < c.P->n_min_chain && (*upc)[k] >= 0) {
+          k = (*upc)[k];
+          ++n;
+        }
+        if (n >= c.P->n_min_chain) out.push_back(h);
       }
     std::sort(out.begin(), out.end());
   }

@@ -58,12 +58,39 @@ def test_link_invariants(oracle_lib):
     # chains are disjoint paths: every hit has at most one cleaned predecessor
     tgt = r.upc[r.upc >= 0]
     assert len(np.unique(tgt)) == len(tgt)
-    # start hits: begin a cleaned chain of >= 3 hits
-    s = r.starts
-    assert np.all(r.upc[s] >= 0) and np.all(r.dnc[s] < 0) and np.all(r.upc[r.upc[s]] >= 0)
-    cand = np.nonzero((r.upc >= 0) & (r.dnc < 0))[0]
-    cand = cand[r.upc[r.upc[cand]] >= 0]
-    assert np.array_equal(np.sort(cand), np.sort(s))
+    # start hits: begin a cleaned chain of >= n_min_chain hits
+    assert np.array_equal(np.sort(r.starts), _chain_heads(r, oracle_lib.DEFAULT_PARAMS["n_min_chain"]))
+
+
+def _chain_heads(r, n_min):
+    """Hits without a cleaned down link whose cleaned chain (followed hit by
+    hit along the cleaned up links) holds at least n_min hits."""
+    out = []
+    for h in np.nonzero((r.upc >= 0) & (r.dnc < 0))[0]:
+        n, c = 1, h
+        while r.upc[c] >= 0:
+            c = r.upc[c]
+            n += 1
+        if n >= n_min:
+            out.append(h)
+    return np.array(sorted(out), np.int64)
+
+
+@pytest.mark.parametrize("n_min", [3, 4, 5, 8])
+def test_start_hits_are_chain_heads(oracle_lib, n_min):
+    """The start-hit rule against its definition: the oracle's start hits
+    are exactly the heads of cleaned chains of >= n_min_chain hits (walked
+    here in Python from the links); the chain length leaves the links
+    unchanged, and a longer minimum keeps a subset of the start hits."""
+    ev = tpcgen.pbpb_event(tpcgen.seed_for(2) + 6, 1500)
+    r = oracle_lib.run_event(ev, precision=32, params=oracle_lib.make_params(n_min_chain=n_min))
+    r3 = oracle_lib.run_event(ev, precision=32, params=oracle_lib.make_params(n_min_chain=3))
+    heads = _chain_heads(r, n_min)
+    assert len(heads) > 100
+    assert np.array_equal(np.sort(r.starts), heads)
+    for k in ("up", "dn", "upc", "dnc"):
+        assert np.array_equal(getattr(r, k), getattr(r3, k))
+    assert set(r.starts.tolist()) <= set(r3.starts.tolist())
 
 
 def test_neighbours_are_global_best_pair(oracle_lib):
