@@ -22,20 +22,28 @@ sys.path.insert(0, ROOT)
 METRIC = "tracked clusters/s on central Pb-Pb-shaped event; p50/p99 event latency"
 HBM_PEAK_GBS = 8000.0
 
-# algorithmic bytes of the tracklet kernel (one launch): per tracklet, the
-# start hit, the seed pair and the tracklet record (64 B); per row visit,
-# the hit index written, the chain link, one hit's (y, z) and the bin range
-# (24 B); per hit inside a search window, its (y, z, id) (12 B)
-BYTES_PER_TRACKLET = 64
-BYTES_PER_ROW_VISIT = 24
-BYTES_PER_WINDOW_HIT = 12
+# Algorithmic bytes (what the method has to move, counted per unit of work
+# with the units counted on the device in the same run):
+#  - the tracklet kernel, per launch: 20 B per tracklet row visit (the hit's
+#    y/z, its chain link and the row's bin range) + 14 B per tracklet hit
+#    (the hit-list entry and the ownership weight's read-modify-write);
+#  - the whole path, per event: 67 B per cluster (grid 30, neighbours 24,
+#    cleaner + start hits 13) + the tracklet terms + 12 B per track hit
+#    (list, weight, y/z read, ID written) + 84 B per output track.
+BYTES_PER_ROW_VISIT = 20
+BYTES_PER_TRACKLET_HIT = 14
+BYTES_PER_CLUSTER = 67
+BYTES_PER_TRACK_HIT = 12
+BYTES_PER_TRACK = 84
 
+# VALU issue peak: 256 CUs x 4 SIMDs, each issuing one wave64 vector
+# instruction per 4 cycles at 2.4 GHz
+VALU_PEAK_GINST_S = 256 * 4 * 2.4 / 4.0
 
-# HBM bytes of one k_tracklets launch measured with rocprofv3 counters
-# (FETCH_SIZE and WRITE_SIZE runs, scaled by the factor that makes each
-# counter read a 1 GiB copy's bytes); used only while the kernel's sources
-# are those the counters were taken on
+# Counter summaries of the tracklet kernel (rocprofv3 --pmc runs), used only
+# while the kernel's sources are those the counters were taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tracklets_central_pbpb_traffic.md")
+SQ_FILE = os.path.join(ROOT, "profiles", "k_tracklets_central_pbpb_sq.md")
 KERNEL_SOURCES = ("paper_1712_09416_amd/csrc/tracklet.hip", "paper_1712_09416_amd/csrc/tpc_device.h",
                   "paper_1712_09416_amd/csrc/tpc_kernels.h")
 
@@ -49,24 +57,59 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """(bytes per launch, source hash) from the committed counter summary,
-    or None if absent or taken on other kernel sources."""
+def _summary_value(path: str, key: str):
+    """Integer `key: value` of a committed counter summary, or None if the
+    file is absent or was taken on other kernel sources."""
     import re
     try:
-        txt = open(TRAFFIC_FILE).read()
+        txt = open(path).read()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_launch:\s*([0-9]+)", txt)
+    m = re.search(key + r":\s*([0-9]+)", txt)
     hsh = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
     if not m or not hsh or hsh.group(1) != kernel_source_hash():
         return None
     return int(m.group(1))
 
 
+def measured_traffic():
+    """L2-miss bytes (FETCH_SIZE + WRITE_SIZE, scaled) per tracklet launch."""
+    return _summary_value(TRAFFIC_FILE, "traffic_bytes_per_launch")
+
+
+def measured_valu():
+    """VALU wave instructions (SQ_INSTS_VALU) per tracklet launch."""
+    return _summary_value(SQ_FILE, "valu_insts_per_launch")
+
+
 def tracklet_bytes(cnt: dict) -> int:
-    return (BYTES_PER_TRACKLET * cnt["tracklets"] + BYTES_PER_ROW_VISIT * cnt["row_visits"]
-            + BYTES_PER_WINDOW_HIT * cnt["window_hits"])
+    return BYTES_PER_ROW_VISIT * cnt["row_visits"] + BYTES_PER_TRACKLET_HIT * cnt["tracklet_hits"]
+
+
+def path_bytes(cnt: dict) -> int:
+    return (BYTES_PER_CLUSTER * cnt["clusters"] + tracklet_bytes(cnt)
+            + BYTES_PER_TRACK_HIT * cnt["track_hits"] + BYTES_PER_TRACK * cnt["tracks"])
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def host_threads() -> int:
+    """CPU threads this process may use (its affinity), at most 16 (the
+    share of one GPU's host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 class Ev:
@@ -180,7 +223,7 @@ def bench_serve(pool, geo, n_req: int) -> dict:
              "peripheral": [e for e in evs if e.name == "pbpb_2000"],
              "central": [e for e in evs if e.name == "pbpb_15000"]}
     rng = np.random.default_rng(1712094164)
-    warm = 30
+    warm = max(30, n_req // 10)
     u = rng.uniform(size=n_req + warm)
     kind = np.where(u < 0.70, "pp", np.where(u < 0.95, "peripheral", "central"))
     picks = []
@@ -260,16 +303,42 @@ def bench_serve(pool, geo, n_req: int) -> dict:
             "drift_calibration_side_task": calib_ab(0.7 * c_cb)}
 
 
-def cpu_baseline(ev, threads: int) -> dict:
-    """The oracle (float decisions, double refit) on the same event."""
+def cpu_baseline(ev, threads: int, reps: int = 3, sample_sectors: int = 6) -> dict:
+    """The oracle (float decisions, double refit; as it stands, one sector
+    per thread) timed on the host: the whole central event on `threads`
+    threads, and a sample of its first `sample_sectors` sectors (their
+    clusters only; sectors are tracked independently) on one thread; median
+    of `reps` runs each."""
+    import numpy as np
     from oracle import oracle
     oracle.build(force=False)
-    t = time.perf_counter()
-    r = oracle.run(ev.sector, ev.row, ev.y, ev.z, ev.geometry(), precision=32, nthreads=threads)
-    dt = time.perf_counter() - t
+    geo = ev.geometry()
+
+    def timed(sel, nthreads):
+        ts, nt = [], 0
+        for _ in range(reps):
+            t = time.perf_counter()
+            r = oracle.run(ev.sector[sel], ev.row[sel], ev.y[sel], ev.z[sel], geo, precision=32,
+                           nthreads=nthreads)
+            ts.append(time.perf_counter() - t)
+            nt = len(r.tracks)
+        return float(np.median(ts)), ts, nt
+
+    everything = slice(None)
+    dt, ts, nt = timed(everything, threads)
+    sel = np.nonzero(ev.sector < sample_sectors)[0]
+    dt1, ts1, nt1 = timed(sel, 1)
+    model = cpu_model()
     return {"value": ev.n / dt, "unit": "clusters/s", "cores": threads, "kind": "oracle",
-            "sample": f"whole central event ({ev.n} clusters, 36 sectors, one sector per "
-                      f"thread), {dt:.2f} s, {len(r.tracks)} tracks"}
+            "cpu_model": model,
+            "sample": f"whole central event ({ev.n} clusters, 36 sectors, one sector per thread), "
+                      f"median of {reps} runs: {dt:.2f} s, {nt} tracks",
+            "runs_s": ts,
+            "single_thread": {"value": len(sel) / dt1, "unit": "clusters/s", "cores": 1,
+                              "sample": f"sectors 0-{sample_sectors - 1} of the central event "
+                                        f"({len(sel)} clusters), median of {reps} runs: "
+                                        f"{dt1:.2f} s, {nt1} tracks",
+                              "runs_s": ts1}}
 
 
 def main() -> int:
@@ -289,7 +358,7 @@ def main() -> int:
     ap.add_argument("--batch-events", type=int, default=64,
                     help="events of the batched workload (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=5)
-    ap.add_argument("--serve-requests", type=int, default=300,
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving workload (0: skip it)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -345,10 +414,14 @@ def main() -> int:
         step()
     torch.cuda.synchronize()
 
-    # timed region: K steps back to back on the tracker's stream
+    # timed region: K steps back to back on the tracker's stream, with the
+    # library's stage events on (HIP events between the stages on the same
+    # stream, no synchronisation): the per-stage times are the means over
+    # exactly these K steps
     st = trk.stream                   # every kernel of the tracker runs there
     ev_steps = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                 for _ in range(args.steps)]
+    trk.set_profiling(True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     for e0, e1 in ev_steps:
@@ -359,6 +432,8 @@ def main() -> int:
     wall_ms = (time.perf_counter() - w0) * 1e3
     lat = [e0.elapsed_time(e1) for e0, e1 in ev_steps]
     total_ms = ev_steps[0][0].elapsed_time(ev_steps[-1][1])
+    stage_ms, counters = trk.profile()
+    trk.set_profiling(False)
 
     # end to end: clusters in pinned host memory -> tracks in host memory
     e2e = []
@@ -373,18 +448,6 @@ def main() -> int:
             if k >= 2:
                 e2e.append((time.perf_counter() - t0) * 1e3)
 
-    # per-stage times and work counters: separate profiled steps
-    trk.set_profiling(True)
-    stage_ms = None
-    counters = None
-    n_prof = max(3, min(args.steps, 10))
-    for _ in range(n_prof):
-        step()
-        ms, cnt = trk.profile()       # waits for the step
-        stage_ms = {k: (stage_ms or {}).get(k, 0.0) + v for k, v in ms.items()}
-        counters = cnt
-    trk.set_profiling(False)
-    stage_ms = {k: v / n_prof for k, v in stage_ms.items()}
     tracks, hits = trk.get_tracks(0)
     # whole-job rate from the host clock around the synchronised region (the
     # GPU-event span is reported beside it)
@@ -432,16 +495,40 @@ def main() -> int:
         plain["streams4_ms_per_event"] = ms4
         plain["streams4_clusters_per_s"] = ev.n / (ms4 * 1e-3)
 
+    # roofline of the dominant kernel (k_tracklets, one launch per step):
+    # algorithmic bytes 20 V + 14 H_t over its mean launch time in the timed
+    # region; the limiter named from its counters (VALU issue share against
+    # the L2-miss traffic's share of the HBM peak)
     t_tl = stage_ms["tracklets"] * 1e-3
     ach = tracklet_bytes(counters) / t_tl / 1e9
     traffic = measured_traffic()
-    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    valu = measured_valu()
+    shares = {}
+    if traffic is not None:
+        shares["hbm"] = traffic / t_tl / 1e9 / HBM_PEAK_GBS
+    if valu is not None:
+        shares["alu"] = valu / t_tl / 1e9 / VALU_PEAK_GINST_S
+    bound = max(shares, key=shares.get) if shares else "hbm"
+    roof = {"bound": bound, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_tracklets",
             "algorithmic_bytes": tracklet_bytes(counters),
-            "launch_ms": stage_ms["tracklets"], "copy_kernel_gbs": copy_gbs}
+            "bytes_formula": "20 x row visits + 14 x tracklet hits",
+            "launch_ms": stage_ms["tracklets"], "copy_kernel_gbs": copy_gbs,
+            "limiter_shares": shares,
+            "traffic_note": "traffic = L2-miss bytes (FETCH_SIZE + WRITE_SIZE, scaled by a "
+                            "copy kernel), most of it served by the Infinity Cache"}
     if traffic is not None:
-        # the measured L2-miss traffic per launch over the same launch time
         roof["traffic_gbs"] = traffic / t_tl / 1e9
+    if valu is not None:
+        roof["alu"] = {"valu_insts_per_launch": valu, "achieved_ginst_s": valu / t_tl / 1e9,
+                       "peak_ginst_s": VALU_PEAK_GINST_S,
+                       "frac": valu / t_tl / 1e9 / VALU_PEAK_GINST_S}
+    # the whole path per step: 67 N + 20 V + 14 H_t + 12 H_k + 84 K
+    pb = path_bytes(counters)
+    roof["whole_path"] = {"algorithmic_bytes": pb,
+                          "bytes_formula": "67 N + 20 V + 14 H_t + 12 H_k + 84 K",
+                          "achieved": pb / (ms_per_step * 1e-3) / 1e9,
+                          "frac": pb / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     out = {
         "metric": METRIC,
@@ -483,8 +570,7 @@ def main() -> int:
         out["serve"] = bench_serve(serve_pool, ev.geometry(), args.serve_requests)
         print(f"bench: serve {out['serve']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(ev, threads)
+        out["cpu_baseline"] = cpu_baseline(ev, host_threads())
     print(json.dumps(out), flush=True)
     return 0
 

@@ -91,6 +91,7 @@ typedef struct tpc_params {
   float x0_cm;              /* radiation length of the gas for the multiple-scattering
                                noise of every transport (0: no scattering) */
   float ms_mass;            /* particle mass of the scattering law (GeV) */
+  int32_t n_min_chain;      /* hits of a cleaned chain that starts a tracklet (3..159) */
 } tpc_params;
 
 /* One output track.  par / cov are given at x_ref, the pad-row radius of
@@ -368,10 +369,13 @@ int tpc_poll(tpc_ctx* ctx, int slot);
 
 /* Measurement (the paper reports tracking time per event, Section 4.2,
  * Table 1).  With profiling on, tpc_track_event records HIP events on the
- * context stream around its steps; tpc_get_profile waits for the stream
- * and returns, for the last tracked slot, the milliseconds of each step
- * (ms[TPC_N_STAGES]: grid, neighbours, clean+starts, tracklets,
- * weights+selection, refit, output) and the slot's work counters
+ * context stream around its steps (no synchronisation; a ring of the last
+ * 256 steps); tpc_set_profiling(ctx, 1) starts a new measurement.
+ * tpc_get_profile waits for the stream and returns the milliseconds of each
+ * step averaged over the steps tracked since profiling was switched on (the
+ * last 256 if more) (ms[TPC_N_STAGES]: grid, neighbours, clean+starts,
+ * tracklets, weights+selection, refit, output) and, for the last tracked
+ * slot, its work counters
  * (counters[TPC_N_COUNTERS]: 0 tracklets, 1 tracklet row visits, 2 hits
  * inside the tracklet search windows, 3 tracks refitted, 4 clusters,
  * 5 sorted hits, 6 tracklet hits (final hit lists, all tracklets),

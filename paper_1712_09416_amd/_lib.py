@@ -46,7 +46,8 @@ class Params(ctypes.Structure):
                 ("n_min_track", ctypes.c_int32), ("bin_target", ctypes.c_float),
                 ("bin_min_edge", ctypes.c_float), ("max_slots", ctypes.c_int32),
                 ("max_events", ctypes.c_int32), ("max_clusters", ctypes.c_int64),
-                ("x0_cm", ctypes.c_float), ("ms_mass", ctypes.c_float)]
+                ("x0_cm", ctypes.c_float), ("ms_mass", ctypes.c_float),
+                ("n_min_chain", ctypes.c_int32)]
 
 
 class MergeParams(ctypes.Structure):

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "tpc_device.h"
@@ -106,12 +107,13 @@ struct Carver {
   }
 };
 
-// Capacities of the tracklet and track regions: chains of >= 3 hits are
-// disjoint, so a sector of n hits has at most n/3 start hits; an output
+// Capacities of the tracklet and track regions: cleaned chains are
+// disjoint and a start hit heads one of >= n_min_chain hits, so a sector of
+// n hits has at most n/n_min_chain start hits; an output
 // track owns >= n_min_track hits that no other track owns, so at most
 // n/n_min_track tracks.  Each sector's region gets one entry more.
 int64_t tracklet_cap(const tpc_params& p) {
-  return p.max_clusters / 3 + (int64_t)p.max_events * kSectorsPerEvent;
+  return p.max_clusters / p.n_min_chain + (int64_t)p.max_events * kSectorsPerEvent;
 }
 int64_t track_cap(const tpc_params& p) {
   return p.max_clusters / p.n_min_track + (int64_t)p.max_events * kSectorsPerEvent;
@@ -255,6 +257,7 @@ bool params_ok(const tpc_params* p) {
   if (!(p->max_events >= 1 && p->max_events <= 4096)) return false;
   if (!(p->max_clusters >= 1 && p->max_clusters <= (int64_t)0x7FFFFFFF)) return false;
   if (!(p->n_gap >= 1 && p->n_min_tracklet >= 2 && p->n_min_track >= 3)) return false;
+  if (!(p->n_min_chain >= 3 && p->n_min_chain <= kRows)) return false;
   if (!(p->s_max > 0.0f && p->s_max < 1.0f && p->chi2_max > 0.0f)) return false;
   if (!(p->nf_window > 0.0f && p->k_win > 0.0f && p->w_max > 0.0f)) return false;
   if (!(p->c_s0 > 0.0f && p->c_t0 > 0.0f && p->c_q0 > 0.0f)) return false;
@@ -263,6 +266,70 @@ bool params_ok(const tpc_params* p) {
         std::isfinite(p->ms_mass)))
     return false;
   return true;
+}
+
+// Why a geometry is refused (nullptr if it is valid).
+const char* geometry_error(const tpc_geometry* g) {
+  if (g->n_sectors != TPC_N_SECTORS || g->n_rows != TPC_N_ROWS)
+    return "geometry must have 36 sectors of 159 pad rows";
+  for (int r = 0; r < TPC_N_ROWS; ++r) {
+    if (!(std::isfinite(g->row_x[r]) && g->row_x[r] > 0.0f) ||
+        (r > 0 && !(g->row_x[r] > g->row_x[r - 1])))
+      return "pad-row radii must be positive and increasing";
+  }
+  if (!(g->z_max > 0.0f && g->tan_half_angle > 0.0f && g->sigma_y0 > 0.0f && g->sigma_z0 > 0.0f &&
+        g->sigma_y1 >= 0.0f && g->sigma_z1 >= 0.0f && std::isfinite(g->bz_tesla)))
+    return "bad geometry constants";
+  return nullptr;
+}
+
+// The constants every kernel receives, from a checked geometry and params.
+void fill_constants(DevConst& k, const tpc_geometry* g, const tpc_params* p) {
+  std::memset(&k, 0, sizeof(k));
+  for (int r = 0; r < kRows; ++r) k.row_x[r] = g->row_x[r];
+  k.tanh_half = g->tan_half_angle;
+  k.z_max = g->z_max;
+  k.sy0 = g->sigma_y0;
+  k.sy1 = g->sigma_y1;
+  k.sz0 = g->sigma_z0;
+  k.sz1 = g->sigma_z1;
+  k.sy1z = k.sy1 / k.z_max;
+  k.sz1z = k.sz1 / k.z_max;
+  k.sy1zd = (double)k.sy1 / (double)k.z_max;
+  k.sz1zd = (double)k.sz1 / (double)k.z_max;
+  // curvature per unit q/pT: d(phi)/dl = b q/pT, b = -c Bz, c = 0.00299792458 GeV/(T cm)
+  k.bd = -0.00299792458 * (double)g->bz_tesla;
+  k.b = (float)k.bd;
+  k.nf_w = p->nf_window;
+  k.nf_mmax = p->nf_mmax;
+  k.chi2max = p->chi2_max;
+  k.kwin = p->k_win;
+  k.wmax = p->w_max;
+  k.smax = p->s_max;
+  k.cs0 = p->c_s0;
+  k.ct0 = p->c_t0;
+  k.cq0 = p->c_q0;
+  k.medge = p->m_edge;
+  k.mz = p->m_z;
+  k.n_gap = p->n_gap;
+  k.n_min_tracklet = p->n_min_tracklet;
+  k.n_min_track = p->n_min_track;
+  k.n_min_chain = p->n_min_chain;
+  k.bin_target = p->bin_target;
+  k.bin_min_edge = p->bin_min_edge;
+  // scattering law: theta0^2 = (k^2 / X0) L / (beta p)^2 with
+  // k = 13.6 MeV (1 + 0.038 ln(1 cm / X0)); computed in double on the host
+  if (p->x0_cm > 0.0f) {
+    const double x0 = (double)p->x0_cm;
+    const double kms = 0.0136 * (1.0 + 0.038 * std::log(1.0 / x0));
+    k.kkd = kms * kms / x0;
+    k.m2d = (double)p->ms_mass * (double)p->ms_mass;
+  } else {
+    k.kkd = 0.0;
+    k.m2d = 0.0;
+  }
+  k.kk = (float)k.kkd;
+  k.m2 = (float)k.m2d;
 }
 
 thread_local std::string g_init_error;
@@ -282,7 +349,9 @@ struct tpc_ctx {
   bool prof_valid = false;
   bool capturing = false;
   int prof_slot = -1;
-  hipEvent_t ev[TPC_N_STAGES + 1] = {};
+  // stage-boundary events of the profiled steps, a ring of kProfRing steps
+  std::vector<std::array<hipEvent_t, TPC_N_STAGES + 1>> prof_ev;
+  int64_t prof_n = 0;         // profiled steps completed since profiling was switched on
   Lane lanes[kMaxLanes];
   hipEvent_t fork = nullptr;
   int fail(int code, const std::string& m) {
@@ -307,8 +376,11 @@ struct tpc_ctx {
 
 namespace {
 
+constexpr int kProfRing = 256;
+
 void mark(tpc_ctx* ctx, int i) {
-  if (ctx->prof && !ctx->capturing) (void)hipEventRecord(ctx->ev[i], ctx->stream);
+  if (ctx->prof && !ctx->capturing)
+    (void)hipEventRecord(ctx->prof_ev[(size_t)(ctx->prof_n % kProfRing)][i], ctx->stream);
 }
 
 int record_done(tpc_ctx* ctx, SlotHost& h) {
@@ -354,7 +426,7 @@ int build_grid(tpc_ctx* ctx, SlotHost& h) {
   k_row_layout<<<grid_stride_blocks(SR, 256), 256, 0, st>>>(s, ctx->k);
   scan_u32(st, s.row_off, nullptr, SR, s.scan_b, nullptr);
   scan_u32(st, s.row_bin, nullptr, SR, s.scan_b, nullptr);
-  k_row_finish<<<grid_stride_blocks(SR, 256), 256, 0, st>>>(s, ctx->p.n_min_track);
+  k_row_finish<<<grid_stride_blocks(SR, 256), 256, 0, st>>>(s, ctx->p.n_min_chain, ctx->p.n_min_track);
   scan_u32(st, s.tl_base, nullptr, s.n_sectors, s.scan_b, nullptr);
   scan_u32(st, s.tk_base, nullptr, s.n_sectors, s.scan_b, nullptr);
   k_scatter<<<grid_stride_blocks(h.n, 256), 256, 0, st>>>(s);
@@ -402,7 +474,7 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
   // host bounds for the grids, from the range's own clusters (the exact
   // counts live on the device; every kernel strides over them)
   const int64_t n_range = range_clusters(h, g0, ns);
-  const int64_t tl_bound = std::min<int64_t>(s.cap_tl, n_range / 3 + ns);
+  const int64_t tl_bound = std::min<int64_t>(s.cap_tl, n_range / ctx->p.n_min_chain + ns);
   const int nb_lane = std::max(8, grid_stride_blocks(tl_bound, 64, 16384) / 8 * 8);
   const int nb_sel = grid_stride_blocks(tl_bound, 256, 4096);
   k_nf_split<<<1, 64, 0, st>>>(s, g0, ns);
@@ -410,10 +482,10 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
   if (marks) mark(ctx, 2);
   // a wave per pad row
   const int nb_rows = grid_stride_blocks((int64_t)ns * kRows * 64, 256, 16384);
-  k_clean_rows<<<nb_rows, 256, 0, st>>>(s, g0, ns);
+  k_clean_rows<<<nb_rows, 256, 0, st>>>(s, g0, ns, ctx->p.n_min_chain);
   scan_u32(st, s.row_nstart + (size_t)g0 * kRows, nullptr, (int64_t)ns * kRows, s.scan_b,
            s.range_cnt + 0, false);
-  k_start_write<<<nb_rows, 256, 0, st>>>(s, g0, ns);
+  k_start_write<<<nb_rows, 256, 0, st>>>(s, g0, ns, ctx->p.n_min_chain);
   if (marks) mark(ctx, 3);
   k_tracklets<<<nb_lane, 64, 0, st>>>(s, ctx->k, g0);
   if (marks) mark(ctx, 4);
@@ -524,6 +596,7 @@ int tpc_params_default(tpc_params* p) {
   p->max_clusters = 4 << 20;
   p->x0_cm = 0.0f;
   p->ms_mass = 0.13957f;
+  p->n_min_chain = 4;
   return TPC_OK;
 }
 
@@ -546,20 +619,9 @@ int tpc_init_geometry(tpc_ctx** out, const tpc_geometry* g, const tpc_params* p,
     return TPC_EINVAL;
   }
   *out = nullptr;
-  if (g->n_sectors != TPC_N_SECTORS || g->n_rows != TPC_N_ROWS) {
-    g_init_error = "geometry must have 36 sectors of 159 pad rows";
-    return TPC_EINVAL;
-  }
-  for (int r = 0; r < TPC_N_ROWS; ++r) {
-    if (!(std::isfinite(g->row_x[r]) && g->row_x[r] > 0.0f) ||
-        (r > 0 && !(g->row_x[r] > g->row_x[r - 1]))) {
-      g_init_error = "pad-row radii must be positive and increasing";
-      return TPC_EINVAL;
-    }
-  }
-  if (!(g->z_max > 0.0f && g->tan_half_angle > 0.0f && g->sigma_y0 > 0.0f && g->sigma_z0 > 0.0f &&
-        g->sigma_y1 >= 0.0f && g->sigma_z1 >= 0.0f && std::isfinite(g->bz_tesla))) {
-    g_init_error = "bad geometry constants";
+  const char* bad = geometry_error(g);
+  if (bad) {
+    g_init_error = bad;
     return TPC_EINVAL;
   }
   if (!params_ok(p)) {
@@ -577,51 +639,7 @@ int tpc_init_geometry(tpc_ctx** out, const tpc_geometry* g, const tpc_params* p,
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
   ctx->ws = reinterpret_cast<uint8_t*>(dev_workspace);
   ctx->ws_bytes = ws_bytes;
-  DevConst& k = ctx->k;
-  std::memset(&k, 0, sizeof(k));
-  for (int r = 0; r < kRows; ++r) k.row_x[r] = g->row_x[r];
-  k.tanh_half = g->tan_half_angle;
-  k.z_max = g->z_max;
-  k.sy0 = g->sigma_y0;
-  k.sy1 = g->sigma_y1;
-  k.sz0 = g->sigma_z0;
-  k.sz1 = g->sigma_z1;
-  k.sy1z = k.sy1 / k.z_max;
-  k.sz1z = k.sz1 / k.z_max;
-  k.sy1zd = (double)k.sy1 / (double)k.z_max;
-  k.sz1zd = (double)k.sz1 / (double)k.z_max;
-  // curvature per unit q/pT: d(phi)/dl = b q/pT, b = -c Bz, c = 0.00299792458 GeV/(T cm)
-  k.bd = -0.00299792458 * (double)g->bz_tesla;
-  k.b = (float)k.bd;
-  k.nf_w = p->nf_window;
-  k.nf_mmax = p->nf_mmax;
-  k.chi2max = p->chi2_max;
-  k.kwin = p->k_win;
-  k.wmax = p->w_max;
-  k.smax = p->s_max;
-  k.cs0 = p->c_s0;
-  k.ct0 = p->c_t0;
-  k.cq0 = p->c_q0;
-  k.medge = p->m_edge;
-  k.mz = p->m_z;
-  k.n_gap = p->n_gap;
-  k.n_min_tracklet = p->n_min_tracklet;
-  k.n_min_track = p->n_min_track;
-  k.bin_target = p->bin_target;
-  k.bin_min_edge = p->bin_min_edge;
-  // scattering law: theta0^2 = (k^2 / X0) L / (beta p)^2 with
-  // k = 13.6 MeV (1 + 0.038 ln(1 cm / X0)); computed in double on the host
-  if (p->x0_cm > 0.0f) {
-    const double x0 = (double)p->x0_cm;
-    const double kms = 0.0136 * (1.0 + 0.038 * std::log(1.0 / x0));
-    k.kkd = kms * kms / x0;
-    k.m2d = (double)p->ms_mass * (double)p->ms_mass;
-  } else {
-    k.kkd = 0.0;
-    k.m2d = 0.0;
-  }
-  k.kk = (float)k.kkd;
-  k.m2 = (float)k.m2d;
+  fill_constants(ctx->k, g, p);
   Carver c{ctx->ws, 0, false};
   ctx->slots.resize(p->max_slots);
   for (int i = 0; i < p->max_slots; ++i) carve_slot(c, *p, ctx->slots[i].d, &ctx->slots[i]);
@@ -946,6 +964,7 @@ int track_slot_eager(tpc_ctx* ctx, int slot) {
   if (rc) return rc;
   rc = finalize(ctx, h);
   if (rc) return rc;
+  if (ctx->prof && !ctx->capturing) ++ctx->prof_n;
   ctx->prof_valid = ctx->prof;
   ctx->prof_slot = slot;
   return record_done(ctx, h);
@@ -1023,11 +1042,14 @@ int tpc_poll(tpc_ctx* ctx, int slot) {
 
 int tpc_set_profiling(tpc_ctx* ctx, int enable) {
   if (!ctx) return TPC_EINVAL;
-  if (enable && !ctx->ev[0]) {
-    for (int i = 0; i <= TPC_N_STAGES; ++i) TPC_HIP(hipEventCreate(&ctx->ev[i]));
+  if (enable && ctx->prof_ev.empty()) {
+    ctx->prof_ev.resize(kProfRing);
+    for (auto& set : ctx->prof_ev)
+      for (auto& e : set) TPC_HIP(hipEventCreate(&e));
   }
   ctx->prof = enable != 0;
   ctx->prof_valid = false;
+  ctx->prof_n = 0;
   return TPC_OK;
 }
 
@@ -1037,10 +1059,16 @@ int tpc_get_profile(tpc_ctx* ctx, double* ms, uint64_t* counters) {
   SlotHost& h = ctx->slots[ctx->prof_slot];
   TPC_HIP(hipStreamSynchronize(ctx->stream));
   if (ms) {
+    // mean over the profiled steps still in the ring
+    const int64_t steps = std::min<int64_t>(ctx->prof_n, kProfRing);
     for (int i = 0; i < TPC_N_STAGES; ++i) {
-      float t = 0.0f;
-      TPC_HIP(hipEventElapsedTime(&t, ctx->ev[i], ctx->ev[i + 1]));
-      ms[i] = t;
+      double sum = 0.0;
+      for (int64_t k = 0; k < steps; ++k) {
+        float t = 0.0f;
+        TPC_HIP(hipEventElapsedTime(&t, ctx->prof_ev[(size_t)k][i], ctx->prof_ev[(size_t)k][i + 1]));
+        sum += t;
+      }
+      ms[i] = steps > 0 ? sum / (double)steps : 0.0;
     }
   }
   if (counters) {
@@ -1155,8 +1183,9 @@ const char* tpc_last_error(const tpc_ctx* ctx) {
 int tpc_destroy(tpc_ctx* ctx) {
   if (!ctx) return TPC_EINVAL;
   (void)hipStreamSynchronize(ctx->stream);
-  for (int i = 0; i <= TPC_N_STAGES; ++i)
-    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  for (auto& set : ctx->prof_ev)
+    for (hipEvent_t e : set)
+      if (e) (void)hipEventDestroy(e);
   for (Lane& l : ctx->lanes) {
     if (l.st) {
       (void)hipStreamSynchronize(l.st);
@@ -1174,3 +1203,4 @@ int tpc_destroy(tpc_ctx* ctx) {
 }
 
 }  // extern "C"
+

@@ -146,20 +146,28 @@ __global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, i
     nf_row(S, K, g0 + v / kRows, v % kRows, cand + threadIdx.x);
 }
 
-// Start of a cleaned chain of >= 3 hits, from the links of a3 only.
-__device__ __forceinline__ bool is_start(const Slot& S, uint32_t h, int32_t& uc, int32_t& dc) {
+// Head of a cleaned chain of >= n_min_chain hits (no cleaned down link; the
+// cleaned up links from h reach n_min_chain hits in all), from the links of
+// a3 only: a link is cleaned when it is mutual.
+__device__ __forceinline__ bool is_start(const Slot& S, uint32_t h, int n_min_chain, int32_t& uc,
+                                         int32_t& dc) {
   const int32_t u = S.up[h], d = S.dn[h];
   uc = (u >= 0 && S.dn[u] == (int32_t)h) ? u : -1;
   dc = (d >= 0 && S.up[d] == (int32_t)h) ? d : -1;
   if (uc < 0 || dc >= 0) return false;
-  const int32_t uu = S.up[uc];
-  return uu >= 0 && S.dn[uu] == uc;
+  int n = 2;
+  for (int32_t k = uc; n < n_min_chain; ++n) {
+    const int32_t kk = S.up[k];
+    if (kk < 0 || S.dn[kk] != k) break;
+    k = kk;
+  }
+  return n >= n_min_chain;
 }
 
 // a4: keep a link only if it is mutual; count the start hits of each row.
 // Also clears the hit weights used by the tracklet selection.  One wave per
 // row (rows hold ~100 hits), 64 hits at a time.
-__global__ void __launch_bounds__(256) k_clean_rows(Slot S, int g0, int ns) {
+__global__ void __launch_bounds__(256) k_clean_rows(Slot S, int g0, int ns, int n_min_chain) {
   const int lane = threadIdx.x & 63;
   const int nwaves = (int)(gridDim.x * blockDim.x / 64);
   const int nr = ns * kRows;
@@ -172,7 +180,7 @@ __global__ void __launch_bounds__(256) k_clean_rows(Slot S, int g0, int ns) {
       bool start = false;
       if (h < h1) {
         int32_t uc, dc;
-        start = is_start(S, h, uc, dc);
+        start = is_start(S, h, n_min_chain, uc, dc);
         S.hit[h].upc = uc;
         S.dnc[h] = dc;
         S.weight[h] = 0u;
@@ -186,7 +194,7 @@ __global__ void __launch_bounds__(256) k_clean_rows(Slot S, int g0, int ns) {
 // a4: write the start hits in (sector, row, position) order at the offsets
 // given by the scan of the per-row counts over the launched sector range.
 // One wave per row, as in k_clean_rows.
-__global__ void __launch_bounds__(256) k_start_write(Slot S, int g0, int ns) {
+__global__ void __launch_bounds__(256) k_start_write(Slot S, int g0, int ns, int n_min_chain) {
   const int lane = threadIdx.x & 63;
   const int nwaves = (int)(gridDim.x * blockDim.x / 64);
   const int nr = ns * kRows;
@@ -200,7 +208,7 @@ __global__ void __launch_bounds__(256) k_start_write(Slot S, int g0, int ns) {
       bool start = false;
       if (h < h1) {
         int32_t uc, dc;
-        start = is_start(S, h, uc, dc);
+        start = is_start(S, h, n_min_chain, uc, dc);
       }
       const unsigned long long m = __ballot(start);
       if (start) {

@@ -159,10 +159,10 @@ __global__ void k_row_layout(Slot S, DevConst K) {
 }
 
 // a2 (after the scans): bin bases of the rows, and the per-sector regions
-// for start hits / tracklets (<= n_g/3 + 1: chains of >= 3 hits are
-// disjoint) and tracks (<= n_g/n_min_track + 1: each track owns at least
+// for start hits / tracklets (<= n_g/n_min_chain + 1: each heads its own
+// cleaned chain of >= n_min_chain hits, and the chains are disjoint) and tracks (<= n_g/n_min_track + 1: each track owns at least
 // n_min_track hits no other track owns), as counts for the next scans.
-__global__ void k_row_finish(Slot S, int n_min_track) {
+__global__ void k_row_finish(Slot S, int n_min_chain, int n_min_track) {
   const int SR = S.n_sectors * kRows;
   const int stride = gridDim.x * blockDim.x;
   const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
@@ -170,7 +170,7 @@ __global__ void k_row_finish(Slot S, int n_min_track) {
   for (int sr = t0; sr < SR; sr += stride) S.bins[sr].base = (int32_t)S.row_bin[sr];
   for (int g = t0; g < S.n_sectors; g += stride) {
     const uint32_t ng = S.row_off[(g + 1) * kRows] - S.row_off[g * kRows];
-    S.tl_base[g] = ng / 3 + 1;
+    S.tl_base[g] = ng / (uint32_t)n_min_chain + 1;
     S.tk_base[g] = ng / (uint32_t)n_min_track + 1;
   }
 }

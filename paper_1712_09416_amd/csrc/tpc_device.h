@@ -40,7 +40,7 @@ struct DevConst {
   float b;          // curvature per unit q/pT, float
   double bd;        // same, double (refit)
   float nf_w, nf_mmax, chi2max, kwin, wmax, smax, cs0, ct0, cq0, medge, mz;
-  int n_gap, n_min_tracklet, n_min_track;
+  int n_gap, n_min_tracklet, n_min_track, n_min_chain;
   float bin_target;  // clusters per grid bin aimed at
   float bin_min_edge;
   float kk, m2;             // scattering law k^2/X0 and mass^2 (0: no scattering), float

@@ -8,7 +8,7 @@ namespace tpc {
 // stage + grid
 __global__ void k_count(Slot S);
 __global__ void k_row_layout(Slot S, DevConst K);
-__global__ void k_row_finish(Slot S, int n_min_track);
+__global__ void k_row_finish(Slot S, int n_min_chain, int n_min_track);
 __global__ void k_scatter(Slot S);
 __global__ void k_row_sort_tiny(Slot S);
 __global__ void k_row_sort_small(Slot S);
@@ -16,8 +16,8 @@ __global__ void k_row_sort_large(Slot S);
 // cellular automaton
 __global__ void k_nf_split(Slot S, int g0, int ns);
 __global__ void k_neighbours(Slot S, DevConst K, int g0);
-__global__ void k_clean_rows(Slot S, int g0, int ns);
-__global__ void k_start_write(Slot S, int g0, int ns);
+__global__ void k_clean_rows(Slot S, int g0, int ns, int n_min_chain);
+__global__ void k_start_write(Slot S, int g0, int ns, int n_min_chain);
 // Kalman filter
 __global__ void k_tracklets(Slot S, DevConst K, int g0);
 __global__ void k_select(Slot S, DevConst K, int g0);

@@ -210,6 +210,18 @@ def test_track_regions_sized_for_n_min_track(L):
     assert L.tpc_workspace_bytes(ctypes.byref(bad)) == 0
 
 
+def test_tracklet_regions_sized_for_n_min_chain(L):
+    """A start hit heads its own cleaned chain of >= n_min_chain hits and
+    the chains are disjoint, so a slot of N clusters needs room for
+    N / n_min_chain tracklets: the workspace shrinks as n_min_chain grows;
+    values outside 3..159 are refused."""
+    sizes = [L.tpc_workspace_bytes(ctypes.byref(default_params(max_clusters=1 << 20, n_min_chain=c)))
+             for c in (3, 4, 8)]
+    assert sizes[0] > sizes[1] > sizes[2] > 0
+    for bad in (2, 160):
+        assert L.tpc_workspace_bytes(ctypes.byref(default_params(n_min_chain=bad))) == 0, bad
+
+
 def test_batch_event_limit(L):
     ctx, p = _ctx(L, max_events=4)
     a = np.zeros(10, np.uint8)

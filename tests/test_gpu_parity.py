@@ -299,7 +299,7 @@ def test_edge_cases(dev):
 def edge_rows_event(seed=20261203):
     """Straight tracks placed at the row range's ends, plus seeded uniform
     noise in their sectors: one ending at the last pad row, one starting at
-    pad row 0, one of exactly ten hits, one of runs of five hits with an
+    pad row 0, one of exactly ten hits, one of runs of six hits with an
     empty row between (steps without a hit in every fit), and a nine-hit one
     on the C side that is too short to become a track."""
     from tpcgen.events import Event
@@ -317,7 +317,7 @@ def edge_rows_event(seed=20261203):
     line(4, np.arange(145, 159), 0.02, 0.3)
     line(5, np.arange(0, 15), -0.03, 0.2)
     line(6, np.arange(60, 70), 0.01, 0.5)
-    line(7, [r for r in range(20, 110) if (r - 20) % 6 != 5], 0.04, 0.4)
+    line(7, [r for r in range(20, 110) if (r - 20) % 7 != 6], 0.04, 0.4)
     line(24, np.arange(150, 159), -0.01, -0.6)
     for sec in (4, 5, 6, 7, 24):
         rr = rng.integers(0, 159, 300)
@@ -343,7 +343,7 @@ def test_tracks_at_row_range_ends(dev, oracle_lib):
     ref = oracle_lib.run_event(ev, precision=32, replay=True)
     rows = sorted(zip(ref.tracks["n_hits"].tolist(), ref.tracks["row_in"].tolist(),
                       ref.tracks["row_out"].tolist()))
-    assert rows == [(10, 60, 69), (14, 145, 158), (15, 0, 14), (75, 20, 108)], rows
+    assert rows == [(10, 60, 69), (14, 145, 158), (15, 0, 14), (78, 20, 109)], rows
     from paper_1712_09416_amd import Tracker
     for mode in ("event", "sectors"):
         trk = Tracker(ev.geometry(), max_clusters=4096)
@@ -492,8 +492,9 @@ def short_segments_event(seed=20261204):
 
 
 def test_min_track_length_three_matches_oracle(dev, oracle_lib):
-    """n_min_track = n_min_tracklet = 3 (the smallest accepted): every track
-    region is sized for n / 3 tracks, so the fused, per-sector and
+    """n_min_track = n_min_tracklet = n_min_chain = 3 (the smallest
+    accepted): every tracklet and track region is sized for n / 3 entries,
+    so the fused, per-sector and
     multi-stream sequences stay inside their sectors' regions; links, hit
     lists and parameters identical to the oracle run with the same cuts.
     The replay bar is checked on the tracks of ten hits or more: below
@@ -503,7 +504,7 @@ def test_min_track_length_three_matches_oracle(dev, oracle_lib):
     moves between passes), which is the method's, not the GPU's."""
     from paper_1712_09416_amd import Tracker
     ev = tpcgen.pbpb_event(tpcgen.seed_for(2) + 93, 800)
-    cuts = dict(n_min_track=3, n_min_tracklet=3)
+    cuts = dict(n_min_track=3, n_min_tracklet=3, n_min_chain=3)
     ref = oracle_lib.run_event(ev, precision=32, replay=True, nthreads=ORACLE_THREADS,
                                params=oracle_lib.make_params(**cuts))
     short = int((ref.tracks["n_hits"] < 10).sum())
