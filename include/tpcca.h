@@ -213,6 +213,31 @@ int tpc_submit(tpc_ctx* ctx, int slot);
  * during graph capture), TPC_EDEVICE. */
 int tpc_track_event_streams(tpc_ctx* ctx, int slot, int n_streams);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): track one
+ * event as tpc_load_clusters(TPC_DEVICE) + tpc_track_event + tpc_get_tracks
+ * would, with no context and no caller workspace.  The workspace is a fixed
+ * 64 MiB array of device memory inside the library, one per GPU, held from
+ * the first call on that GPU until the process ends; the event must fit in
+ * it (about 150,000 clusters with the default params; TPC_ENOMEM beyond,
+ * before anything is enqueued).  No device memory is allocated or freed and
+ * no memset or copy node is enqueued: kernels only, on hip_stream
+ * (asynchronous).  g, p: host; p's max_slots / max_events / max_clusters are
+ * ignored (one event of n clusters).  sector, row, y, z: device arrays of n
+ * clusters (as tpc_load_clusters).  Outputs, device memory owned by the
+ * caller: tracks[max_tracks], hit_ids[max_hits] (the event's tracks in
+ * canonical order and their hit IDs; at most max_tracks / max_hits written)
+ * and status[4] = {tracks, hits, flags, 0} with flags bit 0 = invalid
+ * clusters, bit 1 = a pad row over 4096 clusters, bit 2 = internal capacity
+ * exceeded, bit 3 = tracks or hits beyond max_tracks / max_hits.  Calls on
+ * one GPU share its array: calls on one stream are ordered, calls that
+ * overlap on one GPU (other streams, or other threads) race and must not be
+ * made.  Errors (tpc_last_error(NULL)): TPC_EINVAL, TPC_ENOMEM, TPC_EDEVICE. */
+int tpc_track_event_noalloc(const tpc_geometry* g, const tpc_params* p, const uint8_t* sector,
+                            const uint8_t* row, const float* y, const float* z, int64_t n,
+                            tpc_track* tracks, int64_t max_tracks, int32_t* hit_ids,
+                            int64_t max_hits, uint32_t* status, void* hip_stream);
+
 /* Output of the tracker (Abstract: tracks of the TPC, fitted by the Kalman
  * filter).  Wait for the slot and copy the tracks of one event of it (event = 0 for
  * tpc_load_clusters) into caller host memory: out[max_tracks],

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <array>
 #include <vector>
@@ -1204,3 +1205,150 @@ int tpc_destroy(tpc_ctx* ctx) {
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// Allocation-free tracking of one event: the workspace is a fixed array of
+// device memory owned by the library (one per GPU, held until the process
+// ends), for callers that cannot allocate device memory.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+}  // namespace
+
+// In host code this name is only a stand-in for the device array: host code
+// takes the array's device address from hipGetSymbolAddress (once per GPU)
+// and passes that address, never this name.
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxStaticDevices = 64;
+struct StaticDevice {
+  uint8_t* ptr = nullptr;     // device address of `scratch` on this GPU
+  tpc_ctx* ctx = nullptr;     // host-side context over it (no device memory of its own)
+};
+StaticDevice g_static[kMaxStaticDevices];
+std::mutex g_static_mu;
+
+__global__ void k_static_stage(int64_t* ev_off, int64_t n) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ev_off[0] = 0;
+    ev_off[1] = n;
+  }
+}
+
+// Tracks and hit IDs of the slot's one event into the caller's arrays (at
+// most max_tracks / max_hits of them) and the status words.
+__global__ void k_static_out(Slot S, tpc_track* tracks, int64_t max_tracks, int32_t* hits,
+                             int64_t max_hits, uint32_t* status) {
+  constexpr int64_t kWords = (int64_t)(sizeof(tpc_track) / 4);
+  const int64_t nt = S.out_count[0], nh = S.out_count[1];
+  const int64_t words = (nt < max_tracks ? nt : max_tracks) * kWords;
+  const int64_t nhc = nh < max_hits ? nh : max_hits;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(S.out_tracks);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(tracks);
+  for (int64_t i = t0; i < words; i += stride) dst[i] = src[i];
+  for (int64_t i = t0; i < nhc; i += stride) hits[i] = S.out_hits[i];
+  if (t0 == 0) {
+    uint32_t flags = 0u;
+    if (S.err[0]) flags |= 1u;
+    if (S.err[1]) flags |= 2u;
+    if (S.err[2]) flags |= 4u;
+    if (nt > max_tracks || nh > max_hits) flags |= 8u;
+    status[0] = (uint32_t)nt;
+    status[1] = (uint32_t)nh;
+    status[2] = flags;
+    status[3] = 0u;
+  }
+}
+
+int static_fail(int code, const char* m) {
+  g_init_error = m;
+  return code;
+}
+
+}  // namespace
+
+extern "C" int tpc_track_event_noalloc(const tpc_geometry* g, const tpc_params* p,
+                                       const uint8_t* sector, const uint8_t* row, const float* y,
+                                       const float* z, int64_t n, tpc_track* tracks,
+                                       int64_t max_tracks, int32_t* hit_ids, int64_t max_hits,
+                                       uint32_t* status, void* hip_stream) {
+  g_init_error.clear();
+  if (!g || !p || !status) return static_fail(TPC_EINVAL, "null argument");
+  if (const char* bad = geometry_error(g)) return static_fail(TPC_EINVAL, bad);
+  if (n < 0 || n > ((int64_t)1 << 24)) return static_fail(TPC_EINVAL, "cluster count must be 0..2^24");
+  if (n > 0 && (!sector || !row || !y || !z)) return static_fail(TPC_EINVAL, "null cluster array");
+  if (max_tracks < 0 || max_hits < 0) return static_fail(TPC_EINVAL, "negative buffer size");
+  if ((max_tracks > 0 && !tracks) || (max_hits > 0 && !hit_ids))
+    return static_fail(TPC_EINVAL, "null output buffer");
+  tpc_params q = *p;
+  q.max_slots = 1;
+  q.max_events = 1;
+  q.max_clusters = std::max<int64_t>(n, 1);
+  if (!params_ok(&q)) return static_fail(TPC_EINVAL, "bad params");
+  if (tpc_workspace_bytes(&q) > kStaticScratchBytes)
+    return static_fail(TPC_ENOMEM, "event too large for the allocation-free entry (its 64 MiB "
+                                   "workspace holds about 150,000 clusters)");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxStaticDevices)
+    return static_fail(TPC_EDEVICE, "no usable current device");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticDevice& sd = g_static[dev];
+  if (!sd.ptr) {
+    // set-up, once per GPU, with that GPU current: the array's device address
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return static_fail(TPC_EDEVICE, "hipGetSymbolAddress of the workspace array failed");
+    }
+    sd.ptr = static_cast<uint8_t*>(ptr);
+    sd.ctx = new tpc_ctx();
+    sd.ctx->slots.resize(1);
+    sd.ctx->slots[0].ev_off.reserve(2);
+  }
+  tpc_ctx* ctx = sd.ctx;
+  ctx->p = q;
+  ctx->g = *g;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  ctx->ws = sd.ptr;
+  ctx->ws_bytes = kStaticScratchBytes;
+  fill_constants(ctx->k, g, &q);
+  SlotHost& h = ctx->slots[0];
+  Carver c{sd.ptr, 0, false};
+  carve_slot(c, q, h.d, &h);
+  carve_lanes(c, q, ctx->lanes);
+  Slot& s = h.d;
+  h.n = n;
+  h.n_events = 1;
+  h.merged = false;
+  h.sec_n.clear();
+  h.ev_off.resize(2);
+  h.ev_off[0] = 0;
+  h.ev_off[1] = n;
+  s.n = n;
+  s.n_events = 1;
+  s.n_sectors = kSectorsPerEvent;
+  s.sector = sector;
+  s.row = row;
+  s.y = y;
+  s.z = z;
+  hipStream_t st = ctx->stream;
+  k_static_stage<<<1, 64, 0, st>>>(s.ev_off, n);
+  h.state = 1;
+  int rc = build_grid(ctx, h);
+  if (rc == TPC_OK) rc = track_range(ctx, h, 0, s.n_sectors);
+  if (rc == TPC_OK) rc = finalize(ctx, h);
+  if (rc != TPC_OK) {
+    g_init_error = ctx->err;
+    return rc;
+  }
+  const int64_t work = std::max<int64_t>(max_tracks * (int64_t)(sizeof(tpc_track) / 4), max_hits);
+  k_static_out<<<grid_stride_blocks(work, 256, 1024), 256, 0, st>>>(s, tracks, max_tracks, hit_ids,
+                                                                    max_hits, status);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return static_fail(TPC_EDEVICE, hipGetErrorString(e));
+  return TPC_OK;
+}

@@ -222,6 +222,29 @@ def test_tracklet_regions_sized_for_n_min_chain(L):
         assert L.tpc_workspace_bytes(ctypes.byref(default_params(n_min_chain=bad))) == 0, bad
 
 
+def test_noalloc_checks_before_device_work(L):
+    """The allocation-free entry refuses, before any device call, a missing
+    status array, an event too large for its fixed workspace and bad
+    params (an event of 400,000 clusters needs ~170 MB of workspace)."""
+    g = make_geometry(tpcgen.geometry.geometry_dict())
+    p = default_params()
+    a = np.zeros(16, np.uint32)
+    ptr = a.ctypes.data
+    big = 400_000
+    args = (ptr, ptr, ptr, ptr, big, ptr, 4, ptr, 4)
+    assert L.tpc_track_event_noalloc(ctypes.byref(g), ctypes.byref(p), *args, None, None) == \
+        _lib.TPC_EINVAL
+    assert L.tpc_track_event_noalloc(ctypes.byref(g), ctypes.byref(p), *args, ptr, None) == \
+        _lib.TPC_ENOMEM
+    assert b"allocation-free" in L.tpc_last_error(None)
+    bad = default_params(n_min_chain=2)
+    small = (ptr, ptr, ptr, ptr, 10, ptr, 4, ptr, 4)
+    assert L.tpc_track_event_noalloc(ctypes.byref(g), ctypes.byref(bad), *small, ptr, None) == \
+        _lib.TPC_EINVAL
+    assert L.tpc_track_event_noalloc(ctypes.byref(g), ctypes.byref(p), ptr, ptr, ptr, ptr, -1,
+                                     ptr, 4, ptr, 4, ptr, None) == _lib.TPC_EINVAL
+
+
 def test_batch_event_limit(L):
     ctx, p = _ctx(L, max_events=4)
     a = np.zeros(10, np.uint8)
