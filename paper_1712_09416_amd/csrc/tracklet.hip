@@ -148,8 +148,11 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
         const int32_t bh = search_row(S, K, rb, st, vy, vz, examined, xg);
         if (bh >= 0 && try_hit(K, st, xg, vy, vz, tries)) got = bh;
       }
-      hits[r] = got;
       if (got >= 0) {
+        // the rows missed since the last hit get their -1 now; rows after
+        // the outermost hit are never read, so they are not written
+        for (int m = 1; m <= miss; ++m) hits[r - m] = -1;
+        hits[r] = got;
         next = xg.upc;
         miss = 0;
         last = st;
@@ -206,14 +209,20 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
         const int32_t bh = search_row(S, K, rb, st, vy, vz, examined, xs);
         if (bh >= 0 && try_hit(K, st, xs, vy, vz, tries)) got = bh;
       }
-      hits[r] = got;
+      // the list keeps the outward decisions of rows r0..rout; a row is
+      // written only where the inward decision differs, and rows below r0
+      // (never written) get their misses when the next hit below is found
       if (got >= 0) {
+        for (int m = 1; m <= miss; ++m)
+          if (r + m < r0) hits[r + m] = -1;
+        if (r < r0 || got != uh) hits[r] = got;
         ++n;
         miss = 0;
         last = st;
         rin = r;
-      } else if (++miss >= K.n_gap) {
-        break;
+      } else {
+        if (uh >= 0) hits[r] = -1;   // the outward hit of this row was dropped
+        if (++miss >= K.n_gap) break;
       }
     }
     tl_hits += (unsigned)n;
