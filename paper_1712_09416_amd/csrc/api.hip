@@ -146,6 +146,7 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   s.bin_off = c.take<uint32_t>(kBinsPerHit * (N + SR) + SR + 1);
   s.rank = c.take<uint32_t>(N);
   s.hit = c.take<Hit>(N);
+  s.hit_sr = c.take<uint32_t>(N);
   s.up = c.take<int32_t>(N);
   s.dn = c.take<int32_t>(N);
   s.dnc = c.take<int32_t>(N);
@@ -478,8 +479,9 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
   const int64_t tl_bound = std::min<int64_t>(s.cap_tl, n_range / ctx->p.n_min_chain + ns);
   const int nb_lane = std::max(8, grid_stride_blocks(tl_bound, 64, 16384) / 8 * 8);
   const int nb_sel = grid_stride_blocks(tl_bound, 256, 4096);
-  k_nf_split<<<1, 64, 0, st>>>(s, g0, ns);
-  k_neighbours<<<((ns * kRows + 7) / 8) * 8, 256, 0, st>>>(s, ctx->k, g0);
+  // a lane per hit of the range (the grid from the host bound; the kernel
+  // strides over the device count)
+  k_neighbours<<<grid_stride_blocks(n_range, 256, 65536) / 8 * 8 + 8, 256, 0, st>>>(s, ctx->k, g0, ns);
   if (marks) mark(ctx, 2);
   // a wave per pad row
   const int nb_rows = grid_stride_blocks((int64_t)ns * kRows * 64, 256, 16384);

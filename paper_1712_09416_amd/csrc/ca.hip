@@ -50,20 +50,18 @@ constexpr int kNfCand = 32;      // up-row candidates listed per hit before a ne
 // are read through the caches with the batched window reads (measured
 // faster than staging the rows in LDS, and than holding the candidates in
 // registers, whose fixed-length pairing loop costs more than it saves).
-// This function: the hits of pad row `row` of sector g, `my` the thread's
-// candidate slots in LDS.
-__device__ __forceinline__ void nf_row(const Slot& S, const DevConst& K, int g, int row,
-                                       uint32_t* my) {
-  const int sr = g * kRows + row;
-  const uint32_t h0 = S.row_off[sr], h1 = S.row_off[sr + 1];
+// This function: sorted hit h, `my` the thread's candidate slots in LDS.
+__device__ __forceinline__ void nf_hit(const Slot& S, const DevConst& K, uint32_t h, uint32_t* my) {
+  const int sr = (int)S.hit_sr[h];
+  const int g = sr / kRows;
+  const int row = sr - g * kRows;
   if (row == 0 || row == kRows - 1) {
-    for (uint32_t h = h0 + threadIdx.x; h < h1; h += blockDim.x) {
-      S.up[h] = -1;
-      S.dn[h] = -1;
-    }
+    S.up[h] = -1;
+    S.dn[h] = -1;
     return;
   }
   const RowBins Bd = S.bins[sr - 1], Bu = S.bins[sr + 1];
+  const Hit x = S.hit[h];
   const uint32_t* bod = S.bin_off + Bd.base;
   const uint32_t* bou = S.bin_off + Bu.base;
   const float xr = K.row_x[row];
@@ -71,79 +69,68 @@ __device__ __forceinline__ void nf_row(const Slot& S, const DevConst& K, int g, 
   const float rho_u = K.row_x[row + 1] / xr;
   const float f = (xr - K.row_x[row - 1]) / (K.row_x[row + 1] - K.row_x[row - 1]);
   const float W = K.nf_w;
-  for (uint32_t h = h0 + threadIdx.x; h < h1; h += blockDim.x) {
-    const Hit x = S.hit[h];
-    const float yh = x.y, zh = x.z;
-    const float ypu = yh * rho_u, zpu = zh * rho_u;
-    const float ypd = yh * rho_d, zpd = zh * rho_d;
-    int nu = 0;
-    for_window_hits(Bu, bou, S.hit, ypu, zpu, W, W, [&](uint32_t u, const Hit& c) {
-      if (!(fabsf(c.y - ypu) <= W && fabsf(c.z - zpu) <= W)) return;
-      if (nu < kNfCand) my[nu * kNfThreads] = u;
-      ++nu;
-    });
-    PairBest best;
-    if (nu > 0) {
-      const float sy = sigma_y(K, zh), sz = sigma_z(K, zh);
-      const float wy = 1.0f / (1.5f * (sy * sy));
-      const float wz = 1.0f / (1.5f * (sz * sz));
-      for_window_hits(Bd, bod, S.hit, ypd, zpd, W, W, [&](uint32_t d, const Hit& xd) {
-        if (!(fabsf(xd.y - ypd) <= W && fabsf(xd.z - zpd) <= W)) return;
-        if (nu <= kNfCand) {
-          for (int k = 0; k < nu; ++k) {
-            const uint32_t u = my[k * kNfThreads];
-            const Hit xu = S.hit[u];
-            best.offer(nf_metric(xd.y, xd.z, xu.y, xu.z, yh, zh, f, wy, wz), xd.id, xu.id,
-                       (int32_t)d, (int32_t)u);
-          }
-        } else {
-          for_window_hits(Bu, bou, S.hit, ypu, zpu, W, W, [&](uint32_t u, const Hit& c) {
-            if (!(fabsf(c.y - ypu) <= W && fabsf(c.z - zpu) <= W)) return;
-            best.offer(nf_metric(xd.y, xd.z, c.y, c.z, yh, zh, f, wy, wz), xd.id, c.id,
-                       (int32_t)d, (int32_t)u);
-          });
+  const float yh = x.y, zh = x.z;
+  const float ypu = yh * rho_u, zpu = zh * rho_u;
+  const float ypd = yh * rho_d, zpd = zh * rho_d;
+  int nu = 0;
+  for_window_hits(Bu, bou, S.hit, ypu, zpu, W, W, [&](uint32_t u, const Hit& c) {
+    if (!(fabsf(c.y - ypu) <= W && fabsf(c.z - zpu) <= W)) return;
+    if (nu < kNfCand) my[nu * kNfThreads] = u;
+    ++nu;
+  });
+  PairBest best;
+  if (nu > 0) {
+    const float sy = sigma_y(K, zh), sz = sigma_z(K, zh);
+    const float wy = 1.0f / (1.5f * (sy * sy));
+    const float wz = 1.0f / (1.5f * (sz * sz));
+    for_window_hits(Bd, bod, S.hit, ypd, zpd, W, W, [&](uint32_t d, const Hit& xd) {
+      if (!(fabsf(xd.y - ypd) <= W && fabsf(xd.z - zpd) <= W)) return;
+      if (nu <= kNfCand) {
+        // the listed up hits, four records per memory round trip
+        for (int k0 = 0; k0 < nu; k0 += 4) {
+          uint32_t uu[4];
+          Hit xu[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (k0 + v < nu) {
+              uu[v] = my[(k0 + v) * kNfThreads];
+              xu[v] = S.hit[uu[v]];
+            }
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (k0 + v < nu)
+              best.offer(nf_metric(xd.y, xd.z, xu[v].y, xu[v].z, yh, zh, f, wy, wz), xd.id,
+                         xu[v].id, (int32_t)d, (int32_t)uu[v]);
         }
-      });
-    }
-    const bool ok = best.have && best.m <= K.nf_mmax;
-    S.up[h] = ok ? best.u : -1;
-    S.dn[h] = ok ? best.d : -1;
+      } else {
+        for_window_hits(Bu, bou, S.hit, ypu, zpu, W, W, [&](uint32_t u, const Hit& c) {
+          if (!(fabsf(c.y - ypu) <= W && fabsf(c.z - zpu) <= W)) return;
+          best.offer(nf_metric(xd.y, xd.z, c.y, c.z, yh, zh, f, wy, wz), xd.id, c.id,
+                     (int32_t)d, (int32_t)u);
+        });
+      }
+    });
   }
+  const bool ok = best.have && best.m <= K.nf_mmax;
+  S.up[h] = ok ? best.u : -1;
+  S.dn[h] = ok ? best.d : -1;
 }
 
-// Split of the launched rows over the 8 XCDs, balanced by hits: XCD x takes
-// the rows [split[x], split[x+1]) (indices from the range's first row), those
-// whose first hit lies in the x-th eighth of the range's hits.  Stored in
-// range_cnt[4 .. 12].
-__global__ void k_nf_split(Slot S, int g0, int ns) {
-  const int x = threadIdx.x;
-  if (x > 8) return;
-  const uint32_t* ro = S.row_off + (size_t)g0 * kRows;
-  const int nr = ns * kRows;
-  int v = x == 0 ? 0 : nr;
-  if (x > 0 && x < 8) {
-    const uint64_t hits = ro[nr] - ro[0];
-    const uint32_t target = ro[0] + (uint32_t)(hits * (uint64_t)x / 8u);
-    int lo = 0, hi = nr;            // first row whose first hit is at or after target
-    while (lo < hi) {
-      const int mid = (lo + hi) / 2;
-      if (ro[mid] < target) lo = mid + 1; else hi = mid;
-    }
-    v = lo;
-  }
-  S.range_cnt[4 + x] = (uint32_t)v;
-}
-
-// Blocks are dealt round-robin over the 8 XCDs; the blocks of XCD x stride
-// over its contiguous stretch of rows (k_nf_split), so the rows r-1, r+1
-// that neighbouring blocks read stay in its L2 and every XCD gets the same
-// number of hits however different the sectors' sizes are.
-__global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, int g0) {
+// The hits of sectors [g0, g0 + ns) as one flat sequence (lane per hit, so
+// every wave is full whatever the rows' sizes): blocks are dealt
+// round-robin over the 8 XCDs, and the blocks of XCD x stride over the x-th
+// contiguous eighth of the hits, so the rows r-1, r+1 its lanes read stay
+// in its L2.
+__global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, int g0, int ns) {
   __shared__ uint32_t cand[kNfCand * kNfThreads];
-  const int x = (int)(blockIdx.x % 8), nbx = (int)(gridDim.x / 8);
-  const int v1 = (int)S.range_cnt[5 + x];
-  for (int v = (int)S.range_cnt[4 + x] + (int)(blockIdx.x / 8); v < v1; v += nbx)
-    nf_row(S, K, g0 + v / kRows, v % kRows, cand + threadIdx.x);
+  const uint32_t h_begin = S.row_off[g0 * kRows];
+  const uint32_t h_end = S.row_off[(g0 + ns) * kRows];
+  const uint32_t x = blockIdx.x % 8u, nbx = gridDim.x / 8u;
+  const uint32_t per = (h_end - h_begin + 7u) / 8u;
+  const uint32_t c0 = h_begin + x * per;
+  const uint32_t c1 = min(h_end, c0 + per);
+  for (uint32_t h = c0 + (blockIdx.x / 8u) * kNfThreads + threadIdx.x; h < c1; h += nbx * kNfThreads)
+    nf_hit(S, K, h, cand + threadIdx.x);
 }
 
 // Head of a cleaned chain of >= n_min_chain hits (no cleaned down link; the

@@ -225,8 +225,8 @@ __global__ void k_scatter(Slot S) {
 
 // a2: one block per (sector, row): order the row's hits by (bin, cluster
 // index) — counting sort by bin in LDS, then an insertion sort by index
-// inside each bin (bins hold a hit or two) — write them as Hit records and fill
-// the row's bin offsets.  CAP is the largest row the instance handles; the
+// inside each bin (bins hold a hit or two) — write them as Hit records with
+// their (sector, row) beside them, and fill the row's bin offsets.  CAP is the largest row the instance handles; the
 // instance for rows up to kMaxRowHits also handles the over-full rows.
 template <int CAP>
 __device__ __forceinline__ void row_sort(Slot& S, int sr, uint32_t skip_upto, bool small) {
@@ -257,6 +257,7 @@ __device__ __forceinline__ void row_sort(Slot& S, int sr, uint32_t skip_upto, bo
       h.id = S.hit[off + j].id;
       h.upc = -1;
       S.hit[off + j] = h;
+      S.hit_sr[off + j] = (uint32_t)sr;
     }
     for (int bb = threadIdx.x; bb <= nb; bb += blockDim.x) S.bin_off[b.base + bb] = off;
     return;
@@ -322,6 +323,7 @@ __device__ __forceinline__ void row_sort(Slot& S, int sr, uint32_t skip_upto, bo
     h.id = lid[src];
     h.upc = -1;
     S.hit[off + j] = h;
+    S.hit_sr[off + j] = (uint32_t)sr;
   }
   for (int bb = threadIdx.x; bb <= nb; bb += blockDim.x) S.bin_off[b.base + bb] = off + hist[bb];
 }

@@ -83,6 +83,7 @@ struct Slot {
   uint32_t* bin_off;        // [2 (n + SR) + SR + 1] per row: its bins' first hits, then the end
   uint32_t* rank;           // [n]
   Hit* hit;                 // [n] sorted by (sector, row, bin, id)
+  uint32_t* hit_sr;         // [n] (sector, row) of each sorted hit (slot-wide index)
   // links (sorted-hit indices, -1 none); the cleaned up-link lives in hit[].upc
   int32_t* up;
   int32_t* dn;
@@ -91,8 +92,7 @@ struct Slot {
   uint32_t* tl_base;        // [S+1] tracklet region of each sector
   uint32_t* tk_base;        // [S+1] track region of each sector
   uint32_t* row_nstart;     // [SR+1] start hits per row, then their offsets
-  uint32_t* range_cnt;      // [16]: tracklets, tracks of the launched range; rows > 1024 hits;
-                            // [4..12] the neighbours finder's split of the rows over the XCDs
+  uint32_t* range_cnt;      // [16]: tracklets, tracks of the launched range; rows > 1024 hits
   uint32_t* big_rows;       // [n / 1024 + 1] (sector, row) of the rows over 1024 hits
   int32_t* start_hit;       // [tl capacity] sorted index of the start hit
   int32_t* start_sr;        // [tl capacity] (sector, row) of the start hit

@@ -14,8 +14,7 @@ __global__ void k_row_sort_tiny(Slot S);
 __global__ void k_row_sort_small(Slot S);
 __global__ void k_row_sort_large(Slot S);
 // cellular automaton
-__global__ void k_nf_split(Slot S, int g0, int ns);
-__global__ void k_neighbours(Slot S, DevConst K, int g0);
+__global__ void k_neighbours(Slot S, DevConst K, int g0, int ns);
 __global__ void k_clean_rows(Slot S, int g0, int ns, int n_min_chain);
 __global__ void k_start_write(Slot S, int g0, int ns, int n_min_chain);
 // Kalman filter
