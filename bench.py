@@ -152,12 +152,11 @@ def bench_batch(evs, geo, dev, steps: int) -> dict:
     total = int(offs[-1])
     cat = [torch.from_numpy(np.concatenate([getattr(e, k) for e in evs])).to(dev)
            for k in ("sector", "row", "y", "z")]
-    # grid knobs tuned on this batch (the tuner checks the tracks do not change)
+    # launch shape tuned on this batch (the tuner checks the tracks do not change)
     from paper_1712_09416_amd.autotune import autotune
     tune = autotune(geo, offs, *cat, reps=3)
-    bt, be = tune["best"]
     print(f"bench: batch autotune {tune}", file=sys.stderr, flush=True)
-    trk = Tracker(geo, max_events=len(evs), max_clusters=total, bin_target=bt, bin_min_edge=be)
+    trk = Tracker(geo, max_events=len(evs), max_clusters=total, **tune["best"])
     st = trk.stream
 
     def timed(fn, reps):
@@ -207,8 +206,7 @@ def bench_batch(evs, geo, dev, steps: int) -> dict:
             "one_launch_per_step_ms": ms_eager, "one_launch_per_step_clusters_per_s": rate(ms_eager),
             "per_event_ms": ms_events, "per_event_clusters_per_s": rate(ms_events),
             "plain_ms": ms_plain, "plain_clusters_per_s": rate(ms_plain),
-            "autotune": {"best": {"bin_target": bt, "bin_min_edge": be},
-                         "graph_ms": {f"{t:g}/{e:g}": v for (t, e), v in tune["ms"].items()}}}
+            "autotune": {"best": tune["best"], "graph_ms": tune["ms"]}}
 
 
 def bench_serve(pool, geo, n_req: int) -> dict:
@@ -232,19 +230,31 @@ def bench_serve(pool, geo, n_req: int) -> dict:
         picks.append(kinds[k][counters[k] % len(kinds[k])])
         counters[k] += 1
     cap = max(e.n for e in evs) + 1024
+    # launch shape tuned on a continuous-batching slot of the mix: the first
+    # 8 requests of the stream in one slot
+    import torch
+    from paper_1712_09416_amd.autotune import autotune
+    slot = picks[:8]
+    offs = np.concatenate([[0], np.cumsum([e.n for e in slot])]).astype(np.int64)
+    cat = [torch.from_numpy(np.concatenate([getattr(e, k) for e in slot])).cuda()
+           for k in ("sector", "row", "y", "z")]
+    tune = autotune(geo, offs, *cat, reps=5)
+    shape = tune["best"]
+    del cat
+    print(f"bench: serving-mix autotune {tune}", file=sys.stderr, flush=True)
 
     def requests(times):
         return [Request(float(t), e.sector, e.row, e.y, e.z, tag=e.name) for t, e in zip(times, picks)]
 
     def capacity(plain):
-        srv = Server(geo, n_streams=4, max_events=8, cap_clusters=cap, plain=plain)
+        srv = Server(geo, n_streams=4, max_events=8, cap_clusters=cap, plain=plain, **shape)
         srv.run(requests(np.zeros(len(picks[:40])))[:40])          # warm-up
         st = srv.run(requests(np.zeros(len(picks))))
         srv.close()
         return st.n_requests / st.wall_s
 
     def serve(plain, rate):
-        srv = Server(geo, n_streams=4, max_events=8, cap_clusters=cap, plain=plain)
+        srv = Server(geo, n_streams=4, max_events=8, cap_clusters=cap, plain=plain, **shape)
         srv.run(requests(np.zeros(40))[:40])
         st = srv.run(requests(poisson_arrivals(len(picks), rate, seed=7)), warmup=warm)
         srv.close()
@@ -262,7 +272,7 @@ def bench_serve(pool, geo, n_req: int) -> dict:
         rq = [Request(float(t), e.sector, e.row, e.y, dist[id(e)], tag=e.name)
               for t, e in zip(times, picks)]
         cal = DriftCalibration(250.0, every=50) if with_calib else None
-        srv = Server(geo, n_streams=4, max_events=8, cap_clusters=cap, calib=cal)
+        srv = Server(geo, n_streams=4, max_events=8, cap_clusters=cap, calib=cal, **shape)
         srv.run(rq[:40])
         st = srv.run(rq, warmup=warm)
         srv.close()
@@ -295,6 +305,7 @@ def bench_serve(pool, geo, n_req: int) -> dict:
     print(f"bench: serve batching capacity {c_cb:.1f} events/s", file=sys.stderr, flush=True)
     r1 = 0.7 * c_plain
     return {"mix": "70% pp / 25% peripheral (2000 primaries) / 5% central, pool of 34 distinct events",
+            "autotune": {"slot": "first 8 requests of the stream", "best": shape, "graph_ms": tune["ms"]},
             "capacity_events_per_s": {"plain": c_plain, "continuous_batching": c_cb},
             "at_0.7_plain_capacity": {"rate_events_per_s": r1, "plain": serve(True, r1),
                                       "continuous_batching": serve(False, r1)},
@@ -403,7 +414,12 @@ def main() -> int:
     ev = Ev(central)
     print(f"bench: central event {ev.n} clusters", file=sys.stderr, flush=True)
     ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.sector, ev.row, ev.y, ev.z)]
-    trk = Tracker(ev.geometry(), max_clusters=ev.n)
+    # the launch shape tuned on this event (graph replays; the tuner checks
+    # that the tracks do not change)
+    from paper_1712_09416_amd.autotune import autotune
+    tune_c = autotune(ev.geometry(), np.array([0, ev.n], np.int64), *ins, reps=5)
+    print(f"bench: central autotune {tune_c}", file=sys.stderr, flush=True)
+    trk = Tracker(ev.geometry(), max_clusters=ev.n, **tune_c["best"])
     torch.cuda.synchronize()
 
     def step():
@@ -546,6 +562,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"central Pb-Pb-shaped event, 36 sectors x 159 rows, {ev.n} clusters",
                    "mode": "fused (one launch per step over all sectors)",
+                   "launch_shape": tune_c["best"],
                    "refit": "f64", "seed": tpcgen.seed_for(2)},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
@@ -560,6 +577,7 @@ def main() -> int:
                         "p99_ms": float(np.percentile(e2e, 99)),
                         "clusters_per_s": ev.n / (float(np.mean(e2e)) * 1e-3)} if e2e else None),
         "roofline": roof,
+        "autotune": {"central": {"best": tune_c["best"], "graph_ms": tune_c["ms"]}},
     }
     trk.close()
     print(f"bench: central {ms_per_step:.3f} ms/step, stages {stage_ms}", file=sys.stderr, flush=True)

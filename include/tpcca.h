@@ -92,6 +92,10 @@ typedef struct tpc_params {
                                noise of every transport (0: no scattering) */
   float ms_mass;            /* particle mass of the scattering law (GeV) */
   int32_t n_min_chain;      /* hits of a cleaned chain that starts a tracklet (3..159) */
+  /* launch shape (tuning only: the tracks never depend on these) */
+  int32_t tl_block;         /* tracklet kernel threads per block: 64, 128 or 256 */
+  int32_t win_batch;        /* window hits read per memory round trip: 2, 4 or 8 */
+  int32_t row_batch;        /* hit-list rows read per round trip by the selection: 4, 8 or 16 */
 } tpc_params;
 
 /* One output track.  par / cov are given at x_ref, the pad-row radius of

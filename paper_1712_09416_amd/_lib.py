@@ -47,7 +47,8 @@ class Params(ctypes.Structure):
                 ("bin_min_edge", ctypes.c_float), ("max_slots", ctypes.c_int32),
                 ("max_events", ctypes.c_int32), ("max_clusters", ctypes.c_int64),
                 ("x0_cm", ctypes.c_float), ("ms_mass", ctypes.c_float),
-                ("n_min_chain", ctypes.c_int32)]
+                ("n_min_chain", ctypes.c_int32), ("tl_block", ctypes.c_int32),
+                ("win_batch", ctypes.c_int32), ("row_batch", ctypes.c_int32)]
 
 
 class MergeParams(ctypes.Structure):

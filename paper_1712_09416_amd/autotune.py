@@ -1,21 +1,31 @@
-"""Autotuner for the grid knobs of a batched slot.
+"""Autotuner for the launch shape of a batched slot.
 
-The pad-row grid's bin size (clusters per bin aimed at, smallest bin edge)
+The knobs change how the work is laid out, never what is computed: the
+pad-row grid's bin size (clusters per bin aimed at, smallest bin edge)
 changes how many hits each window query touches, never which hits pass the
-exact window test, so the tracks do not depend on it.  For a given batch the
-tuner times graph replays of every candidate, checks that each candidate's
-tracks are identical to the first one's, and returns the fastest setting.
+exact window test; the tracklet kernel's block size, the window hits read
+per memory round trip and the hit-list rows read per round trip by the
+selection change only the order of loads and lanes.  So the tracks do not
+depend on them: for a given batch the tuner times graph replays of each
+candidate, checks that its tracks are identical to the first candidate's,
+and keeps the fastest, one group of knobs at a time (coordinate descent).
 """
 from __future__ import annotations
 
 import hashlib
+import itertools
 
 import numpy as np
 import torch
 
 from .tracker import Tracker
 
-DEFAULT_CANDIDATES = [(t, e) for t in (0.25, 0.5, 1.0) for e in (1.0, 2.0, 3.0)]
+KNOBS = {"bin_target": (0.25, 0.5, 1.0), "bin_min_edge": (1.0, 2.0, 3.0),
+         "tl_block": (64, 128, 256), "win_batch": (2, 4, 8), "row_batch": (4, 8, 16)}
+DEFAULTS = {"bin_target": 0.25, "bin_min_edge": 1.0, "tl_block": 64, "win_batch": 4,
+            "row_batch": 8}
+# groups tuned together, in this order
+GROUPS = (("bin_target", "bin_min_edge"), ("tl_block",), ("win_batch",), ("row_batch",))
 
 
 def _digest(trk: Tracker, n_events: int) -> str:
@@ -27,38 +37,57 @@ def _digest(trk: Tracker, n_events: int) -> str:
     return h.hexdigest()
 
 
-def autotune(geometry: dict, offsets, sector, row, y, z, candidates=None, reps: int = 5,
-             **params) -> dict:
-    """Time the batch (device tensors, event offsets) under each (bin_target,
-    bin_min_edge) candidate.  Returns {"best": (t, e), "ms": {...}}; raises if
-    any candidate's tracks differ."""
-    candidates = list(candidates or DEFAULT_CANDIDATES)
+def _label(cand: dict) -> str:
+    return ",".join(f"{k}={cand[k]:g}" for k in KNOBS)
+
+
+def autotune(geometry: dict, offsets, sector, row, y, z, reps: int = 5, groups=GROUPS,
+             knobs=None, **params) -> dict:
+    """Tune the launch shape for the batch given as device tensors and event
+    offsets.  knobs: candidate values per knob (default KNOBS).  Returns
+    {"best": {knob: value}, "ms": {label: ms per replay}}; raises if any
+    candidate's tracks differ from the first one's."""
+    knobs = dict(KNOBS, **(knobs or {}))
     offs = np.ascontiguousarray(offsets, np.int64)
     n_events = len(offs) - 1
     total = int(offs[-1])
     ms, ref = {}, None
-    for cand in candidates:
-        trk = Tracker(geometry, max_events=n_events, max_clusters=total,
-                      bin_target=float(cand[0]), bin_min_edge=float(cand[1]), **params)
-        trk.load_batch(0, offs, sector, row, y, z)
-        trk.capture(0)
-        trk.launch(0)
-        dig = _digest(trk, n_events)
-        if ref is None:
-            ref = dig
-        elif dig != ref:
-            trk.close()
-            raise RuntimeError(f"tracks changed with grid setting {cand}")
-        st = trk.stream
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(st)
-        for _ in range(reps):
+
+    def run(cand):
+        nonlocal ref
+        label = _label(cand)
+        if label in ms:
+            return ms[label]
+        trk = Tracker(geometry, max_events=n_events, max_clusters=total, **cand, **params)
+        try:
+            trk.load_batch(0, offs, sector, row, y, z)
+            trk.capture(0)
             trk.launch(0)
-        e1.record(st)
-        torch.cuda.synchronize()
-        ms[cand] = e0.elapsed_time(e1) / reps
-        trk.close()
-        del trk
-    best = min(ms, key=ms.get)
-    return {"best": best, "ms": ms}
+            dig = _digest(trk, n_events)
+            if ref is None:
+                ref = dig
+            elif dig != ref:
+                raise RuntimeError(f"tracks changed with launch shape {label}")
+            st = trk.stream
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(st)
+            for _ in range(reps):
+                trk.launch(0)
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms[label] = e0.elapsed_time(e1) / reps
+        finally:
+            trk.close()
+            del trk
+        return ms[label]
+
+    best = dict(DEFAULTS)
+    for group in groups:
+        timed = {}
+        for vals in itertools.product(*(knobs[k] for k in group)):
+            cand = dict(best)
+            cand.update(zip(group, vals))
+            timed[vals] = run(cand)
+        best.update(zip(group, min(timed, key=timed.get)))
+    return {"best": best, "ms": ms, "best_ms": ms[_label(best)]}

@@ -260,6 +260,9 @@ bool params_ok(const tpc_params* p) {
   if (!(p->max_clusters >= 1 && p->max_clusters <= (int64_t)0x7FFFFFFF)) return false;
   if (!(p->n_gap >= 1 && p->n_min_tracklet >= 2 && p->n_min_track >= 3)) return false;
   if (!(p->n_min_chain >= 3 && p->n_min_chain <= kRows)) return false;
+  if (!(p->tl_block == 64 || p->tl_block == 128 || p->tl_block == 256)) return false;
+  if (!(p->win_batch == 2 || p->win_batch == 4 || p->win_batch == 8)) return false;
+  if (!(p->row_batch == 4 || p->row_batch == 8 || p->row_batch == 16)) return false;
   if (!(p->s_max > 0.0f && p->s_max < 1.0f && p->chi2_max > 0.0f)) return false;
   if (!(p->nf_window > 0.0f && p->k_win > 0.0f && p->w_max > 0.0f)) return false;
   if (!(p->c_s0 > 0.0f && p->c_t0 > 0.0f && p->c_q0 > 0.0f)) return false;
@@ -477,11 +480,14 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
   // counts live on the device; every kernel strides over them)
   const int64_t n_range = range_clusters(h, g0, ns);
   const int64_t tl_bound = std::min<int64_t>(s.cap_tl, n_range / ctx->p.n_min_chain + ns);
-  const int nb_lane = std::max(8, grid_stride_blocks(tl_bound, 64, 16384) / 8 * 8);
+  const int tl_block = ctx->p.tl_block;
+  const int nb_lane =
+      std::max(8, grid_stride_blocks(tl_bound, tl_block, 16384 * 64 / tl_block) / 8 * 8);
   const int nb_sel = grid_stride_blocks(tl_bound, 256, 4096);
   // a lane per hit of the range (the grid from the host bound; the kernel
   // strides over the device count)
-  k_neighbours<<<grid_stride_blocks(n_range, 256, 65536) / 8 * 8 + 8, 256, 0, st>>>(s, ctx->k, g0, ns);
+  launch_neighbours(ctx->p.win_batch, grid_stride_blocks(n_range, 256, 65536) / 8 * 8 + 8, st, s,
+                    ctx->k, g0, ns);
   if (marks) mark(ctx, 2);
   // a wave per pad row
   const int nb_rows = grid_stride_blocks((int64_t)ns * kRows * 64, 256, 16384);
@@ -490,11 +496,11 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
            s.range_cnt + 0, false);
   k_start_write<<<nb_rows, 256, 0, st>>>(s, g0, ns, ctx->p.n_min_chain);
   if (marks) mark(ctx, 3);
-  k_tracklets<<<nb_lane, 64, 0, st>>>(s, ctx->k, g0);
+  launch_tracklets(ctx->p.win_batch, nb_lane, ctx->p.tl_block, st, s, ctx->k, g0);
   if (marks) mark(ctx, 4);
-  k_select<<<nb_sel, 256, 0, st>>>(s, ctx->k, g0);
+  launch_select(ctx->p.row_batch, nb_sel, st, s, ctx->k, g0);
   scan_u32(st, s.tl_sel, s.range_cnt + 0, tl_bound, s.scan_b, s.range_cnt + 1, false);
-  k_track_write<<<nb_sel, 256, 0, st>>>(s, g0, ns);
+  launch_track_write(ctx->p.row_batch, nb_sel, st, s, g0, ns);
   if (marks) mark(ctx, 5);
   // four waves per block: a block's waves go to the four SIMDs of one CU,
   // so the few hundred working waves of an event do not share SIMDs
@@ -600,6 +606,9 @@ int tpc_params_default(tpc_params* p) {
   p->x0_cm = 0.0f;
   p->ms_mass = 0.13957f;
   p->n_min_chain = 4;
+  p->tl_block = 64;
+  p->win_batch = 4;
+  p->row_batch = 8;
   return TPC_OK;
 }
 

@@ -50,7 +50,9 @@ constexpr int kNfCand = 32;      // up-row candidates listed per hit before a ne
 // are read through the caches with the batched window reads (measured
 // faster than staging the rows in LDS, and than holding the candidates in
 // registers, whose fixed-length pairing loop costs more than it saves).
-// This function: sorted hit h, `my` the thread's candidate slots in LDS.
+// This function: sorted hit h, `my` the thread's candidate slots in LDS;
+// WB hit records are read per memory round trip (a tuning knob).
+template <int WB>
 __device__ __forceinline__ void nf_hit(const Slot& S, const DevConst& K, uint32_t h, uint32_t* my) {
   const int sr = (int)S.hit_sr[h];
   const int g = sr / kRows;
@@ -73,7 +75,7 @@ __device__ __forceinline__ void nf_hit(const Slot& S, const DevConst& K, uint32_
   const float ypu = yh * rho_u, zpu = zh * rho_u;
   const float ypd = yh * rho_d, zpd = zh * rho_d;
   int nu = 0;
-  for_window_hits(Bu, bou, S.hit, ypu, zpu, W, W, [&](uint32_t u, const Hit& c) {
+  for_window_hits<WB>(Bu, bou, S.hit, ypu, zpu, W, W, [&](uint32_t u, const Hit& c) {
     if (!(fabsf(c.y - ypu) <= W && fabsf(c.z - zpu) <= W)) return;
     if (nu < kNfCand) my[nu * kNfThreads] = u;
     ++nu;
@@ -83,27 +85,27 @@ __device__ __forceinline__ void nf_hit(const Slot& S, const DevConst& K, uint32_
     const float sy = sigma_y(K, zh), sz = sigma_z(K, zh);
     const float wy = 1.0f / (1.5f * (sy * sy));
     const float wz = 1.0f / (1.5f * (sz * sz));
-    for_window_hits(Bd, bod, S.hit, ypd, zpd, W, W, [&](uint32_t d, const Hit& xd) {
+    for_window_hits<WB>(Bd, bod, S.hit, ypd, zpd, W, W, [&](uint32_t d, const Hit& xd) {
       if (!(fabsf(xd.y - ypd) <= W && fabsf(xd.z - zpd) <= W)) return;
       if (nu <= kNfCand) {
-        // the listed up hits, four records per memory round trip
-        for (int k0 = 0; k0 < nu; k0 += 4) {
-          uint32_t uu[4];
-          Hit xu[4];
+        // the listed up hits, WB records per memory round trip
+        for (int k0 = 0; k0 < nu; k0 += WB) {
+          uint32_t uu[WB];
+          Hit xu[WB];
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
+          for (int v = 0; v < WB; ++v)
             if (k0 + v < nu) {
               uu[v] = my[(k0 + v) * kNfThreads];
               xu[v] = S.hit[uu[v]];
             }
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
+          for (int v = 0; v < WB; ++v)
             if (k0 + v < nu)
               best.offer(nf_metric(xd.y, xd.z, xu[v].y, xu[v].z, yh, zh, f, wy, wz), xd.id,
                          xu[v].id, (int32_t)d, (int32_t)uu[v]);
         }
       } else {
-        for_window_hits(Bu, bou, S.hit, ypu, zpu, W, W, [&](uint32_t u, const Hit& c) {
+        for_window_hits<WB>(Bu, bou, S.hit, ypu, zpu, W, W, [&](uint32_t u, const Hit& c) {
           if (!(fabsf(c.y - ypu) <= W && fabsf(c.z - zpu) <= W)) return;
           best.offer(nf_metric(xd.y, xd.z, c.y, c.z, yh, zh, f, wy, wz), xd.id, c.id,
                      (int32_t)d, (int32_t)u);
@@ -121,6 +123,7 @@ __device__ __forceinline__ void nf_hit(const Slot& S, const DevConst& K, uint32_
 // round-robin over the 8 XCDs, and the blocks of XCD x stride over the x-th
 // contiguous eighth of the hits, so the rows r-1, r+1 its lanes read stay
 // in its L2.
+template <int WB>
 __global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, int g0, int ns) {
   __shared__ uint32_t cand[kNfCand * kNfThreads];
   const uint32_t h_begin = S.row_off[g0 * kRows];
@@ -130,7 +133,16 @@ __global__ void __launch_bounds__(kNfThreads) k_neighbours(Slot S, DevConst K, i
   const uint32_t c0 = h_begin + x * per;
   const uint32_t c1 = min(h_end, c0 + per);
   for (uint32_t h = c0 + (blockIdx.x / 8u) * kNfThreads + threadIdx.x; h < c1; h += nbx * kNfThreads)
-    nf_hit(S, K, h, cand + threadIdx.x);
+    nf_hit<WB>(S, K, h, cand + threadIdx.x);
+}
+
+void launch_neighbours(int wb, int blocks, hipStream_t st, const Slot& S, const DevConst& K, int g0,
+                       int ns) {
+  switch (wb) {
+    case 2: k_neighbours<2><<<blocks, kNfThreads, 0, st>>>(S, K, g0, ns); break;
+    case 8: k_neighbours<8><<<blocks, kNfThreads, 0, st>>>(S, K, g0, ns); break;
+    default: k_neighbours<4><<<blocks, kNfThreads, 0, st>>>(S, K, g0, ns); break;
+  }
 }
 
 // Head of a cleaned chain of >= n_min_chain hits (no cleaned down link; the

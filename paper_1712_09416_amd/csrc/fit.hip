@@ -15,26 +15,27 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-// Rows are walked kRowBatch at a time: the hit-list entries of a batch are
-// loaded together, then the weights of their hits, so a batch costs two
-// memory round trips instead of two per row.
-constexpr int kRowBatch = 8;
+// Rows are walked RB at a time (a tuning knob): the hit-list entries of a
+// batch are loaded together, then the weights of their hits, so a batch
+// costs two memory round trips instead of two per row.
 
 // hv[u] = the tracklet's hit in row r0+u if that row is inside [rin, rout]
 // of an active lane, else -1 (rows outside are not read).
+template <int RB>
 __device__ __forceinline__ void load_row_batch(const TlRow& hits, int r0, bool active, int rin,
-                                               int rout, int32_t (&hv)[kRowBatch]) {
+                                               int rout, int32_t (&hv)[RB]) {
 #pragma unroll
-  for (int u = 0; u < kRowBatch; ++u) {
+  for (int u = 0; u < RB; ++u) {
     const int r = r0 + u;
     hv[u] = (active && r >= rin && r <= rout) ? hits[r] : -1;
   }
 }
 
-__device__ __forceinline__ void load_weights(const Slot& S, const int32_t (&hv)[kRowBatch],
-                                             uint32_t (&wv)[kRowBatch]) {
+template <int RB>
+__device__ __forceinline__ void load_weights(const Slot& S, const int32_t (&hv)[RB],
+                                             uint32_t (&wv)[RB]) {
 #pragma unroll
-  for (int u = 0; u < kRowBatch; ++u) wv[u] = hv[u] >= 0 ? S.weight[hv[u]] : 0u;
+  for (int u = 0; u < RB; ++u) wv[u] = hv[u] >= 0 ? S.weight[hv[u]] : 0u;
 }
 
 // a6: a valid tracklet becomes a track if it owns (holds the maximal weight
@@ -42,6 +43,7 @@ __device__ __forceinline__ void load_weights(const Slot& S, const int32_t (&hv)[
 // range; the scan of these flags places the tracks.
 // Lane per tracklet; a wave walks the rows its 64 consecutive tracklets
 // span together, so each row's hit-list reads are contiguous (tile layout).
+template <int RB>
 __global__ void __launch_bounds__(256) k_select(Slot S, DevConst K, int g0) {
   const uint32_t total = S.range_cnt[0];
   const uint32_t base = S.tl_base[g0];
@@ -65,13 +67,13 @@ __global__ void __launch_bounds__(256) k_select(Slot S, DevConst K, int g0) {
     const int lo = wave_min(valid ? rin : kRows), hi = wave_max(valid ? rout : -1);
     const TlRow hits = tl_row(S, T);
     int cnt = 0;
-    for (int r0 = lo; r0 <= hi; r0 += kRowBatch) {
-      int32_t hv[kRowBatch];
+    for (int r0 = lo; r0 <= hi; r0 += RB) {
+      int32_t hv[RB];
       load_row_batch(hits, r0, valid, rin, rout, hv);
-      uint32_t wv[kRowBatch];
+      uint32_t wv[RB];
       load_weights(S, hv, wv);
 #pragma unroll
-      for (int u = 0; u < kRowBatch; ++u) cnt += (hv[u] >= 0 && wv[u] == w) ? 1 : 0;
+      for (int u = 0; u < RB; ++u) cnt += (hv[u] >= 0 && wv[u] == w) ? 1 : 0;
     }
     if (t < total) S.tl_sel[t] = valid && cnt >= K.n_min_track ? 1u : 0u;
   }
@@ -82,6 +84,7 @@ __global__ void __launch_bounds__(256) k_select(Slot S, DevConst K, int g0) {
 // together by the wave as in k_select.  The range's track region holds
 // every track its hits allow (each owns >= n_min_track hits of its own); a
 // position beyond it is not written and raises the capacity error.
+template <int RB>
 __global__ void __launch_bounds__(256) k_track_write(Slot S, int g0, int ns) {
   const uint32_t total = S.range_cnt[0];
   const uint32_t ntk = S.range_cnt[1];
@@ -116,13 +119,13 @@ __global__ void __launch_bounds__(256) k_track_write(Slot S, int g0, int ns) {
     int32_t* own = S.tk_own + (size_t)k * kRows;
     uint8_t* own_row = S.tk_own_row + (size_t)k * kRows;
     int cnt = 0;
-    for (int r0 = lo; r0 <= hi; r0 += kRowBatch) {
-      int32_t hv[kRowBatch];
+    for (int r0 = lo; r0 <= hi; r0 += RB) {
+      int32_t hv[RB];
       load_row_batch(hits, r0, sel, rin, rout, hv);
-      uint32_t wv[kRowBatch];
+      uint32_t wv[RB];
       load_weights(S, hv, wv);
 #pragma unroll
-      for (int u = 0; u < kRowBatch; ++u) {
+      for (int u = 0; u < RB; ++u) {
         if (hv[u] >= 0 && wv[u] == w) {
           own[cnt] = hv[u];
           own_row[cnt] = (uint8_t)(r0 + u);
@@ -134,6 +137,22 @@ __global__ void __launch_bounds__(256) k_track_write(Slot S, int g0, int ns) {
       S.tk_tracklet[k] = (int32_t)T;
       S.tk_nown[k] = cnt;
     }
+  }
+}
+
+void launch_select(int rb, int blocks, hipStream_t st, const Slot& S, const DevConst& K, int g0) {
+  switch (rb) {
+    case 4: k_select<4><<<blocks, 256, 0, st>>>(S, K, g0); break;
+    case 16: k_select<16><<<blocks, 256, 0, st>>>(S, K, g0); break;
+    default: k_select<8><<<blocks, 256, 0, st>>>(S, K, g0); break;
+  }
+}
+
+void launch_track_write(int rb, int blocks, hipStream_t st, const Slot& S, int g0, int ns) {
+  switch (rb) {
+    case 4: k_track_write<4><<<blocks, 256, 0, st>>>(S, g0, ns); break;
+    case 16: k_track_write<16><<<blocks, 256, 0, st>>>(S, g0, ns); break;
+    default: k_track_write<8><<<blocks, 256, 0, st>>>(S, g0, ns); break;
   }
 }
 

@@ -215,8 +215,8 @@ __device__ __forceinline__ int bin_z(const RowBins& b, float z) {
 // are read together, then their hits four at a time across the ranges, so
 // a query waits for a few memory round trips rather than one per hit or
 // per range.  fn(p, hit) runs in ascending p within a range, ranges in
-// ascending z.
-template <class Fn>
+// ascending z.  WB: hit records read per round trip (a tuning knob).
+template <int WB, class Fn>
 __device__ __forceinline__ void for_window_hits(const RowBins& b, const uint32_t* bo, const Hit* hit,
                                                 float yc, float zc, float wy, float wz, Fn&& fn) {
   const float eps = 1e-3f;
@@ -234,23 +234,23 @@ __device__ __forceinline__ void for_window_hits(const RowBins& b, const uint32_t
         hi[k] = bo[first + iy1 + 1];
       }
     }
-    // the four ranges as one sequence (same order), read four hits at a
+    // the four ranges as one sequence (same order), read WB hits at a
     // time whichever ranges they fall in
     const uint32_t c0 = hi[0] - lo[0];
     const uint32_t c1 = c0 + (hi[1] - lo[1]);
     const uint32_t c2 = c1 + (hi[2] - lo[2]);
     const uint32_t c3 = c2 + (hi[3] - lo[3]);
-    for (uint32_t f = 0; f < c3; f += 4) {
-      uint32_t p[4];
-      Hit x[4];
+    for (uint32_t f = 0; f < c3; f += WB) {
+      uint32_t p[WB];
+      Hit x[WB];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < WB; ++u) {
         const uint32_t q = f + u;
         p[u] = q < c0 ? lo[0] + q : q < c1 ? lo[1] + (q - c0) : q < c2 ? lo[2] + (q - c1) : lo[3] + (q - c2);
         if (q < c3) x[u] = hit[p[u]];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < WB; ++u)
         if (f + u < c3) fn(p[u], x[u]);
     }
   }

@@ -5,6 +5,15 @@
 
 namespace tpc {
 
+// launchers of the kernels instantiated for tuning knobs (results never
+// depend on the knobs): wb = window hits read per round trip (2, 4, 8),
+// rb = hit-list rows read per round trip (4, 8, 16)
+void launch_neighbours(int wb, int blocks, hipStream_t st, const Slot& S, const DevConst& K, int g0,
+                       int ns);
+void launch_tracklets(int wb, int blocks, int threads, hipStream_t st, const Slot& S,
+                      const DevConst& K, int g0);
+void launch_select(int rb, int blocks, hipStream_t st, const Slot& S, const DevConst& K, int g0);
+void launch_track_write(int rb, int blocks, hipStream_t st, const Slot& S, int g0, int ns);
 // stage + grid
 __global__ void k_count(Slot S);
 __global__ void k_row_layout(Slot S, DevConst K);
@@ -14,13 +23,9 @@ __global__ void k_row_sort_tiny(Slot S);
 __global__ void k_row_sort_small(Slot S);
 __global__ void k_row_sort_large(Slot S);
 // cellular automaton
-__global__ void k_neighbours(Slot S, DevConst K, int g0, int ns);
 __global__ void k_clean_rows(Slot S, int g0, int ns, int n_min_chain);
 __global__ void k_start_write(Slot S, int g0, int ns, int n_min_chain);
 // Kalman filter
-__global__ void k_tracklets(Slot S, DevConst K, int g0);
-__global__ void k_select(Slot S, DevConst K, int g0);
-__global__ void k_track_write(Slot S, int g0, int ns);
 __global__ void k_refit(Slot S, DevConst K, int g0, int ns);
 // output
 __global__ void k_scan_tiles(const uint32_t* in, const uint32_t* n_dev, int64_t n_host,

@@ -19,7 +19,8 @@ __device__ __forceinline__ bool inside(const DevConst& K, const Helix<float>& h,
 // Best hit of row sr for the predicted state: inside
 // |r_y| <= min(k sqrt(S_yy), w_max), |r_z| <= min(k sqrt(S_zz), w_max),
 // smallest chi2, ties to the smaller cluster ID.  -1 if none; the hit record
-// is returned in `out`.
+// is returned in `out`.  WB: hit records read per round trip.
+template <int WB>
 __device__ __forceinline__ int32_t search_row(const Slot& S, const DevConst& K, const RowBins& rb,
                                               const Helix<float>& h, float vy, float vz,
                                               unsigned& examined, Hit& out) {
@@ -32,7 +33,7 @@ __device__ __forceinline__ int32_t search_row(const Slot& S, const DevConst& K, 
   int32_t best = -1;
   float bchi = 0.0f;
   uint32_t bid = 0;
-  for_window_hits(rb, S.bin_off + rb.base, S.hit, yc, zc, wy, wz, [&](uint32_t p, const Hit& x) {
+  for_window_hits<WB>(rb, S.bin_off + rb.base, S.hit, yc, zc, wy, wz, [&](uint32_t p, const Hit& x) {
     const float ry = x.y - yc, rz = x.z - zc;
     if (!(fabsf(ry) <= wy && fabsf(rz) <= wz)) return;
     ++examined;                 // hits inside the window (independent of the binning)
@@ -64,7 +65,8 @@ __device__ __forceinline__ bool try_hit(const DevConst& K, Helix<float>& h, cons
 //  in    restart at the outermost hit with the prior covariance and the
 //        outward (s, T, Q); rows down to 0: re-confirm the outward hit, else
 //        search; same gap rule.  The inward hits form the tracklet.
-__global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
+template <int WB>
+__global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
   // Tracklets are ordered by (sector, row): give each XCD (blocks are
   // dispatched round-robin over the 8 XCDs) one contiguous chunk, so the
   // hits a chunk's lanes read stay in that XCD's L2.
@@ -145,7 +147,7 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
         if (got < 0) chain = false;
       }
       if (got < 0) {
-        const int32_t bh = search_row(S, K, rb, st, vy, vz, examined, xg);
+        const int32_t bh = search_row<WB>(S, K, rb, st, vy, vz, examined, xg);
         if (bh >= 0 && try_hit(K, st, xg, vy, vz, tries)) got = bh;
       }
       if (got >= 0) {
@@ -206,7 +208,7 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
       if (uh >= 0 && try_hit(K, st, xu, vy, vz, tries)) got = uh;
       if (got < 0) {
         Hit xs;
-        const int32_t bh = search_row(S, K, rb, st, vy, vz, examined, xs);
+        const int32_t bh = search_row<WB>(S, K, rb, st, vy, vz, examined, xs);
         if (bh >= 0 && try_hit(K, st, xs, vy, vz, tries)) got = bh;
       }
       // the list keeps the outward decisions of rows r0..rout; a row is
@@ -261,6 +263,15 @@ __global__ void __launch_bounds__(64) k_tracklets(Slot S, DevConst K, int g0) {
   wave_add_u64(&S.stats[2], examined);
   wave_add_u64(&S.stats[6], tl_hits);
   wave_add_u64(&S.stats[7], tries);
+}
+
+void launch_tracklets(int wb, int blocks, int threads, hipStream_t st, const Slot& S,
+                      const DevConst& K, int g0) {
+  switch (wb) {
+    case 2: k_tracklets<2><<<blocks, threads, 0, st>>>(S, K, g0); break;
+    case 8: k_tracklets<8><<<blocks, threads, 0, st>>>(S, K, g0); break;
+    default: k_tracklets<4><<<blocks, threads, 0, st>>>(S, K, g0); break;
+  }
 }
 
 }  // namespace tpc

@@ -69,8 +69,9 @@ class ServeStats:
 class _Worker:
     """One tracker on its own stream with pinned staging buffers."""
 
-    def __init__(self, geometry, max_events, cap, device):
-        self.trk = Tracker(geometry, max_events=max_events, max_clusters=cap, device=device)
+    def __init__(self, geometry, max_events, cap, device, **params):
+        self.trk = Tracker(geometry, max_events=max_events, max_clusters=cap, device=device,
+                           **params)
         self.cap = cap
         pin = dict(pin_memory=True)
         self.h_sector = torch.empty(cap, dtype=torch.uint8, **pin)
@@ -121,17 +122,19 @@ class _Worker:
 
 class Server:
     """n_streams trackers; each slot holds up to max_events events and
-    cap_clusters clusters; at most budget_clusters clusters in flight."""
+    cap_clusters clusters; at most budget_clusters clusters in flight;
+    params: tracker params (e.g. a tuned launch shape)."""
 
     def __init__(self, geometry: dict, n_streams: int = 4, max_events: int = 8,
                  cap_clusters: int = 4 << 20, budget_clusters: int | None = None,
-                 device: str = "cuda:0", plain: bool = False, calib=None):
+                 device: str = "cuda:0", plain: bool = False, calib=None, **params):
         self.plain = plain
         self.calib = calib        # optional DriftCalibration side task
         if plain:
             n_streams, max_events = 1, 1
         self.max_events = max_events
-        self.workers = [_Worker(geometry, max_events, cap_clusters, device) for _ in range(n_streams)]
+        self.workers = [_Worker(geometry, max_events, cap_clusters, device, **params)
+                        for _ in range(n_streams)]
         self.cap = cap_clusters
         self.budget = budget_clusters if budget_clusters is not None else n_streams * cap_clusters
 

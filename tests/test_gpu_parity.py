@@ -418,19 +418,30 @@ def test_serving_results_equal_alone(dev, oracle_lib):
                 raise AssertionError(f"plain={plain} request {i}: {err}") from None
 
 
-def test_autotune_grid_knobs_keep_tracks(dev):
-    """Every grid setting the autotuner tries gives the same tracks (the
-    tuner raises otherwise), including extreme bin sizes."""
+def test_autotune_knobs_keep_tracks(dev, oracle_lib):
+    """Every launch shape the autotuner tries (grid bin sizes, extreme ones
+    included; tracklet block size; window hits and hit-list rows read per
+    round trip) gives the same tracks (the tuner raises otherwise), and the
+    tuned shape's tracks are the oracle's."""
+    from paper_1712_09416_amd import Tracker
     from paper_1712_09416_amd.autotune import autotune
     evs = [tpcgen.pbpb_event(tpcgen.seed_for(3, 900 + e), m) for e, m in enumerate([120, 700, 40])]
     geo = evs[0].geometry()
     offs = np.concatenate([[0], np.cumsum([e.n for e in evs])]).astype(np.int64)
     cat = [torch.from_numpy(np.concatenate([getattr(e, k) for e in evs])).to(dev)
            for k in ("sector", "row", "y", "z")]
-    cands = [(2.0, 2.0), (0.5, 0.5), (1.0, 3.0), (8.0, 1.0), (64.0, 10.0)]
-    res = autotune(geo, offs, *cat, candidates=cands, reps=1)
-    say(f"autotune: {res}")
-    assert res["best"] in cands and len(res["ms"]) == len(cands)
+    knobs = {"bin_target": (2.0, 0.5, 8.0, 64.0), "bin_min_edge": (2.0, 0.5, 10.0)}
+    res = autotune(geo, offs, *cat, knobs=knobs, reps=1)
+    say(f"autotune: best {res['best']}, {len(res['ms'])} shapes")
+    assert len(res["ms"]) == 12 + 2 + 2 + 2
+    trk = Tracker(geo, max_events=len(evs), max_clusters=int(offs[-1]), **res["best"])
+    trk.load_batch(0, offs, *cat)
+    trk.track_event(0)
+    for e, ev in enumerate(evs):
+        tb, hb = trk.get_tracks(0, e)
+        compare_tracks(tb, hb, oracle_lib.run(ev.sector, ev.row, ev.y, ev.z, geo, precision=32,
+                                              nthreads=ORACLE_THREADS))
+    trk.close()
 
 
 def test_multi_stream_sectors_equal_fused(dev, oracle_lib):
