@@ -44,8 +44,7 @@ VALU_PEAK_GINST_S = 256 * 4 * 2.4 / 4.0
 # while the kernel's sources are those the counters were taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tracklets_central_pbpb_traffic.md")
 SQ_FILE = os.path.join(ROOT, "profiles", "k_tracklets_central_pbpb_sq.md")
-KERNEL_SOURCES = ("paper_1712_09416_amd/csrc/tracklet.hip", "paper_1712_09416_amd/csrc/tpc_device.h",
-                  "paper_1712_09416_amd/csrc/tpc_kernels.h")
+KERNEL_SOURCES = ("paper_1712_09416_amd/csrc/tracklet.hip", "paper_1712_09416_amd/csrc/tpc_device.h")
 
 
 def kernel_source_hash() -> str:
@@ -358,6 +357,12 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--central-shape", default="",
+                    help="launch shape of the central event as k=v,... (skips its autotuning)")
+    ap.add_argument("--no-single-stream", action="store_true",
+                    help="skip the one-event-at-a-time reference run (counter runs)")
+    ap.add_argument("--inflight", type=int, default=3,
+                    help="events in flight (one tracker context and stream each)")
     ap.add_argument("--plain-steps", type=int, default=3,
                     help="steps of the per-sector (plain) launch sequence, for comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -416,40 +421,65 @@ def main() -> int:
     ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.sector, ev.row, ev.y, ev.z)]
     # the launch shape tuned on this event (graph replays; the tuner checks
     # that the tracks do not change)
-    from paper_1712_09416_amd.autotune import autotune
-    tune_c = autotune(ev.geometry(), np.array([0, ev.n], np.int64), *ins, reps=5)
+    from paper_1712_09416_amd.autotune import autotune, DEFAULTS
+    if args.central_shape:
+        # a given shape (e.g. for counter runs): no tuning
+        shape = dict(DEFAULTS)
+        for kv in args.central_shape.split(","):
+            k, v = kv.split("=")
+            shape[k] = type(DEFAULTS[k])(float(v))
+        tune_c = {"best": shape, "ms": {}, "given": True}
+    else:
+        tune_c = autotune(ev.geometry(), np.array([0, ev.n], np.int64), *ins, reps=5)
     print(f"bench: central autotune {tune_c}", file=sys.stderr, flush=True)
-    trk = Tracker(ev.geometry(), max_clusters=ev.n, **tune_c["best"])
+    # events in flight: one tracker context per stream, step i on tracker
+    # i mod n (each event's whole path on its tracker's stream; the events
+    # of different streams overlap on the GPU, the paper's pipelined events)
+    n_fl = max(1, args.inflight)
+    trks = [Tracker(ev.geometry(), max_clusters=ev.n, **tune_c["best"]) for _ in range(n_fl)]
+    trk = trks[0]
+    st = trk.stream
     torch.cuda.synchronize()
 
-    def step():
-        trk.load(0, *ins)
-        trk.track_event(0)
+    def run_steps(pool, k_steps):
+        """k_steps steps, step i on pool[i % len(pool)], with the library's
+        stage events on (HIP events between the stages on each tracker's
+        stream, no synchronisation).  Returns the host wall time, the per-step
+        HIP-event latencies, the per-stage means over these steps (averaged
+        over the trackers) and the work counters."""
+        for t in pool:
+            t.set_profiling(True)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(k_steps)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for i, (e0, e1) in enumerate(evs):
+            t = pool[i % len(pool)]
+            e0.record(t.stream)
+            t.load(0, *ins)
+            t.track_event(0)
+            e1.record(t.stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - w0) * 1e3
+        lats = [e0.elapsed_time(e1) for e0, e1 in evs]
+        prof = [t.profile() for t in pool[:min(len(pool), k_steps)]]
+        for t in pool:
+            t.set_profiling(False)
+        stages = {k: float(np.mean([p[0][k] for p in prof])) for k in prof[0][0]}
+        return wall, lats, stages, prof[0][1]
 
-    for _ in range(args.warmup):
-        step()
+    for i in range(args.warmup):
+        trks[i % n_fl].load(0, *ins)
+        trks[i % n_fl].track_event(0)
     torch.cuda.synchronize()
 
-    # timed region: K steps back to back on the tracker's stream, with the
-    # library's stage events on (HIP events between the stages on the same
-    # stream, no synchronisation): the per-stage times are the means over
-    # exactly these K steps
-    st = trk.stream                   # every kernel of the tracker runs there
-    ev_steps = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                for _ in range(args.steps)]
-    trk.set_profiling(True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    for e0, e1 in ev_steps:
-        e0.record(st)
-        step()
-        e1.record(st)
-    torch.cuda.synchronize()
-    wall_ms = (time.perf_counter() - w0) * 1e3
-    lat = [e0.elapsed_time(e1) for e0, e1 in ev_steps]
-    total_ms = ev_steps[0][0].elapsed_time(ev_steps[-1][1])
-    stage_ms, counters = trk.profile()
-    trk.set_profiling(False)
+    # timed region: K steps, n_fl events in flight
+    wall_ms, lat, stage_ms, counters = run_steps(trks, args.steps)
+    # the same K steps on one stream (one event at a time), for reference
+    if args.no_single_stream:
+        wall1_ms, lat1, stage1_ms = wall_ms, lat, stage_ms
+    else:
+        wall1_ms, lat1, stage1_ms, _ = run_steps(trks[:1], args.steps)
 
     # end to end: clusters in pinned host memory -> tracks in host memory
     e2e = []
@@ -465,10 +495,18 @@ def main() -> int:
                 e2e.append((time.perf_counter() - t0) * 1e3)
 
     tracks, hits = trk.get_tracks(0)
-    # whole-job rate from the host clock around the synchronised region (the
-    # GPU-event span is reported beside it)
+    for t in trks[1:]:
+        th, hh = t.get_tracks(0)
+        assert np.array_equal(hh, hits) and np.array_equal(th["par"], tracks["par"]), \
+            "trackers of the pipelined run disagree"
+        t.close()
+    # whole-job rate from the host clock around the synchronised region
     ms_per_step = wall_ms / args.steps
     value = ev.n / (ms_per_step * 1e-3)
+    single_stream = {"ms_per_step": wall1_ms / args.steps,
+                     "clusters_per_s": ev.n / (wall1_ms / args.steps * 1e-3),
+                     "p50_ms": float(np.percentile(lat1, 50)),
+                     "p99_ms": float(np.percentile(lat1, 99)), "stage_ms": stage1_ms}
 
     # cross-sector merger on the tracked central event (the step after the
     # per-sector path; timed on its own, not part of the step above)
@@ -539,6 +577,11 @@ def main() -> int:
         roof["alu"] = {"valu_insts_per_launch": valu, "achieved_ginst_s": valu / t_tl / 1e9,
                        "peak_ginst_s": VALU_PEAK_GINST_S,
                        "frac": valu / t_tl / 1e9 / VALU_PEAK_GINST_S}
+    # the same kernel when one event runs alone on the GPU
+    t_tl1 = stage1_ms["tracklets"] * 1e-3
+    roof["single_stream"] = {"launch_ms": stage1_ms["tracklets"],
+                             "achieved": tracklet_bytes(counters) / t_tl1 / 1e9,
+                             "frac": tracklet_bytes(counters) / t_tl1 / 1e9 / HBM_PEAK_GBS}
     # the whole path per step: 67 N + 20 V + 14 H_t + 12 H_k + 84 K
     pb = path_bytes(counters)
     roof["whole_path"] = {"algorithmic_bytes": pb,
@@ -554,7 +597,6 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
-        "gpu_ms_per_step": total_ms / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -562,11 +604,15 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"central Pb-Pb-shaped event, 36 sectors x 159 rows, {ev.n} clusters",
                    "mode": "fused (one launch per step over all sectors)",
+                   "events_in_flight": n_fl,
                    "launch_shape": tune_c["best"],
                    "refit": "f64", "seed": tpcgen.seed_for(2)},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
+        "latency_note": "per-event HIP-event time on its tracker's stream, with the other "
+                        "events in flight sharing the GPU",
         "stage_ms": stage_ms,
+        "single_stream": single_stream,
         "counters": counters,
         "tracks": int(len(tracks)),
         "track_hits": int(len(hits)),
