@@ -157,7 +157,7 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   s.big_rows = c.take<uint32_t>(N / 1024 + 1);
   s.start_hit = c.take<int32_t>(cap_tl);
   s.start_sr = c.take<int32_t>(cap_tl);
-  s.tl_hits = c.take<int32_t>((cap_tl + 63) / 64 * 64 * kRows);
+  s.tl_hits = c.take<uint16_t>((cap_tl + 63) / 64 * 64 * kRowBlocks * 8);
   s.tl_info = c.take<int32_t>(cap_tl * 4);
   s.tl_weight = c.take<uint32_t>(cap_tl);
   s.tl_state = c.take<float>(cap_tl * 5);

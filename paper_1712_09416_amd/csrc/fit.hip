@@ -20,15 +20,22 @@ __device__ __forceinline__ int wave_max(int v) {
 // costs two memory round trips instead of two per row.
 
 // hv[u] = the tracklet's hit in row r0+u if that row is inside [rin, rout]
-// of an active lane, else -1 (rows outside are not read).
+// of an active lane, else -1 (rows outside are not read); gr = the
+// tracklet's sector times the rows per sector.
 template <int RB>
-__device__ __forceinline__ void load_row_batch(const TlRow& hits, int r0, bool active, int rin,
-                                               int rout, int32_t (&hv)[RB]) {
+__device__ __forceinline__ void load_row_batch(const Slot& S, const TlList& hits, int gr, int r0,
+                                               bool active, int rin, int rout,
+                                               int32_t (&hv)[RB]) {
+  uint32_t e[RB], f[RB];
 #pragma unroll
   for (int u = 0; u < RB; ++u) {
     const int r = r0 + u;
-    hv[u] = (active && r >= rin && r <= rout) ? hits[r] : -1;
+    const bool in = active && r >= rin && r <= rout;
+    e[u] = in ? hits.at(r) : (uint32_t)kNoEntry;
+    f[u] = in ? (uint32_t)S.row_off[gr + r] : 0u;
   }
+#pragma unroll
+  for (int u = 0; u < RB; ++u) hv[u] = entry_hit(e[u], f[u]);
 }
 
 template <int RB>
@@ -55,6 +62,7 @@ __global__ void __launch_bounds__(256) k_select(Slot S, DevConst K, int g0) {
     bool valid = false;
     int rin = 1, rout = 0;
     uint32_t w = 0;
+    int gr = 0;
     if (t < total) {
       const int32_t* info = S.tl_info + (size_t)T * 4;
       valid = info[3] != 0;
@@ -62,14 +70,15 @@ __global__ void __launch_bounds__(256) k_select(Slot S, DevConst K, int g0) {
         rin = info[1];
         rout = info[2];
         w = S.tl_weight[T];
+        gr = S.start_sr[T] / kRows * kRows;
       }
     }
     const int lo = wave_min(valid ? rin : kRows), hi = wave_max(valid ? rout : -1);
-    const TlRow hits = tl_row(S, T);
+    const TlList hits = tl_list(S, T);
     int cnt = 0;
     for (int r0 = lo; r0 <= hi; r0 += RB) {
       int32_t hv[RB];
-      load_row_batch(hits, r0, valid, rin, rout, hv);
+      load_row_batch(S, hits, gr, r0, valid, rin, rout, hv);
       uint32_t wv[RB];
       load_weights(S, hv, wv);
 #pragma unroll
@@ -98,6 +107,7 @@ __global__ void __launch_bounds__(256) k_track_write(Slot S, int g0, int ns) {
     bool sel = false;
     uint32_t k = 0, w = 0;
     int rin = 1, rout = 0;
+    int gr = 0;
     if (t < total) {
       const uint32_t pos = S.tl_sel[t];
       const uint32_t next = t + 1 < total ? S.tl_sel[t + 1] : ntk;
@@ -112,16 +122,17 @@ __global__ void __launch_bounds__(256) k_track_write(Slot S, int g0, int ns) {
         rin = info[1];
         rout = info[2];
         w = S.tl_weight[T];
+        gr = S.start_sr[T] / kRows * kRows;
       }
     }
     const int lo = wave_min(sel ? rin : kRows), hi = wave_max(sel ? rout : -1);
-    const TlRow hits = tl_row(S, T);
+    const TlList hits = tl_list(S, T);
     int32_t* own = S.tk_own + (size_t)k * kRows;
     uint8_t* own_row = S.tk_own_row + (size_t)k * kRows;
     int cnt = 0;
     for (int r0 = lo; r0 <= hi; r0 += RB) {
       int32_t hv[RB];
-      load_row_batch(hits, r0, sel, rin, rout, hv);
+      load_row_batch(S, hits, gr, r0, sel, rin, rout, hv);
       uint32_t wv[RB];
       load_weights(S, hv, wv);
 #pragma unroll

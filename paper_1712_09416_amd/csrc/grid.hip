@@ -138,7 +138,7 @@ __device__ RowBins make_bins(const DevConst& K, int row, bool side_c, uint32_t n
   b.iby = (float)ny / wy;
   b.ibz = (float)nz / wz;
   b.base = 0;
-  b.pad = 0;
+  b.first = 0;
   return b;
 }
 
@@ -167,7 +167,10 @@ __global__ void k_row_finish(Slot S, int n_min_chain, int n_min_track) {
   const int stride = gridDim.x * blockDim.x;
   const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
   if (t0 == 0) S.range_cnt[2] = 0;   // rows over 1024 hits, listed by the row sort
-  for (int sr = t0; sr < SR; sr += stride) S.bins[sr].base = (int32_t)S.row_bin[sr];
+  for (int sr = t0; sr < SR; sr += stride) {
+    S.bins[sr].base = (int32_t)S.row_bin[sr];
+    S.bins[sr].first = (int32_t)S.row_off[sr];
+  }
   for (int g = t0; g < S.n_sectors; g += stride) {
     const uint32_t ng = S.row_off[(g + 1) * kRows] - S.row_off[g * kRows];
     S.tl_base[g] = ng / (uint32_t)n_min_chain + 1;

@@ -24,6 +24,8 @@ constexpr int kSectorsPerEvent = 36;
 constexpr int kMaxRowHits = 4096;         // LDS sort capacity of one pad row
 constexpr int kBinsPerHit = 2;            // a row has at most this many bins per hit
 constexpr uint32_t kNoHit = 0xFFFFFFFFu;
+constexpr int kRowBlocks = (kRows + 7) / 8;   // a tracklet's hit list in blocks of 8 rows
+constexpr uint16_t kNoEntry = 0xFFFFu;        // hit-list entry of a row without hit
 
 // ---------------------------------------------------------------------------
 // constants handed to every kernel by value
@@ -52,7 +54,7 @@ struct RowBins {
   float y0, z0, iby, ibz;   // lower edges and inverse bin sizes
   int32_t ny, nz;           // bins in y and z
   int32_t base;             // first entry of this row in bin_off
-  int32_t pad;
+  int32_t first;            // the row's first sorted hit
 };
 
 // A sorted hit: coordinates, global cluster index, cleaned up-link (sorted
@@ -97,7 +99,7 @@ struct Slot {
   int32_t* start_hit;       // [tl capacity] sorted index of the start hit
   int32_t* start_sr;        // [tl capacity] (sector, row) of the start hit
   // tracklets
-  int32_t* tl_hits;         // [tl capacity / 64][kRows][64] sorted index per row, -1 none
+  uint16_t* tl_hits;        // [tl capacity / 64][kRowBlocks][64][8] per row: the hit's offset in its row, kNoEntry none
   int32_t* tl_info;         // [tl capacity][4]: n, row_in, row_out, valid
   uint32_t* tl_weight;      // [tl capacity]
   float* tl_state;          // [tl capacity][5] inner state (y, z, s, T, Q)
@@ -132,16 +134,49 @@ struct Slot {
   int32_t cap_e;
 };
 
-// Row-indexed hit list of tracklet T.  Stored in tiles of 64 tracklets,
-// entry (T, r) at ((T / 64) * kRows + r) * 64 + T % 64: the lanes of a
-// wave (consecutive tracklets) stepping through the same row touch
-// neighbouring words, not one cache line each.
-struct TlRow {
-  int32_t* p;
-  __device__ __forceinline__ int32_t& operator[](int r) const { return p[(size_t)r * 64]; }
+// Row-indexed hit list of tracklet T: per row the hit's offset from its
+// row's first sorted hit (rows hold at most 4096 hits), kNoEntry if none.
+// Stored in tiles of 64 tracklets; inside a tile, blocks of 8 rows, and in
+// a block the 8 entries of each tracklet together (16 bytes): a tracklet
+// reads or writes 8 rows with one access, and the lanes of a wave
+// (consecutive tracklets) touch one contiguous kilobyte per block.
+struct TlList {
+  uint16_t* p;              // this tracklet's entries of row block 0
+  __device__ __forceinline__ uint4 load_block(int b) const {
+    return *reinterpret_cast<const uint4*>(p + (size_t)b * 512);
+  }
+  __device__ __forceinline__ void store_block(int b, const uint4& v) const {
+    *reinterpret_cast<uint4*>(p + (size_t)b * 512) = v;
+  }
+  __device__ __forceinline__ uint16_t at(int r) const { return p[(size_t)(r >> 3) * 512 + (r & 7)]; }
 };
-__device__ __forceinline__ TlRow tl_row(const Slot& S, uint32_t T) {
-  return TlRow{S.tl_hits + (size_t)(T >> 6) * kRows * 64 + (T & 63u)};
+__device__ __forceinline__ TlList tl_list(const Slot& S, uint32_t T) {
+  return TlList{S.tl_hits + ((size_t)(T >> 6) * kRowBlocks * 64 + (T & 63u)) * 8};
+}
+// entry k (0..7) of a block held in registers as two 64-bit halves (a
+// shift and a two-way select: no indexed access, which the compiler would
+// place in scratch memory)
+__device__ __forceinline__ uint32_t block_get(const uint4& v, int k) {
+  const uint64_t h = k < 4 ? ((uint64_t)v.y << 32 | v.x) : ((uint64_t)v.w << 32 | v.z);
+  return (uint32_t)(h >> ((k & 3) * 16)) & 0xFFFFu;
+}
+__device__ __forceinline__ void block_set(uint4& v, int k, uint32_t e) {
+  const bool lo = k < 4;
+  uint64_t h = lo ? ((uint64_t)v.y << 32 | v.x) : ((uint64_t)v.w << 32 | v.z);
+  const int sh = (k & 3) * 16;
+  h = (h & ~(0xFFFFull << sh)) | ((uint64_t)(e & 0xFFFFu) << sh);
+  const uint32_t a = (uint32_t)h, b = (uint32_t)(h >> 32);
+  v.x = lo ? a : v.x;
+  v.y = lo ? b : v.y;
+  v.z = lo ? v.z : a;
+  v.w = lo ? v.w : b;
+}
+__device__ __forceinline__ uint4 block_empty() {
+  return make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+}
+// sorted-hit index of an entry of the row whose first hit is `first`
+__device__ __forceinline__ int32_t entry_hit(uint32_t e, uint32_t first) {
+  return e == kNoEntry ? -1 : (int32_t)(first + e);
 }
 
 // Buffers of the cross-sector merger, per slot (K = track capacity, S =

@@ -1,7 +1,8 @@
 // a5: tracklet construction (paper, Abstract: Kalman-filter track
 // following).  One lane per start hit, float arithmetic; the lane's state
-// and per-row decisions live in registers, its hit list in global memory
-// (row-indexed, written only for the rows the lane visits).
+// and the decisions of its current block of 8 rows live in registers, its
+// hit list in global memory (row-indexed, a block written when the lane
+// leaves it).
 #include "tpc_device.h"
 #include "tpc_kernels.h"
 
@@ -90,7 +91,8 @@ __global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
     const int32_t p0 = S.start_hit[T];
     const Hit x0 = S.hit[p0];
     const Hit x1 = S.hit[x0.upc];
-    const TlRow hits = tl_row(S, T);
+    const TlList hits = tl_list(S, T);
+    const uint32_t first0 = S.row_off[sr0];
 
     // radii of the start row and the next one (r0 <= 157: a start hit has
     // an up link)
@@ -109,13 +111,17 @@ __global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
       const float sy = sigma_y(K, st.z), sz = sigma_z(K, st.z);
       reset_cov(st, sy * sy, sz * sz, K.cs0, K.ct0, K.cq0);
     }
-    hits[r0] = p0;
+    // the hit list's block of the current row, in registers
+    int cb = r0 >> 3;
+    uint4 blk = block_empty();
+    block_set(blk, r0 & 7, (uint32_t)p0 - first0);
 
     // outward
     Helix<float> last = st;
     int rout = r0;
     float x_rout = x_r0;
     int32_t next = x0.upc;     // cleaned chain link of the last accepted hit
+    int32_t p_out = p0;        // the outermost accepted hit
     bool chain = true;
     int miss = 0;
     // row radii: the current one carried in a register, the next one read
@@ -132,6 +138,11 @@ __global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
       const RowBins rb = S.bins[g * kRows + r];
       Hit xnext;
       if (chain && next >= 0) xnext = S.hit[next];
+      if ((r & 7) == 0) {          // into the next block of rows
+        hits.store_block(cb, blk);
+        cb = r >> 3;
+        blk = block_empty();
+      }
       if (!transport(st, xr - x_prev, K.b, K.smax, K.kk, K.m2)) break;
       x_prev = xr;
       if (!inside(K, st, xr, side_c)) break;
@@ -151,11 +162,9 @@ __global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
         if (bh >= 0 && try_hit(K, st, xg, vy, vz, tries)) got = bh;
       }
       if (got >= 0) {
-        // the rows missed since the last hit get their -1 now; rows after
-        // the outermost hit are never read, so they are not written
-        for (int m = 1; m <= miss; ++m) hits[r - m] = -1;
-        hits[r] = got;
+        block_set(blk, r & 7, (uint32_t)got - (uint32_t)rb.first);
         next = xg.upc;
+        p_out = got;
         miss = 0;
         last = st;
         rout = r;
@@ -164,9 +173,10 @@ __global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
         break;
       }
     }
+    hits.store_block(cb, blk);
 
     // inward, covariance reset at the outermost hit
-    const Hit xo = S.hit[hits[rout]];
+    const Hit xo = S.hit[p_out];
     st = last;
     st.y = xo.y;
     st.z = xo.z;
@@ -178,27 +188,38 @@ __global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
     int rin = rout;
     last = st;
     miss = 0;
-    // the outward hit of the next row down loaded one step ahead, the
-    // hit-list entry of the row below it two steps ahead
-    int32_t uh_next = rout - 1 >= r0 && rout >= 1 ? hits[rout - 1] : -1;
+    // the blocks of the current row and of the one below, in registers (the
+    // outward decisions, rewritten as the inward ones are taken); the
+    // outward hit of the next row down loaded one step ahead, the first hit
+    // of the row below it two steps ahead
+    const int gr = g * kRows;
+    cb = (rout - 1) >> 3;
+    blk = hits.load_block(cb);
+    uint4 blk_dn = cb > 0 ? hits.load_block(cb - 1) : block_empty();
+    const uint32_t f_a = rout - 1 >= r0 ? (uint32_t)S.row_off[gr + rout - 1] : 0u;
+    uint32_t f_next = rout - 2 >= r0 ? (uint32_t)S.row_off[gr + rout - 2] : 0u;
+    int32_t uh_next = rout - 1 >= r0 ? entry_hit(block_get(blk, (rout - 1) & 7), f_a) : -1;
     Hit xu_next;
     if (uh_next >= 0) xu_next = S.hit[uh_next];
-    int32_t uh_next2 = rout - 2 >= r0 ? hits[rout - 2] : -1;
     x_prev = x_rout;
     x_ahead = K.row_x[max(rout - 1, 0)];
-    // wait for this read here, once: a read still in flight at the loop's
+    // wait for these reads here, once: a read still in flight at the loop's
     // entry would make the compiler wait inside every step
-    asm volatile("" : "+v"(x_ahead));
+    asm volatile("" : "+v"(x_ahead), "+v"(f_next));
     for (int r = rout - 1; r >= 0; --r) {
       ++visits;
       const float xr = x_ahead;
       x_ahead = K.row_x[max(r - 1, 0)];
-      const RowBins rb = S.bins[g * kRows + r];
+      const RowBins rb = S.bins[gr + r];
       const int32_t uh = uh_next;
       const Hit xu = xu_next;
-      uh_next = uh_next2;
+      // row r-1: its outward entry (this block or the one below) and the
+      // first hit of its row, read a step ago
+      uh_next = -1;
+      if (r - 1 >= r0)
+        uh_next = entry_hit(block_get((r & 7) == 0 ? blk_dn : blk, (r - 1) & 7), f_next);
       if (uh_next >= 0) xu_next = S.hit[uh_next];
-      uh_next2 = r - 2 >= r0 ? hits[r - 2] : -1;
+      if (r - 2 >= r0) f_next = (uint32_t)S.row_off[gr + r - 2];
       if (!transport(st, xr - x_prev, K.b, K.smax, K.kk, K.m2)) break;
       x_prev = xr;
       if (!inside(K, st, xr, side_c)) break;
@@ -211,22 +232,23 @@ __global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
         const int32_t bh = search_row<WB>(S, K, rb, st, vy, vz, examined, xs);
         if (bh >= 0 && try_hit(K, st, xs, vy, vz, tries)) got = bh;
       }
-      // the list keeps the outward decisions of rows r0..rout; a row is
-      // written only where the inward decision differs, and rows below r0
-      // (never written) get their misses when the next hit below is found
+      block_set(blk, r & 7, got >= 0 ? (uint32_t)got - (uint32_t)rb.first : (uint32_t)kNoEntry);
       if (got >= 0) {
-        for (int m = 1; m <= miss; ++m)
-          if (r + m < r0) hits[r + m] = -1;
-        if (r < r0 || got != uh) hits[r] = got;
         ++n;
         miss = 0;
         last = st;
         rin = r;
-      } else {
-        if (uh >= 0) hits[r] = -1;   // the outward hit of this row was dropped
-        if (++miss >= K.n_gap) break;
+      } else if (++miss >= K.n_gap) {
+        break;
+      }
+      if ((r & 7) == 0 && r > 0) {   // into the block below
+        hits.store_block(cb, blk);
+        --cb;
+        blk = blk_dn;
+        blk_dn = cb > 0 ? hits.load_block(cb - 1) : block_empty();
       }
     }
+    hits.store_block(cb, blk);
     tl_hits += (unsigned)n;
     int32_t* info = S.tl_info + (size_t)T * 4;
     const bool valid = n >= K.n_min_tracklet;
@@ -241,14 +263,18 @@ __global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
     // of the tracklets holding it; issued here, without waiting for results,
     // so the atomics overlap the other lanes' Kalman steps
     if (valid) {
-      // the list is read back eight rows per memory round trip
-      for (int r0 = rin; r0 <= rout; r0 += 8) {
-        int32_t hv[8];
+      // the list is read back a block of eight rows per memory round trip
+      for (int b = rin >> 3; b <= rout >> 3; ++b) {
+        const uint4 v = hits.load_block(b);
+        uint32_t f[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) hv[u] = r0 + u <= rout ? hits[r0 + u] : -1;
+        for (int u = 0; u < 8; ++u) f[u] = (uint32_t)S.row_off[gr + min(8 * b + u, kRows - 1)];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (hv[u] >= 0) atomicMax(&S.weight[hv[u]], w);
+        for (int u = 0; u < 8; ++u) {
+          const int r = 8 * b + u;
+          const int32_t h = (r >= rin && r <= rout) ? entry_hit(block_get(v, u), f[u]) : -1;
+          if (h >= 0) atomicMax(&S.weight[h], w);
+        }
       }
     }
     float* sv = S.tl_state + (size_t)T * 5;
