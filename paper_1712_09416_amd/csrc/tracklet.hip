@@ -189,13 +189,15 @@ __global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
     last = st;
     miss = 0;
     // the blocks of the current row and of the one below, in registers (the
-    // outward decisions, rewritten as the inward ones are taken); the
-    // outward hit of the next row down loaded one step ahead, the first hit
-    // of the row below it two steps ahead
+    // outward decisions, rewritten as the inward ones are taken; a block is
+    // stored back only if an entry changed); the outward hit of the next
+    // row down loaded one step ahead, the first hit of the row below it two
+    // steps ahead
     const int gr = g * kRows;
     cb = (rout - 1) >> 3;
     blk = hits.load_block(cb);
     uint4 blk_dn = cb > 0 ? hits.load_block(cb - 1) : block_empty();
+    bool dirty = false;
     const uint32_t f_a = rout - 1 >= r0 ? (uint32_t)S.row_off[gr + rout - 1] : 0u;
     uint32_t f_next = rout - 2 >= r0 ? (uint32_t)S.row_off[gr + rout - 2] : 0u;
     int32_t uh_next = rout - 1 >= r0 ? entry_hit(block_get(blk, (rout - 1) & 7), f_a) : -1;
@@ -232,7 +234,13 @@ __global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
         const int32_t bh = search_row<WB>(S, K, rb, st, vy, vz, examined, xs);
         if (bh >= 0 && try_hit(K, st, xs, vy, vz, tries)) got = bh;
       }
-      block_set(blk, r & 7, got >= 0 ? (uint32_t)got - (uint32_t)rb.first : (uint32_t)kNoEntry);
+      {
+        const uint32_t e = got >= 0 ? (uint32_t)got - (uint32_t)rb.first : (uint32_t)kNoEntry;
+        if (block_get(blk, r & 7) != e) {
+          block_set(blk, r & 7, e);
+          dirty = true;
+        }
+      }
       if (got >= 0) {
         ++n;
         miss = 0;
@@ -242,13 +250,14 @@ __global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
         break;
       }
       if ((r & 7) == 0 && r > 0) {   // into the block below
-        hits.store_block(cb, blk);
+        if (dirty) hits.store_block(cb, blk);
+        dirty = false;
         --cb;
         blk = blk_dn;
         blk_dn = cb > 0 ? hits.load_block(cb - 1) : block_empty();
       }
     }
-    hits.store_block(cb, blk);
+    if (dirty) hits.store_block(cb, blk);
     tl_hits += (unsigned)n;
     int32_t* info = S.tl_info + (size_t)T * 4;
     const bool valid = n >= K.n_min_tracklet;
@@ -260,8 +269,8 @@ __global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
     const uint32_t w = ((uint32_t)n << 24) | (0xFFFFFFu - id0);
     S.tl_weight[T] = w;
     // a6 (ownership): every hit of a valid tracklet keeps the largest weight
-    // of the tracklets holding it; issued here, without waiting for results,
-    // so the atomics overlap the other lanes' Kalman steps
+    // of the tracklets holding it; issued here, so the atomics overlap the
+    // other lanes' Kalman steps, and only where the weight read is smaller
     if (valid) {
       // the list is read back a block of eight rows per memory round trip
       for (int b = rin >> 3; b <= rout >> 3; ++b) {
@@ -269,12 +278,18 @@ __global__ void __launch_bounds__(256) k_tracklets(Slot S, DevConst K, int g0) {
         uint32_t f[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) f[u] = (uint32_t)S.row_off[gr + min(8 * b + u, kRows - 1)];
+        int32_t h[8];
+        uint32_t cur[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int r = 8 * b + u;
-          const int32_t h = (r >= rin && r <= rout) ? entry_hit(block_get(v, u), f[u]) : -1;
-          if (h >= 0) atomicMax(&S.weight[h], w);
+          h[u] = (r >= rin && r <= rout) ? entry_hit(block_get(v, u), f[u]) : -1;
+          cur[u] = h[u] >= 0 ? S.weight[h[u]] : 0xFFFFFFFFu;
         }
+        // a weight already at least w stays so (the maximum only grows)
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (cur[u] < w) atomicMax(&S.weight[h[u]], w);
       }
     }
     float* sv = S.tl_state + (size_t)T * 5;
