@@ -753,7 +753,8 @@ struct Sector {
 
 // ---------------------------------------------------------------------------
 // Cross-sector merger.  A particle crossing the boundary between two
-// neighbouring sectors of one side leaves one track segment in each; the
+// neighbouring sectors of one side, or the central membrane between the
+// two sectors of one azimuth, leaves one track segment in each; the
 // per-sector tracker fits them separately.  The merger joins such segments
 // and refits the joined hit list across the sector frames.  The paper names
 // this step only as the continuation of the per-sector tracking; the
@@ -762,9 +763,11 @@ struct Sector {
 //     over its hits seeded with its fitted parameters at the innermost hit
 //     and the prior covariance;
 //  M2 a pair (A, B) of tracks of one event, B in a neighbouring sector of
-//     A's side, with 0 < B.row_in - A.row_out <= row_gap, is compatible if
-//     A's outer state, turned into B's frame and transported to B's
-//     innermost row, matches B's fitted state: chi2 = d^T (C_A + C_B)^-1 d
+//     A's side or in the sector across the membrane from A's (same
+//     azimuth, same frame), with 0 < B.row_in - A.row_out <= row_gap, is
+//     compatible if A's outer state, turned into B's frame (no turn across
+//     the membrane) and transported to B's innermost row, matches B's
+//     fitted state: chi2 = d^T (C_A + C_B)^-1 d
 //     over the 5 parameters (Cholesky) <= chi2_max.  T and Q do not change
 //     under rotation or transport, and d_i^2 / S_ii never exceeds the full
 //     chi2, so pairs failing the cut on T or Q alone are skipped before any
@@ -934,14 +937,21 @@ struct Merger {
     return true;
   }
 
-  // +1 if sector b follows a counter-clockwise (frame turned by +a), -1 if
-  // it precedes it, 0 if not neighbours on the same side.
+  // +1 if sector b follows a counter-clockwise on its side (frame turned by
+  // +a), -1 if it precedes it, kMembrane if b is across the membrane from a
+  // (same azimuth: the same frame), 0 otherwise.
+  static constexpr int kMembrane = 2;
   static int neighbour(int a, int b) {
-    if (a / 18 != b / 18) return 0;
     const int ka = a % 18, kb = b % 18;
+    if (a / 18 != b / 18) return ka == kb ? kMembrane : 0;
     if (kb == (ka + 1) % 18) return 1;
     if (ka == (kb + 1) % 18) return -1;
     return 0;
+  }
+  // the frame of sector b from that of sector a (neighbour(a, b) = dir != 0)
+  bool turn(State<double>& st, double& x, int dir) const {
+    if (dir == kMembrane) return true;
+    return rotate(st, x, ca, double(dir) * sa, c.b, c.smax);
   }
 
   // M2: chi2 of the pair (outer state of A, track B), false if incompatible
@@ -956,7 +966,7 @@ struct Merger {
     if (dQ * dQ > cut * (outA.C[14] + B.cov[14])) return false;
     State<double> st = outA;
     double x = c.X[A.row_out];
-    if (!rotate(st, x, ca, double(dir) * sa, c.b, c.smax)) return false;
+    if (!turn(st, x, dir)) return false;
     if (!transport_to(st, x, c.X[B.row_in], c.b, c.smax, double(M.step_max), c.kk, c.m2)) return false;
     double d[5], S[15];
     for (int i = 0; i < 5; ++i) d[i] = st.p[i] - B.par[i];
@@ -992,9 +1002,9 @@ struct Merger {
       if (j == int(segs.size()) - 1) {
         --k;                                  // the outermost hit seeded the pass
       } else {
-        const int dir = neighbour(sg.sector, segs[j + 1].sector);
+        const int dir = neighbour(segs[j + 1].sector, sg.sector);   // outer -> inner frame
         double x = c.X[cur_row];
-        if (!rotate(st, x, ca, -double(dir) * sa, c.b, c.smax)) return false;
+        if (!turn(st, x, dir)) return false;
         const int r = in.row[sg.hits[k]];
         if (!transport_to(st, x, c.X[r], c.b, c.smax, double(M.step_max), c.kk, c.m2)) return false;
         const double sy = sig_y(c, st.p[1]), sz = sig_z(c, st.p[1]);
@@ -1034,8 +1044,7 @@ struct Merger {
       if (!transport_to(st, x, xo, c.b, c.smax, double(M.step_max), c.kk, c.m2)) return false;
       x = xo;
       if (j + 1 < segs.size()) {
-        const int dir = neighbour(segs[j].sector, segs[j + 1].sector);
-        if (!rotate(st, x, ca, double(dir) * sa, c.b, c.smax)) return false;
+        if (!turn(st, x, neighbour(segs[j].sector, segs[j + 1].sector))) return false;
       }
     }
     s0 = st.p[2];
@@ -1058,8 +1067,8 @@ struct Merger {
       if (!ok[a]) continue;
       const int sa_ = in.tracks[a].sector;
       const int side = sa_ / 18, k = sa_ % 18;
-      for (int nbk : {(k + 1) % 18, (k + 17) % 18}) {
-        for (int32_t bi : by_sector[side * 18 + nbk]) {
+      for (int sb : {side * 18 + (k + 1) % 18, side * 18 + (k + 17) % 18, (1 - side) * 18 + k}) {
+        for (int32_t bi : by_sector[sb]) {
           double ch;
           if (!pair_chi2(in.tracks[a], outer[a], in.tracks[bi], ch)) continue;
           if (best_out[a] < 0 || ch < chi_out[a] || (ch == chi_out[a] && bi < best_out[a])) {

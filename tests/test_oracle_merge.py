@@ -241,3 +241,30 @@ def test_nothing_to_merge_in_one_sector(oracle_lib):
     r, m = _merge_case(oracle_lib, ev)
     assert np.all(m.link_out < 0) and np.all(m.n_segments == 1)
     assert np.array_equal(m.tracks, r.tracks) and np.array_equal(m.hits, r.hits)
+
+
+def test_membrane_crossing_segments_are_joined(oracle_lib):
+    """Tracks crossing the central membrane leave a segment in sector k (A
+    side) and its continuation in sector k + 18 (same azimuth, same frame):
+    each such pair is linked, and the merged track holds every cluster of
+    its particle (its two segments' hits), fitted across the membrane with
+    parameters within 5 sigma of the truth at its innermost hit."""
+    ev = tpcgen.membrane_event()
+    r, m = _merge_case(oracle_lib, ev)
+    n = len(r.tracks)
+    maj = [_majority(ev, r.track_hits(k)) for k in range(n)]
+    links = [(a, b) for a in range(n) if (b := m.link_out[a]) >= 0]
+    assert len(links) == 12
+    for a, b in links:
+        ta, tb = r.tracks[a], r.tracks[b]
+        assert maj[a][0] == maj[b][0] >= 0
+        assert int(tb["sector"]) == int(ta["sector"]) + 18
+        assert 0 < tb["row_in"] - ta["row_out"] <= 12
+    assert len(m.tracks) == 12
+    for k, t in enumerate(m.tracks):
+        ids = m.hits[t["hit_off"]: t["hit_off"] + t["n_hits"]]
+        p = Counter(ev.pid[ids].tolist()).most_common(1)[0][0]
+        assert set(ids.tolist()) == set(np.nonzero(ev.pid == p)[0].tolist())
+        tr = ev.truth[int(t["inner_id"])]
+        var = np.asarray(t["cov"])[[0, 2, 5, 9, 14]]
+        assert np.all(np.abs((np.asarray(t["par"]) - tr) / np.sqrt(var)) < 5.0), k

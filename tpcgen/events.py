@@ -333,6 +333,23 @@ def tiny_event(seed, n_tracks=3, pt_lo=0.5, pt_hi=5.0, smear=True, noise_frac=0.
                        sectors=[0], smear=smear)
 
 
+def membrane_event(seed=20261205, n_tracks=12, noise_frac=0.05) -> Event:
+    """Stiff tracks that cross the central membrane inside the TPC: vertex
+    z 5-15 cm on the A side, a small negative dip chosen so that z = 0 is
+    reached at a transverse radius of 120-200 cm; one track per azimuthal
+    sector (12 of the 18), near its centre.  Each leaves a segment in sector
+    k (A side) and its continuation in sector k + 18 (C side)."""
+    rng = np.random.default_rng(seed)
+    pt = rng.uniform(2.0, 5.0, n_tracks)
+    p = _particles(rng, n_tracks, pt, 0.0, 1.0, 0.0, 0.1, kind=0)
+    k = np.arange(n_tracks)
+    p["phi"] = np.deg2rad(20.0 * k + 10.0 + rng.uniform(-3.0, 3.0, n_tracks))
+    vz = rng.uniform(5.0, 15.0, n_tracks)
+    p["vz"] = vz
+    p["eta"] = -np.arcsinh(vz / rng.uniform(120.0, 200.0, n_tracks))
+    return build_event("membrane", seed, p, G.SIGMA_PP, noise_frac, 1.0, rng)
+
+
 def batch_multiplicities(n_events=64, seed=None) -> np.ndarray:
     seed = seed_for(CFG_BATCH) if seed is None else seed
     rng = np.random.default_rng(seed)
