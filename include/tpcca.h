@@ -296,12 +296,15 @@ int tpc_merge_params_default(tpc_merge_params* m);
 /* Join track segments across sector boundaries, for every event of a
  * tracked slot (Section 2: data of all links of an event are merged for the
  * global reconstruction; the step after the per-sector tracking: a particle crossing
- * from one sector into its neighbour on the same side leaves one segment in
- * each).  Per track, the state at its outermost hit (an outward Kalman pass
- * seeded with its fitted parameters); each pair (A, B), B in a neighbouring
- * sector with 0 < B.row_in - A.row_out <= row_gap, is compared after
- * turning A's outer state into B's frame (sectors are 2 atan(tan_half_angle)
- * apart) and transporting it to B's innermost row: chi2 of the 5-parameter
+ * from one sector into its neighbour on the same side, or across the central
+ * membrane into the other side's sector of the same azimuth, leaves one
+ * segment in each).  Per track, the state at its outermost hit (an outward
+ * Kalman pass seeded with its fitted parameters); each pair (A, B), B in a
+ * neighbouring sector or across the membrane with
+ * 0 < B.row_in - A.row_out <= row_gap, is compared after turning A's outer
+ * state into B's frame (neighbouring sectors are 2 atan(tan_half_angle)
+ * apart; across the membrane the frame is the same) and transporting it to
+ * B's innermost row: chi2 of the 5-parameter
  * difference with covariance C_A + C_B, kept if <= chi2_max; A and B are
  * linked when each is the other's smallest-chi2 partner (ties to the
  * smaller track index); each chain of linked segments is refitted inward

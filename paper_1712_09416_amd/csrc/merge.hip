@@ -1,5 +1,6 @@
 // Cross-sector merger: a particle that crosses the boundary between two
-// neighbouring sectors of one side leaves one track segment in each; the
+// neighbouring sectors of one side, or the central membrane between the two
+// sectors of one azimuth, leaves one track segment in each; the
 // per-sector tracker fits them separately.  This step (the continuation of
 // the per-sector tracking the paper's tracker chain performs next) joins
 // such segments and refits the joined hit list across the sector frames.
@@ -7,7 +8,8 @@
 //  M1 each track's state at its outermost hit: one outward Kalman pass over
 //     its hits, seeded with its fitted parameters at the innermost hit and
 //     the prior covariance (lane per track);
-//  M2 pairs (A, B) of one event, B in a neighbouring sector of A's side,
+//  M2 pairs (A, B) of one event, B in a neighbouring sector of A's side or
+//     in the sector across the membrane (same frame, no turn),
 //     0 < B.row_in - A.row_out <= row_gap: A's outer state turned into B's
 //     frame and transported to B's innermost row is compared with B's
 //     fitted state, chi2 = d^T (C_A + C_B)^-1 d over the 5 parameters.
@@ -172,13 +174,24 @@ __device__ bool chi2_5(const double* S, const double* d, double& chi2) {
 }
 
 // +1 if sector b (0..35 of one event) is the next one counter-clockwise of
-// a on the same side, -1 the previous one, 0 otherwise
+// a on the same side, -1 the previous one, kMembrane if b is across the
+// central membrane from a (same azimuth: the same frame), 0 otherwise
+constexpr int kMembrane = 2;
 __device__ __forceinline__ int neighbour(int a, int b) {
-  if (a / 18 != b / 18) return 0;
   const int ka = a % 18, kb = b % 18;
+  if (a / 18 != b / 18) return ka == kb ? kMembrane : 0;
   if (kb == (ka + 1) % 18) return 1;
   if (ka == (kb + 1) % 18) return -1;
   return 0;
+}
+
+// the state in the frame of sector b from that of sector a, dir =
+// neighbour(a, b) != 0 (no turn across the membrane)
+template <bool kCov = true>
+__device__ __forceinline__ bool turn_frame(Helix<double>& st, double& x, int dir, const DevConst& K,
+                                           const MergeConst& C) {
+  if (dir == kMembrane) return true;
+  return rotate_frame<kCov>(st, x, C.ca, (double)dir * C.sa, K.bd, C.smax);
 }
 
 __device__ __forceinline__ const int32_t* track_hits(const Slot& S, const tpc_track& t) {
@@ -289,7 +302,7 @@ __device__ bool pair_chi2(const DevConst& K, const MergeConst& C, const tpc_trac
   st.q = op[4];
   for (int i = 0; i < 15; ++i) st.c[i] = oc[i];
   double x = xrow(K, A.row_out);
-  if (!rotate_frame(st, x, C.ca, (double)dir * C.sa, K.bd, C.smax)) return false;
+  if (!turn_frame(st, x, dir, K, C)) return false;
   if (!transport_to_x(st, x, xrow(K, B.row_in), K.bd, C.smax, C.step_max, K.kkd, K.m2d)) return false;
   double d[5], Sm[15];
   d[0] = st.y - B.par[0];
@@ -303,8 +316,9 @@ __device__ bool pair_chi2(const DevConst& K, const MergeConst& C, const tpc_trac
 }
 
 // Candidates of a track among the tracks of the two neighbouring sectors
-// of its side in its event, those whose row (`off` indexes first rows, or
-// last rows) lies in [r_lo, r_hi]: every pair the row condition of M2 admits.
+// of its side and of the sector across the membrane, in its event, those
+// whose row (`off` indexes first rows, or last rows) lies in [r_lo, r_hi]:
+// every pair the sector and row conditions of M2 admit.
 template <class Fn>
 __device__ __forceinline__ void for_neighbours(const uint32_t* off, const int32_t* list,
                                                const tpc_track& t, int r_lo, int r_hi, Fn&& fn) {
@@ -312,9 +326,9 @@ __device__ __forceinline__ void for_neighbours(const uint32_t* off, const int32_
   r_hi = min(r_hi, kRows - 1);
   if (r_lo > r_hi) return;
   const int side = t.sector / 18, k = t.sector % 18;
-  const int nb[2] = {(k + 1) % 18, (k + 17) % 18};
-  for (int u = 0; u < 2; ++u) {
-    const int g = t.event * kSectorsPerEvent + side * 18 + nb[u];
+  const int nb[3] = {side * 18 + (k + 1) % 18, side * 18 + (k + 17) % 18, (1 - side) * 18 + k};
+  for (int u = 0; u < 3; ++u) {
+    const int g = t.event * kSectorsPerEvent + nb[u];
     const uint32_t i1 = off[g * kRows + r_hi + 1];
     for (uint32_t i = off[g * kRows + r_lo]; i < i1; ++i) fn(list[i]);
   }
@@ -442,9 +456,10 @@ __device__ bool chain_pass(const Slot& S, const DevConst& K, const MergeConst& C
     if (j == ch.n - 1) {
       --k;
     } else {
-      const int dir = neighbour(T.sector, S.out_tracks[ch.pos[j + 1]].sector);
+      // from the outer segment's frame to this one's
+      const int dir = neighbour(S.out_tracks[ch.pos[j + 1]].sector, T.sector);
       double x = xrow(K, cur_row);
-      if (!rotate_frame(st, x, C.ca, -(double)dir * C.sa, K.bd, C.smax)) return false;
+      if (!turn_frame(st, x, dir, K, C)) return false;
       const int64_t g = ev0 + h[k];
       const int r = S.row[g];
       if (!transport_to_x(st, x, xrow(K, r), K.bd, C.smax, C.step_max, K.kkd, K.m2d)) return false;
@@ -503,7 +518,7 @@ __device__ bool carry_out(const Slot& S, const DevConst& K, const MergeConst& C,
     x = xo;
     if (j + 1 < ch.n) {
       const int dir = neighbour(T.sector, S.out_tracks[ch.pos[j + 1]].sector);
-      if (!rotate_frame<false>(st, x, C.ca, (double)dir * C.sa, K.bd, C.smax)) return false;
+      if (!turn_frame<false>(st, x, dir, K, C)) return false;
     }
   }
   s0 = st.s;
