@@ -198,9 +198,7 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   m.best_in = c.take<int32_t>(cap_tk);
   m.chi_in = c.take<double>(cap_tk);
   m.in_key = c.take<unsigned long long>(cap_tk);
-  m.pr_n = c.take<int32_t>(cap_tk);
-  m.pr_b = c.take<int32_t>(cap_tk * kMgPairs);
-  m.pr_chi = c.take<double>(cap_tk * kMgPairs);
+  m.out_key = c.take<unsigned long long>(cap_tk);
   m.link_out = c.take<int32_t>(cap_tk);
   m.link_in = c.take<int32_t>(cap_tk);
   m.head_ok = c.take<int32_t>(cap_tk);
@@ -784,18 +782,22 @@ int tpc_merge(tpc_ctx* ctx, int slot, const tpc_merge_params* mp) {
   for (uint32_t* p : {m.in_off, m.out_off}) k_zero_u32<<<grid_stride_blocks(nsr + 1, 256), 256, 0, st>>>(p, nsr + 1);
   for (uint32_t* p : {m.in_cur, m.out_cur}) k_zero_u32<<<grid_stride_blocks(nsr, 256), 256, 0, st>>>(p, nsr);
   k_fill_i32<<<nb, 256, 0, st>>>(m.link_in, K, -1);
-  // per B: smallest chi2 (bit pattern; all ones = none) and its A
-  k_fill_i32<<<grid_stride_blocks(2 * K, 256), 256, 0, st>>>(reinterpret_cast<int32_t*>(m.in_key),
-                                                             2 * K, -1);
-  k_fill_i32<<<nb, 256, 0, st>>>(m.best_in, K, 0x7FFFFFFF);
+  // per track: smallest chi2 as inner and as outer partner (bit pattern;
+  // all ones = none) and the partner reaching it
+  for (unsigned long long* p : {m.in_key, m.out_key})
+    k_fill_i32<<<grid_stride_blocks(2 * K, 256), 256, 0, st>>>(reinterpret_cast<int32_t*>(p),
+                                                               2 * K, -1);
+  for (int32_t* p : {m.best_in, m.best_out}) k_fill_i32<<<nb, 256, 0, st>>>(p, K, 0x7FFFFFFF);
   k_mg_count<<<nb, 256, 0, st>>>(s, m);
   scan_u32(st, m.in_off, nullptr, nsr, s.scan_b, nullptr);
   scan_u32(st, m.out_off, nullptr, nsr, s.scan_b, nullptr);
   k_mg_scatter<<<nb, 256, 0, st>>>(s, m);
   k_mg_outer<<<nbt, 256, 0, st>>>(s, ctx->k, m, C);
-  k_mg_best_out<<<nbt, 256, 0, st>>>(s, ctx->k, m, C);
-  k_mg_best_in<<<nbt, 256, 0, st>>>(s, ctx->k, m, C);
-  k_mg_in_final<<<nb, 256, 0, st>>>(s, m);
+  // one-wave blocks, four tracks each
+  const int nbp = grid_stride_blocks((K + 3) / 4, 1, 16384);
+  k_mg_pairs<false><<<nbp, 64, 0, st>>>(s, ctx->k, m, C);
+  k_mg_pairs<true><<<nbp, 64, 0, st>>>(s, ctx->k, m, C);
+  k_mg_final<<<nb, 256, 0, st>>>(s, m);
   k_mg_link<<<nb, 256, 0, st>>>(s, m);
   k_mg_chain<<<nbt, 256, 0, st>>>(s, ctx->k, m, C);
   k_mg_emit<<<nb, 256, 0, st>>>(s, m);

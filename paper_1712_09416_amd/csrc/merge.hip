@@ -15,8 +15,10 @@
 //     fitted state, chi2 = d^T (C_A + C_B)^-1 d over the 5 parameters.
 //     T and Q do not change under rotation or transport and d_i^2 / S_ii
 //     never exceeds the chi2, so pairs failing the cut on them alone are
-//     skipped before any transport.  Lane per A (best outer partner) and
-//     lane per B (best inner partner), ties to the smaller track position;
+//     skipped before any transport.  Each A's best outer partner and each
+//     B's best inner partner, ties to the smaller track position, from the
+//     pairs evaluated in parallel (a pass for the smallest chi2s, a second
+//     for the partners reaching them);
 //  M3 a pair is linked if each is the other's best; links form chains;
 //  M4 each chain of >= 2 segments is refitted inward over all its hits, in
 //     passes (the first seeded with the outermost segment's outer state,
@@ -315,100 +317,120 @@ __device__ bool pair_chi2(const DevConst& K, const MergeConst& C, const tpc_trac
   return chi2 <= cut;
 }
 
-// Candidates of a track among the tracks of the two neighbouring sectors
-// of its side and of the sector across the membrane, in its event, those
-// whose row (`off` indexes first rows, or last rows) lies in [r_lo, r_hi]:
-// every pair the sector and row conditions of M2 admit.
-template <class Fn>
-__device__ __forceinline__ void for_neighbours(const uint32_t* off, const int32_t* list,
-                                               const tpc_track& t, int r_lo, int r_hi, Fn&& fn) {
-  r_lo = max(r_lo, 0);
-  r_hi = min(r_hi, kRows - 1);
-  if (r_lo > r_hi) return;
-  const int side = t.sector / 18, k = t.sector % 18;
-  const int nb[3] = {side * 18 + (k + 1) % 18, side * 18 + (k + 17) % 18, (1 - side) * 18 + k};
-  for (int u = 0; u < 3; ++u) {
-    const int g = t.event * kSectorsPerEvent + nb[u];
-    const uint32_t i1 = off[g * kRows + r_hi + 1];
-    for (uint32_t i = off[g * kRows + r_lo]; i < i1; ++i) fn(list[i]);
+constexpr int kPairLanes = 16;   // lanes walking one track's candidates
+
+// A compatible pair (A, B): its chi2 lowers A's and B's smallest chi2
+// (kFinal = false; the bit pattern of a non-negative double orders like its
+// value), or, once those are known, offers B as A's best outer partner and
+// A as B's best inner partner where it reaches them (kFinal = true; the
+// smaller track position wins a tie).
+template <bool kFinal>
+__device__ __forceinline__ void pair_eval(const Slot& S, const DevConst& K, const MergeSlot& M,
+                                          const MergeConst& C, int32_t a, int32_t b) {
+  double ch;
+  if (!pair_chi2(K, C, S.out_tracks[a], M.op + (size_t)a * 5, M.oc + (size_t)a * 15,
+                 S.out_tracks[b], ch))
+    return;
+  const unsigned long long key = (unsigned long long)__double_as_longlong(ch);
+  if (!kFinal) {
+    atomicMin(&M.out_key[a], key);
+    atomicMin(&M.in_key[b], key);
+  } else {
+    if (key == M.out_key[a]) atomicMin(&M.best_out[a], b);
+    if (key == M.in_key[b]) atomicMin(&M.best_in[b], a);
   }
 }
 
-// M2 + M3: best outer partner of each A.  Every compatible pair is
-// evaluated here once: its chi2 also lowers B's smallest chi2 (the bit
-// pattern of a non-negative double orders like its value), and the first
-// kMgPairs pairs of A are kept for the pass that picks B's best A.
-__global__ void __launch_bounds__(256) k_mg_best_out(Slot S, DevConst K, MergeSlot M,
-                                                    MergeConst C) {
+// M2 + M3 over every pair the sector and row conditions admit: the tracks
+// of A's event in the two neighbouring sectors of its side and in the
+// sector across the membrane whose first row lies in (A.row_out,
+// A.row_out + row_gap], three runs of in_list.  Each A is walked by
+// kPairLanes lanes of a one-wave block; the pairs that pass the cuts on T
+// and Q (a few in a hundred) queue in LDS, and the wave evaluates them 64
+// at a time, so the frame turn, transport and chi2 run on full waves.  Run
+// twice (kFinal false, then true); the results do not depend on the order
+// in which pairs are met.
+template <bool kFinal>
+__global__ void __launch_bounds__(64) k_mg_pairs(Slot S, DevConst K, MergeSlot M, MergeConst C) {
+  __shared__ int32_t qa[128], qb[128];
+  constexpr int kPerWave = 64 / kPairLanes;
+  const uint32_t ntk = S.out_count[0];
+  const int lane = threadIdx.x;
+  const int gl = lane % kPairLanes;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const double cut = C.chi2_max;
+  int qn = 0;   // queued pairs (the same in every lane)
+  for (uint32_t base = blockIdx.x * kPerWave; base < ntk; base += gridDim.x * kPerWave) {
+    const uint32_t a = base + lane / kPairLanes;
+    uint32_t s0 = 0, s1 = 0, s2 = 0;
+    int c1 = 0, c2 = 0, c3 = 0;
+    double oT = 0.0, oQ = 0.0, vT = 0.0, vQ = 0.0;
+    if (a < ntk && M.ok[a]) {
+      const tpc_track& A = S.out_tracks[a];
+      const int r_lo = A.row_out + 1, r_hi = min(A.row_out + C.row_gap, kRows - 1);
+      if (r_lo <= r_hi) {
+        const int side = A.sector / 18, k = A.sector % 18;
+        const int g = A.event * kSectorsPerEvent;
+        const uint32_t* off = M.in_off;
+        const int ga = (g + side * 18 + (k + 1) % 18) * kRows;
+        const int gb = (g + side * 18 + (k + 17) % 18) * kRows;
+        const int gc = (g + (1 - side) * 18 + k) * kRows;
+        s0 = off[ga + r_lo];
+        s1 = off[gb + r_lo];
+        s2 = off[gc + r_lo];
+        c1 = (int)(off[ga + r_hi + 1] - s0);
+        c2 = c1 + (int)(off[gb + r_hi + 1] - s1);
+        c3 = c2 + (int)(off[gc + r_hi + 1] - s2);
+        oT = M.op[(size_t)a * 5 + 3];
+        oQ = M.op[(size_t)a * 5 + 4];
+        vT = M.oc[(size_t)a * 15 + 9];
+        vQ = M.oc[(size_t)a * 15 + 14];
+      }
+    }
+    for (int i0 = 0; __any(i0 < c3); i0 += kPairLanes) {
+      const int i = i0 + gl;
+      bool pass = false;
+      int32_t b = 0;
+      if (i < c3) {
+        const uint32_t idx = i < c1 ? s0 + i : i < c2 ? s1 + (i - c1) : s2 + (i - c2);
+        b = M.in_list[idx];
+        const tpc_track& B = S.out_tracks[b];
+        // the cuts of pair_chi2 on T and Q, in its arithmetic
+        const double dT = oT - B.par[3], dQ = oQ - B.par[4];
+        pass = !(dT * dT > cut * (vT + B.cov[9])) && !(dQ * dQ > cut * (vQ + B.cov[14]));
+      }
+      const unsigned long long m = __ballot(pass);
+      if (pass) {
+        const int pos = qn + __popcll(m & below);
+        qa[pos] = (int32_t)a;
+        qb[pos] = b;
+      }
+      qn += __popcll(m);
+      if (qn >= 64) {
+        __syncthreads();
+        qn -= 64;
+        pair_eval<kFinal>(S, K, M, C, qa[qn + lane], qb[qn + lane]);
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+  if (lane < qn) pair_eval<kFinal>(S, K, M, C, qa[lane], qb[lane]);
+}
+
+template __global__ void k_mg_pairs<false>(Slot, DevConst, MergeSlot, MergeConst);
+template __global__ void k_mg_pairs<true>(Slot, DevConst, MergeSlot, MergeConst);
+
+// a track without a compatible partner: -1 and chi2 0
+__global__ void k_mg_final(Slot S, MergeSlot M) {
   const uint32_t ntk = S.out_count[0];
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
-    int32_t best = -1;
-    double bc = 0.0;
-    int32_t np = 0;
-    if (M.ok[a]) {
-      const tpc_track& A = S.out_tracks[a];
-      const double* op = M.op + (size_t)a * 5;
-      const double* oc = M.oc + (size_t)a * 15;
-      for_neighbours(M.in_off, M.in_list, A, A.row_out + 1, A.row_out + C.row_gap, [&](int32_t b) {
-        double ch;
-        if (!pair_chi2(K, C, A, op, oc, S.out_tracks[b], ch)) return;
-        atomicMin(&M.in_key[b], (unsigned long long)__double_as_longlong(ch));
-        if (np < kMgPairs) {
-          M.pr_b[(size_t)a * kMgPairs + np] = b;
-          M.pr_chi[(size_t)a * kMgPairs + np] = ch;
-        }
-        ++np;
-        if (best < 0 || ch < bc || (ch == bc && b < best)) {
-          best = b;
-          bc = ch;
-        }
-      });
-    }
-    M.best_out[a] = best;
-    M.chi_out[a] = bc;
-    M.pr_n[a] = np;
-  }
-}
-
-// M2 + M3: best inner partner of each B: among the A whose pair reaches B's
-// smallest chi2, the smaller track position (lane per A, over the pairs the
-// previous pass kept; an A with more than kMgPairs pairs evaluates them again).
-__global__ void __launch_bounds__(256) k_mg_best_in(Slot S, DevConst K, MergeSlot M,
-                                                   MergeConst C) {
-  const uint32_t ntk = S.out_count[0];
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < ntk; a += stride) {
-    const int32_t np = M.pr_n[a];
-    if (np == 0) continue;
-    auto offer = [&](int32_t b, double ch) {
-      if ((unsigned long long)__double_as_longlong(ch) == M.in_key[b])
-        atomicMin(&M.best_in[b], (int32_t)a);
-    };
-    if (np <= kMgPairs) {
-      for (int k = 0; k < np; ++k)
-        offer(M.pr_b[(size_t)a * kMgPairs + k], M.pr_chi[(size_t)a * kMgPairs + k]);
-    } else {
-      const tpc_track& A = S.out_tracks[a];
-      const double* op = M.op + (size_t)a * 5;
-      const double* oc = M.oc + (size_t)a * 15;
-      for_neighbours(M.in_off, M.in_list, A, A.row_out + 1, A.row_out + C.row_gap, [&](int32_t b) {
-        double ch;
-        if (pair_chi2(K, C, A, op, oc, S.out_tracks[b], ch)) offer(b, ch);
-      });
-    }
-  }
-}
-
-// B without a compatible A: -1 and chi2 0
-__global__ void k_mg_in_final(Slot S, MergeSlot M) {
-  const uint32_t ntk = S.out_count[0];
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < ntk; b += stride) {
-    const unsigned long long key = M.in_key[b];
-    const bool none = key == ~0ull;
-    M.chi_in[b] = none ? 0.0 : __longlong_as_double((long long)key);
-    if (none) M.best_in[b] = -1;
+    const unsigned long long ki = M.in_key[a], ko = M.out_key[a];
+    M.chi_in[a] = ki == ~0ull ? 0.0 : __longlong_as_double((long long)ki);
+    if (ki == ~0ull) M.best_in[a] = -1;
+    M.chi_out[a] = ko == ~0ull ? 0.0 : __longlong_as_double((long long)ko);
+    if (ko == ~0ull) M.best_out[a] = -1;
   }
 }
 
@@ -424,102 +446,167 @@ __global__ void k_mg_link(Slot S, MergeSlot M) {
   }
 }
 
+// A chain's segments, innermost first: where each one's hit list starts in
+// out_hits, its hit count, sector and first and last pad rows (the rows of
+// its first and last hit).  Read once per chain; every pass walks these.
 struct Chain {
   int n;
-  int32_t pos[kMaxChain];
+  int64_t ev0;                   // the event's first cluster
+  int64_t hoff[kMaxChain];
+  int32_t nh[kMaxChain];
+  uint8_t sec[kMaxChain], rin[kMaxChain], rout[kMaxChain];
 };
 
-// one inward pass over the chain, seeded with (s0, t0, q0) at the
-// outermost hit
+// One inward pass over the chain, seeded with (s0, t0, q0) at the
+// outermost hit.  The pass is one flat loop of transport steps, each a row
+// step inside a segment or one of the equal steps from a turned frame to
+// the next segment's outermost hit, followed by an update where the step
+// ends on a hit.  The lanes of a wave thus stay in step through segment
+// changes, which fall at different rows for different chains (a loop over
+// segments with a row loop inside would hold every lane of a wave in each
+// segment until the longest one of the wave ends).
 __device__ bool chain_pass(const Slot& S, const DevConst& K, const MergeConst& C, const Chain& ch,
                            double s0, double t0, double q0, Helix<double>& out, double& chi2,
                            int& n) {
-  const tpc_track L = S.out_tracks[ch.pos[ch.n - 1]];
-  const int64_t evL = S.ev_off[L.event];
-  const int32_t* hl = track_hits(S, L);
-  const int64_t go = evL + hl[L.n_hits - 1];
+  const int64_t ev0 = ch.ev0;
+  int j = ch.n - 1;
+  const int32_t* h = S.out_hits + ch.hoff[j];
+  int k = ch.nh[j] - 1;
+  int sector = ch.sec[j];
+  int cur_row = ch.rout[j];
   Helix<double> st;
-  st.y = (double)S.y[go];
-  st.z = (double)S.z[go];
+  {
+    const int64_t go = ev0 + h[k];
+    st.y = (double)S.y[go];
+    st.z = (double)S.z[go];
+  }
   st.s = s0;
   st.t = t0;
   st.q = q0;
   prior_d(K, st, st.z);
   chi2 = 0.0;
   n = 1;
-  int cur_row = S.row[go];
-  for (int j = ch.n - 1; j >= 0; --j) {
-    const tpc_track T = S.out_tracks[ch.pos[j]];
-    const int64_t ev0 = S.ev_off[T.event];
-    const int32_t* h = track_hits(S, T);
-    int k = T.n_hits - 1;
-    if (j == ch.n - 1) {
-      --k;
-    } else {
-      // from the outer segment's frame to this one's
-      const int dir = neighbour(S.out_tracks[ch.pos[j + 1]].sector, T.sector);
+  --k;
+  // the row walk through the segment's hits h[k..0] below cur_row (one hit
+  // per row, rows strictly descending).  Every read of a step is issued at
+  // its top and used after the transport: the radius of the next row (the
+  // current one carried in a register), the next hit's coordinates, the row
+  // of the hit after it and the list entry after that (indices clamped to
+  // h[0]).
+  int r, rn, rstop;
+  int64_t gn;
+  int32_t h_after;
+  double x_hi;
+  float x_next;
+  auto walk_from = [&](int row) {
+    r = row - 1;
+    x_hi = xrow(K, row);
+    x_next = K.row_x[max(row - 1, 0)];
+    const int kk = max(k, 0);
+    gn = ev0 + h[kk];
+    rn = k >= 0 ? (int)S.row[gn] : -1;
+    h_after = h[max(k - 1, 0)];
+    rstop = k >= 0 ? (int)ch.rin[j] : row;
+  };
+  walk_from(cur_row);
+  // equal steps left to the outermost hit of the segment entered last
+  int sub = 0;
+  double dxb = 0.0;
+  float by = 0.f, bz = 0.f;
+  for (;;) {
+    if (sub == 0 && r < rstop) {
+      // segment done: turn into the next segment's frame and aim at its
+      // outermost hit in steps of at most step_max
+      if (j == 0) break;
+      --j;
+      const int dir = neighbour(sector, ch.sec[j]);
+      sector = ch.sec[j];
       double x = xrow(K, cur_row);
       if (!turn_frame(st, x, dir, K, C)) return false;
+      h = S.out_hits + ch.hoff[j];
+      k = ch.nh[j] - 1;
       const int64_t g = ev0 + h[k];
-      const int r = S.row[g];
-      if (!transport_to_x(st, x, xrow(K, r), K.bd, C.smax, C.step_max, K.kkd, K.m2d)) return false;
-      chi2 = chi2 + update_hit(S, K, st, g);
-      ++n;
-      cur_row = r;
+      by = S.y[g];
+      bz = S.z[g];
+      const int rb = ch.rout[j];
+      const double d = xrow(K, rb) - x;
+      if (!(fabs(d) <= 1000.0)) return false;
+      sub = max(1, (int)ceil(fabs(d) / C.step_max));
+      dxb = d / (double)sub;
+      // after the update at that hit, the walk continues below its row
+      cur_row = rb;
       --k;
+      walk_from(rb);
     }
-    // the segment's remaining hits h[k..0], inward (one hit per row, rows
-    // strictly descending), as a walk of row steps.  Every read of a step
-    // is issued at its top and used after the transport: the radius of the
-    // next row (the current one carried in a register), the next hit's
-    // coordinates, the row of the hit after it and the list entry after
-    // that (indices clamped to h[0]).
-    if (k >= 0) {
-      int64_t gn = ev0 + h[k];
-      int rn = S.row[gn];
-      int32_t h_after = h[max(k - 1, 0)];
-      const int rstop = S.row[ev0 + h[0]];
-      double x_hi = xrow(K, cur_row);
-      float x_next = K.row_x[max(cur_row - 1, 0)];
-      for (int r = cur_row - 1; r >= rstop; --r) {
-        const double x_lo = (double)x_next;
-        x_next = K.row_x[max(r - 1, 0)];
-        const float hy = S.y[gn], hz = S.z[gn];
-        const int64_t g_after = ev0 + h_after;
-        const int r_after = S.row[g_after];
-        const int32_t h_after2 = h[max(k - 2, 0)];
-        if (!transport(st, x_lo - x_hi, K.bd, C.smax, K.kkd, K.m2d)) return false;
-        x_hi = x_lo;
-        if (r != rn) continue;
-        chi2 = chi2 + update_yz(K, st, hy, hz);
-        ++n;
+    double dx;
+    float hy, hz;
+    bool upd;
+    int64_t g_after = 0;
+    int r_after = 0;
+    int32_t h_after2 = 0;
+    const bool walking = sub == 0;
+    if (walking) {
+      const double x_lo = (double)x_next;
+      x_next = K.row_x[max(r - 1, 0)];
+      hy = S.y[gn];
+      hz = S.z[gn];
+      g_after = ev0 + h_after;
+      r_after = S.row[g_after];
+      h_after2 = h[max(k - 2, 0)];
+      dx = x_lo - x_hi;
+      x_hi = x_lo;
+      upd = r == rn;
+    } else {
+      dx = dxb;
+      hy = by;
+      hz = bz;
+      upd = --sub == 0;
+    }
+    if (!transport(st, dx, K.bd, C.smax, K.kkd, K.m2d)) return false;
+    if (upd) {
+      chi2 = chi2 + update_yz(K, st, hy, hz);
+      ++n;
+    }
+    if (walking) {
+      if (upd) {
         cur_row = r;
         --k;
         gn = g_after;
         rn = k >= 0 ? r_after : -1;
         h_after = h_after2;
       }
+      --r;
     }
   }
   out = st;
   return true;
 }
 
-// the inner result of a pass carried out to the outermost hit (the next
-// pass resets the covariance, so only its parameters matter)
-__device__ bool carry_out(const Slot& S, const DevConst& K, const MergeConst& C, const Chain& ch,
+// The inner result of a pass carried out to the outermost hit (the next
+// pass resets the covariance, so only its parameters matter): through each
+// segment to its last row in equal steps of at most step_max, turning
+// frames between segments; one flat loop of steps, as the pass.
+__device__ bool carry_out(const DevConst& K, const MergeConst& C, const Chain& ch,
                           Helix<double> st, double& s0, double& t0, double& q0) {
-  const tpc_track F = S.out_tracks[ch.pos[0]];
-  double x = xrow(K, S.row[S.ev_off[F.event] + track_hits(S, F)[0]]);
-  for (int j = 0; j < ch.n; ++j) {
-    const tpc_track T = S.out_tracks[ch.pos[j]];
-    const double xo = xrow(K, S.row[S.ev_off[T.event] + track_hits(S, T)[T.n_hits - 1]]);
-    if (!transport_to_x<false>(st, x, xo, K.bd, C.smax, C.step_max, K.kkd, K.m2d)) return false;
+  double x = xrow(K, ch.rin[0]);
+  int j = 0;
+  double xo = xrow(K, ch.rout[0]);
+  double d = xo - x;
+  if (!(fabs(d) <= 1000.0)) return false;
+  int sub = max(1, (int)ceil(fabs(d) / C.step_max));
+  double dxs = d / (double)sub;
+  for (;;) {
+    if (!transport<double, false>(st, dxs, K.bd, C.smax, K.kkd, K.m2d)) return false;
+    if (--sub > 0) continue;
     x = xo;
-    if (j + 1 < ch.n) {
-      const int dir = neighbour(T.sector, S.out_tracks[ch.pos[j + 1]].sector);
-      if (!turn_frame<false>(st, x, dir, K, C)) return false;
-    }
+    if (++j == ch.n) break;
+    const int dir = neighbour(ch.sec[j - 1], ch.sec[j]);
+    if (!turn_frame<false>(st, x, dir, K, C)) return false;
+    xo = xrow(K, ch.rout[j]);
+    d = xo - x;
+    if (!(fabs(d) <= 1000.0)) return false;
+    sub = max(1, (int)ceil(fabs(d) / C.step_max));
+    dxs = d / (double)sub;
   }
   s0 = st.s;
   t0 = st.t;
@@ -537,14 +624,22 @@ __global__ void __launch_bounds__(256) k_mg_chain(Slot S, DevConst K, MergeSlot 
     Chain ch;
     ch.n = 0;
     bool fits = true;
+    int32_t last = (int32_t)a;
     for (int32_t p = (int32_t)a; p >= 0; p = M.link_out[p]) {
       if (ch.n == kMaxChain) {
         fits = false;
         break;
       }
-      ch.pos[ch.n++] = p;
+      const tpc_track& T = S.out_tracks[p];
+      if (ch.n == 0) ch.ev0 = S.ev_off[T.event];
+      ch.hoff[ch.n] = (int64_t)S.ev_hit_off[T.event] + T.hit_off;
+      ch.nh[ch.n] = T.n_hits;
+      ch.sec[ch.n] = (uint8_t)T.sector;
+      ch.rin[ch.n] = (uint8_t)T.row_in;
+      ch.rout[ch.n] = (uint8_t)T.row_out;
+      ++ch.n;
+      last = p;
     }
-    const int32_t last = ch.pos[ch.n - 1];
     bool good = fits && M.ok[last] != 0;
     double s0 = M.op[(size_t)last * 5 + 2], t0 = M.op[(size_t)last * 5 + 3],
            q0 = M.op[(size_t)last * 5 + 4];
@@ -552,7 +647,7 @@ __global__ void __launch_bounds__(256) k_mg_chain(Slot S, DevConst K, MergeSlot 
     double chi2 = 0.0;
     int nh = 0;
     for (int pass = 0; pass < C.passes && good; ++pass) {
-      if (pass > 0) good = carry_out(S, K, C, ch, res, s0, t0, q0);
+      if (pass > 0) good = carry_out(K, C, ch, res, s0, t0, q0);
       if (good) good = chain_pass(S, K, C, ch, s0, t0, q0, res, chi2, nh);
     }
     if (!good) continue;

@@ -196,10 +196,8 @@ struct MergeSlot {
   double* chi_out;          // [K]
   int32_t* best_in;         // [K] best inner partner, -1 none
   double* chi_in;           // [K]
-  unsigned long long* in_key;  // [K] per B: bits of the smallest chi2 of a compatible A (~0: none)
-  int32_t* pr_n;            // [K] per A: compatible B's found
-  int32_t* pr_b;            // [K][kMgPairs] the first of them
-  double* pr_chi;           // [K][kMgPairs] and their chi2
+  unsigned long long* in_key;   // [K] per B: bits of the smallest chi2 of a compatible A (~0: none)
+  unsigned long long* out_key;  // [K] per A: the same over its compatible B's
   int32_t* link_out;        // [K] mutual best outer partner, -1 none
   int32_t* link_in;         // [K]
   int32_t* head_ok;         // [K] per chain head: chain of >= 2 segments refitted
@@ -217,8 +215,6 @@ struct MergeSlot {
   uint32_t* ev_track_off;   // [E+1]
   uint32_t* ev_hit_off;     // [E+1]
 };
-
-constexpr int kMgPairs = 4;   // compatible partners kept per track for the inner-best pass
 
 // Constants of one merge call.
 struct MergeConst {

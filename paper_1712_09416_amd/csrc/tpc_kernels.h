@@ -46,9 +46,9 @@ __global__ void k_write_out(Slot S, DevConst K);
 __global__ void k_mg_count(Slot S, MergeSlot M);
 __global__ void k_mg_scatter(Slot S, MergeSlot M);
 __global__ void k_mg_outer(Slot S, DevConst K, MergeSlot M, MergeConst C);
-__global__ void k_mg_best_out(Slot S, DevConst K, MergeSlot M, MergeConst C);
-__global__ void k_mg_best_in(Slot S, DevConst K, MergeSlot M, MergeConst C);
-__global__ void k_mg_in_final(Slot S, MergeSlot M);
+template <bool kFinal>
+__global__ void k_mg_pairs(Slot S, DevConst K, MergeSlot M, MergeConst C);
+__global__ void k_mg_final(Slot S, MergeSlot M);
 __global__ void k_mg_link(Slot S, MergeSlot M);
 __global__ void k_mg_chain(Slot S, DevConst K, MergeSlot M, MergeConst C);
 __global__ void k_mg_emit(Slot S, MergeSlot M);
