@@ -441,12 +441,13 @@ def main() -> int:
     st = trk.stream
     torch.cuda.synchronize()
 
-    def run_steps(pool, k_steps):
+    def run_steps(pool, k_steps, merge=False):
         """k_steps steps, step i on pool[i % len(pool)], with the library's
         stage events on (HIP events between the stages on each tracker's
-        stream, no synchronisation).  Returns the host wall time, the per-step
-        HIP-event latencies, the per-stage means over these steps (averaged
-        over the trackers) and the work counters."""
+        stream, no synchronisation); with merge, each step also runs the
+        cross-sector merger on its event.  Returns the host wall time, the
+        per-step HIP-event latencies, the per-stage means over these steps
+        (averaged over the trackers) and the work counters."""
         for t in pool:
             t.set_profiling(True)
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -458,6 +459,8 @@ def main() -> int:
             e0.record(t.stream)
             t.load(0, *ins)
             t.track_event(0)
+            if merge:
+                t.merge(0)
             e1.record(t.stream)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - w0) * 1e3
@@ -494,11 +497,25 @@ def main() -> int:
             if k >= 2:
                 e2e.append((time.perf_counter() - t0) * 1e3)
 
+    # tracking and merging each event, the same events in flight: the
+    # merger's latency-bound kernels share the GPU with the other events'
+    merge_inflight = None
+    if args.merge_reps > 0 and args.steps > 0:
+        wall_m, lat_m, _, _ = run_steps(trks, args.steps, merge=True)
+        merge_inflight = {"ms_per_step": wall_m / args.steps,
+                          "clusters_per_s": ev.n / (wall_m / args.steps * 1e-3),
+                          "p50_ms": float(np.percentile(lat_m, 50)),
+                          "events_in_flight": n_fl}
+
     tracks, hits = trk.get_tracks(0)
-    for t in trks[1:]:
-        th, hh = t.get_tracks(0)
-        assert np.array_equal(hh, hits) and np.array_equal(th["par"], tracks["par"]), \
-            "trackers of the pipelined run disagree"
+    # the trackers of the pipeline that tracked the event (fewer than
+    # n_fl when the run has fewer steps)
+    n_ran = min(n_fl, max(args.steps, args.warmup))
+    for i, t in enumerate(trks[1:], start=1):
+        if i < n_ran:
+            th, hh = t.get_tracks(0)
+            assert np.array_equal(hh, hits) and np.array_equal(th["par"], tracks["par"]), \
+                "trackers of the pipelined run disagree"
         t.close()
     # whole-job rate from the host clock around the synchronised region
     ms_per_step = wall_ms / args.steps
@@ -524,7 +541,8 @@ def main() -> int:
         torch.cuda.synchronize()
         mt, mh, mseg = trk.get_merged(0)
         merge = {"ms": m0.elapsed_time(m1) / args.merge_reps, "tracks_in": int(len(tracks)),
-                 "tracks_out": int(len(mt)), "chains": int((mseg > 1).sum())}
+                 "tracks_out": int(len(mt)), "chains": int((mseg > 1).sum()),
+                 "track_and_merge_in_flight": merge_inflight}
 
     # plain: the same event with the per-sector launch sequence
     plain = None
