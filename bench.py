@@ -580,13 +580,17 @@ def main() -> int:
         shares["hbm"] = traffic / t_tl / 1e9 / HBM_PEAK_GBS
     if valu is not None:
         shares["alu"] = valu / t_tl / 1e9 / VALU_PEAK_GINST_S
-    bound = max(shares, key=shares.get) if shares else "hbm"
+    # no counters for these kernel sources: the limiter is not named
+    bound = max(shares, key=shares.get) if shares else None
     roof = {"bound": bound, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_tracklets",
             "algorithmic_bytes": tracklet_bytes(counters),
             "bytes_formula": "20 x row visits + 14 x tracklet hits",
             "launch_ms": stage_ms["tracklets"], "copy_kernel_gbs": copy_gbs,
             "limiter_shares": shares,
+            "limiter_note": ("VALU issue share vs L2-miss traffic share of the HBM peak, from "
+                             "the committed counters" if shares else
+                             "counters were taken on other kernel sources: limiter unmeasured"),
             "traffic_note": "traffic = L2-miss bytes (FETCH_SIZE + WRITE_SIZE, scaled by a "
                             "copy kernel), most of it served by the Infinity Cache"}
     if traffic is not None:
