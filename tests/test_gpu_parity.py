@@ -624,17 +624,21 @@ def merge_case(trk, slot, event, ev, oracle_lib, geometry=None):
     return ref
 
 
-@pytest.mark.parametrize("kind", ["pp", "peripheral", "central", "membrane"])
+@pytest.mark.parametrize("kind", ["pp", "peripheral", "central", "membrane", "jet"])
 def test_merge_matches_oracle(dev, oracle_lib, kind):
     """Merged tracks, hit lists, segment counts, links and best-candidate
     chi2 bit-identical to the oracle's merger run on the same tracks (which
     are themselves bit-identical to the oracle's tracker); the membrane
-    workload's twelve segment pairs across z = 0 are all joined."""
+    workload's twelve segment pairs across z = 0 are all joined.  In the
+    boundary jet every segment pair of the crossing passes the T and Q cuts,
+    so a wave's four tracks queue well over 64 pairs (the LDS queue is
+    evaluated full many times, as well as at the end)."""
     from paper_1712_09416_amd import Tracker
     ev = {"pp": lambda: tpcgen.pp_event(),
           "peripheral": lambda: tpcgen.pbpb_event(tpcgen.seed_for(4, 101), 2000),
           "central": lambda: tpcgen.central_event(),
-          "membrane": lambda: tpcgen.membrane_event()}[kind]()
+          "membrane": lambda: tpcgen.membrane_event(),
+          "jet": lambda: tpcgen.boundary_jet_event()}[kind]()
     trk = Tracker(ev.geometry(), max_clusters=ev.n)
     ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.sector, ev.row, ev.y, ev.z)]
     trk.load(0, *ins)
@@ -645,6 +649,8 @@ def test_merge_matches_oracle(dev, oracle_lib, kind):
         assert (ref.n_segments > 1).sum() > 100
     if kind == "membrane":
         assert len(ref.tracks) == 12 and np.all(ref.n_segments == 2)
+    if kind == "jet":
+        assert (ref.n_segments > 1).sum() >= 60
     # a second merge of the same tracking gives the same output
     trk.merge(0)
     gt, gh, gseg = trk.get_merged(0, 0)

@@ -268,3 +268,28 @@ def test_membrane_crossing_segments_are_joined(oracle_lib):
         tr = ev.truth[int(t["inner_id"])]
         var = np.asarray(t["cov"])[[0, 2, 5, 9, 14]]
         assert np.all(np.abs((np.asarray(t["par"]) - tr) / np.sqrt(var)) < 5.0), k
+
+
+def test_boundary_jet_is_joined_by_position(oracle_lib):
+    """A jet of tracks of one momentum turning across a sector boundary:
+    every segment pair of the crossing passes the cuts on T and Q (tens of
+    candidates per segment), so only the fitted positions and angles pick
+    the partners.  Every link joins two segments of one particle, and most
+    particles that left a segment on each side are joined."""
+    ev = tpcgen.boundary_jet_event()
+    r, m = _merge_case(oracle_lib, ev)
+    n = len(r.tracks)
+    maj = [_majority(ev, r.track_hits(k))[0] for k in range(n)]
+    links = [(a, b) for a in range(n) if (b := m.link_out[a]) >= 0]
+    assert len(links) >= 60
+    assert all(maj[a] == maj[b] >= 0 for a, b in links)
+    # the cuts on T and Q leave many candidates: the match decides
+    sec = r.tracks["sector"].astype(int)
+    crossing = Counter(maj[k] for k in range(n) if sec[k] in (0, 1) and maj[k] >= 0)
+    both = [p for p, c in crossing.items()
+            if {int(s) for s in sec[[k for k in range(n) if maj[k] == p]]} >= {0, 1}]
+    joined = {maj[a] for a, _ in links}
+    assert len(joined & set(both)) >= 0.8 * len(both), (len(joined & set(both)), len(both))
+    for k in np.nonzero(m.n_segments > 1)[0]:
+        ids = m.track_hits(k)
+        assert Counter(ev.pid[ids].tolist()).most_common(1)[0][1] >= 0.9 * len(ids)

@@ -350,6 +350,23 @@ def membrane_event(seed=20261205, n_tracks=12, noise_frac=0.05) -> Event:
     return build_event("membrane", seed, p, G.SIGMA_PP, noise_frac, 1.0, rng)
 
 
+def boundary_jet_event(seed=20261206, n_tracks=150) -> Event:
+    """Negative tracks of one momentum (pT 0.8 GeV/c, eta 0.3) from vertices
+    spread along the beam (z 60 cm either side), launched at 11.4-12.4
+    degrees so that they turn across the boundary of sectors 0 and 1 near
+    150 cm: every segment pair there passes the merger's cuts on T and Q
+    (a segment has up to ~70 such candidates), and only the position match
+    picks the partner."""
+    rng = np.random.default_rng(seed)
+    p = _particles(rng, n_tracks, np.full(n_tracks, 0.8), 0.0, 1.0, 0.0, 1.0, kind=0)
+    k = np.arange(n_tracks)
+    p["phi"] = np.deg2rad(11.4 + 1.0 * ((k * 37) % n_tracks + 0.5) / n_tracks)
+    p["eta"] = np.full(n_tracks, 0.3)
+    p["vz"] = -60.0 + 120.0 * (k + 0.5) / n_tracks
+    p["charge"] = np.full(n_tracks, -1.0)
+    return build_event("boundary_jet", seed, p, G.SIGMA_PP, 0.02, 1.0, rng)
+
+
 def batch_multiplicities(n_events=64, seed=None) -> np.ndarray:
     seed = seed_for(CFG_BATCH) if seed is None else seed
     rng = np.random.default_rng(seed)
