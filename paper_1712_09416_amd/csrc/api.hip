@@ -502,7 +502,9 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
   if (marks) mark(ctx, 5);
   // four waves per block: a block's waves go to the four SIMDs of one CU,
   // so the few hundred working waves of an event do not share SIMDs
-  k_refit<<<grid_stride_blocks(std::max<int64_t>(1, tl_bound / 4), 256, 1024), 256, 0, st>>>(s, ctx->k, g0, ns);
+  // a multiple of 8 blocks: each XCD strides over its chunk of the tracks
+  const int nb_ref = (grid_stride_blocks(std::max<int64_t>(1, tl_bound / 4), 256, 1024) + 7) / 8 * 8;
+  k_refit<<<nb_ref, 256, 0, st>>>(s, ctx->k, g0, ns);
   if (marks) mark(ctx, 6);
   TPC_LAUNCHED();
   return TPC_OK;

@@ -244,9 +244,17 @@ __global__ void __launch_bounds__(256) k_refit(Slot S, DevConst K, int g0, int n
   const uint32_t tk0 = S.tk_base[g0];
   // tracks past the region were not written (capacity error raised)
   const uint32_t total = min(S.range_cnt[1], S.tk_base[g0 + ns] - tk0);
-  const uint32_t stride = gridDim.x * blockDim.x;
+  // each XCD (blocks are dispatched round-robin over the 8) a contiguous
+  // chunk of the tracks, which are in sector order: a sector's hits are read
+  // through one XCD's L2
+  constexpr uint32_t kXcd = 8;
+  const uint32_t xcd = blockIdx.x % kXcd, jb = blockIdx.x / kXcd;
+  const uint32_t nbx = (gridDim.x - xcd + kXcd - 1) / kXcd;
+  const uint32_t chunk = (total + kXcd - 1) / kXcd;
+  const uint32_t c0 = min(total, xcd * chunk);
+  const uint32_t c1 = min(total, c0 + chunk);
   unsigned nfit = 0;
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+  for (uint32_t t = c0 + jb * blockDim.x + threadIdx.x; t < c1; t += nbx * blockDim.x) {
     ++nfit;
     const uint32_t k = tk0 + t;
     const int32_t T = S.tk_tracklet[k];
