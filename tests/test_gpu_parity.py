@@ -507,7 +507,8 @@ def test_min_track_length_three_matches_oracle(dev, oracle_lib):
     accepted): every tracklet and track region is sized for n / 3 entries,
     so the fused, per-sector and
     multi-stream sequences stay inside their sectors' regions; links, hit
-    lists and parameters identical to the oracle run with the same cuts.
+    lists and parameters identical to the oracle run with the same cuts, and
+    the merger over these short segments identical to the oracle's.
     The replay bar is checked on the tracks of ten hits or more: below
     that, the oracle's own three-pass double refit from the float seed
     differs from the all-double replay by up to 1.1e-3 (3-4 hit tracks,
@@ -527,6 +528,10 @@ def test_min_track_length_three_matches_oracle(dev, oracle_lib):
         compare_links(lk, ref)
         compare_tracks(tracks, hits, ref)
         compare_replay(tracks, ref.replay, min_hits=10)
+    # the merger over segments as short as three hits
+    trk.merge(0)
+    mref = merge_case(trk, 0, 0, ev, oracle_lib)
+    assert (mref.n_segments > 1).sum() > 0
     trk.close()
     # one sector holding a track per five clusters
     ev = short_segments_event()
