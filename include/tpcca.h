@@ -223,7 +223,7 @@ int tpc_track_event_streams(tpc_ctx* ctx, int slot, int n_streams);
  * would, with no context and no caller workspace.  The workspace is a fixed
  * 64 MiB array of device memory inside the library, one per GPU, held from
  * the first call on that GPU until the process ends; the event must fit in
- * it (about 150,000 clusters with the default params; TPC_ENOMEM beyond,
+ * it (about 185,000 clusters with the default params; TPC_ENOMEM beyond,
  * before anything is enqueued).  No device memory is allocated or freed and
  * no memset or copy node is enqueued: kernels only, on hip_stream
  * (asynchronous).  g, p: host; p's max_slots / max_events / max_clusters are
