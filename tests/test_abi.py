@@ -225,7 +225,7 @@ def test_tracklet_regions_sized_for_n_min_chain(L):
 def test_noalloc_checks_before_device_work(L):
     """The allocation-free entry refuses, before any device call, a missing
     status array, an event too large for its fixed workspace and bad
-    params (an event of 400,000 clusters needs ~170 MB of workspace)."""
+    params (an event of 400,000 clusters needs ~145 MB of workspace)."""
     g = make_geometry(tpcgen.geometry.geometry_dict())
     p = default_params()
     a = np.zeros(16, np.uint32)
