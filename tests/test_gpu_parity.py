@@ -546,6 +546,39 @@ def test_min_track_length_three_matches_oracle(dev, oracle_lib):
     trk.close()
 
 
+# cuts and detector constants other than the defaults: (params, geometry)
+NONDEFAULT = {
+    "tight": (dict(nf_window=2.0, nf_mmax=9.0, chi2_max=9.0, k_win=3.0, w_max=3.0, n_gap=3), {}),
+    "loose": (dict(nf_window=4.5, nf_mmax=25.0, chi2_max=25.0, k_win=5.0, w_max=8.0, s_max=0.9,
+                   c_s0=0.5, c_t0=2.0, c_q0=50.0, m_edge=0.5, m_z=2.0, n_gap=8,
+                   n_min_tracklet=8, n_min_track=8, n_min_chain=5), {}),
+    "reversed_field": ({}, dict(bz_tesla=np.float32(-0.5))),
+    "sigma_and_drift": ({}, dict(sigma_y0=np.float32(0.15), sigma_y1=np.float32(0.05),
+                                 sigma_z0=np.float32(0.2), sigma_z1=np.float32(0.05),
+                                 z_max=np.float32(245.0))),
+}
+
+
+@pytest.mark.parametrize("case", sorted(NONDEFAULT))
+def test_nondefault_constants_match_oracle(dev, oracle_lib, case):
+    """Every cut and detector constant reaches the kernels from the
+    parameters and the geometry (none is compiled in): with tighter and
+    looser cuts than the defaults, the magnetic field reversed, and another
+    cluster-error model and drift length, links, hit lists and parameters
+    equal the oracle's run with the same values."""
+    cuts, g = NONDEFAULT[case]
+    ev = tpcgen.pbpb_event(tpcgen.seed_for(2) + 77, 800)
+    geo = dict(ev.geometry(), **g)
+    ref = oracle_lib.run(ev.sector, ev.row, ev.y, ev.z, geo, precision=32, replay=True,
+                         nthreads=ORACLE_THREADS, params=oracle_lib.make_params(**cuts))
+    say(f"{case}: {ev.n} clusters, {len(ref.tracks)} tracks")
+    assert len(ref.tracks) > 1000 and ref.replay_bad == 0
+    tracks, hits, lk = gpu_run(ev, dev, geometry=geo, **cuts)
+    compare_links(lk, ref)
+    compare_tracks(tracks, hits, ref)
+    compare_replay(tracks, ref.replay)
+
+
 def test_track_events_and_submit(dev, oracle_lib):
     """tpc_track_events over three slots (captured on the first call, then
     replayed; a re-staged slot is captured again) and tpc_submit (graph
