@@ -696,6 +696,35 @@ def test_merge_matches_oracle(dev, oracle_lib, kind):
     trk.close()
 
 
+@pytest.mark.parametrize("over", [dict(chi2_max=10.0, row_gap=6, step_max=1.0, passes=2, s_max=0.99),
+                                  dict(chi2_max=60.0, row_gap=20, step_max=4.0, passes=4)],
+                         ids=["tight", "loose"])
+def test_merge_params_match_oracle(dev, oracle_lib, over):
+    """Merge cuts other than the defaults (match chi2, row gap, transport
+    step, refit passes, |sin phi| bound) reach the kernels: the merged
+    output equals the oracle's merger with the same values."""
+    from paper_1712_09416_amd import Tracker
+    ev = tpcgen.pbpb_event(tpcgen.seed_for(4, 101), 2000)
+    trk = Tracker(ev.geometry(), max_clusters=ev.n)
+    ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.sector, ev.row, ev.y, ev.z)]
+    trk.load(0, *ins)
+    trk.track_event(0)
+    trk.merge(0, **over)
+    tracks, hits = trk.get_tracks(0, 0)
+    gt, gh, gseg = trk.get_merged(0, 0)
+    lk = trk.merge_links(0, 0, len(tracks))
+    ref = oracle_lib.merge(as_oracle_tracks(tracks, oracle_lib), hits, ev.row, ev.y, ev.z,
+                           ev.geometry(), **over)
+    say(f"merge {over}: {len(tracks)} -> {len(gt)} tracks")
+    assert (ref.n_segments > 1).sum() > 50
+    assert np.array_equal(lk["best_out"], ref.best_out)
+    assert np.array_equal(lk["best_chi2"][ref.best_out >= 0], ref.best_chi2[ref.best_out >= 0])
+    assert np.array_equal(lk["link_out"], ref.link_out)
+    assert np.array_equal(lk["merged_into"], ref.merged_into)
+    compare_merged(gt, gh, gseg, ref)
+    trk.close()
+
+
 def test_merge_batch_equals_single(dev, oracle_lib):
     """Merging a batch slot gives each event its own single-event merge."""
     from paper_1712_09416_amd import Tracker
