@@ -140,7 +140,8 @@ def bench_batch(evs, geo, dev, steps: int) -> dict:
     """64 events of uneven size (Pb-Pb shape, multiplicity log-uniform
     50-15000): tracked together in one slot (one launch per step over all
     2304 sectors), replayed from a HIP graph, with the grid knobs autotuned
-    on the batch; compared with the same slot without the graph, with one
+    on the batch; the same events over 2-4 slots replayed in flight on their
+    own streams; compared with the one slot without the graph, with one
     event at a time (fused launches) and with the plain per-sector launch
     sequence."""
     import numpy as np
@@ -176,6 +177,40 @@ def bench_batch(evs, geo, dev, steps: int) -> dict:
     trk.launch(0)
     ms_graph = timed(lambda: trk.launch(0), steps)
 
+    # the same 64 events over k slots in flight: k trackers (streams), each
+    # replaying the graph of its share of the events (largest first, dealt
+    # round-robin), so one slot's latency-bound tails overlap the others'
+    # work; the host clock around the synchronised replays
+    sizes = offs[1:] - offs[:-1]
+    order = np.argsort(-sizes, kind="stable")
+    inflight = {}
+    for k in (2, 3, 4):
+        pool = []
+        for j in range(k):
+            idx = np.sort(order[j::k])
+            sub_off = np.concatenate([[0], np.cumsum(sizes[idx])]).astype(np.int64)
+            sub = [torch.cat([c[offs[i]:offs[i + 1]] for i in idx]) for c in cat]
+            t = Tracker(geo, max_events=len(idx), max_clusters=max(1, int(sub_off[-1])),
+                        **tune["best"])
+            t.load_batch(0, sub_off, *sub)
+            t.capture(0)
+            t.launch(0)
+            pool.append((t, sub))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for t, _sub in pool:
+                t.launch(0)
+        torch.cuda.synchronize()
+        inflight[k] = (time.perf_counter() - t0) * 1e3 / steps
+        nt_k = sum(len(t.get_tracks(0, e)[0]) for t, sub in pool
+                   for e in range(t.params.max_events))
+        assert nt_k == ntracks, ("slots in flight disagree with the one slot", nt_k, ntracks)
+        for t, _sub in pool:
+            t.close()
+        del pool
+    k_best = min(inflight, key=inflight.get)
+
     def eager():
         trk.load_batch(0, offs, *cat)
         trk.track_event(0)
@@ -202,6 +237,9 @@ def bench_batch(evs, geo, dev, steps: int) -> dict:
     rate = lambda ms: total / (ms * 1e-3)  # noqa: E731
     return {"events": len(evs), "clusters": total, "sectors": 36 * len(evs), "tracks": ntracks,
             "graph_ms": ms_graph, "graph_clusters_per_s": rate(ms_graph),
+            "graph_slots_in_flight": {"best_slots": k_best, "ms": inflight[k_best],
+                                      "clusters_per_s": rate(inflight[k_best]),
+                                      "ms_by_slots": inflight},
             "one_launch_per_step_ms": ms_eager, "one_launch_per_step_clusters_per_s": rate(ms_eager),
             "per_event_ms": ms_events, "per_event_clusters_per_s": rate(ms_events),
             "plain_ms": ms_plain, "plain_clusters_per_s": rate(ms_plain),
