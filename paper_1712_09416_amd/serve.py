@@ -36,6 +36,9 @@ from .tracker import Tracker
 
 @dataclass
 class Request:
+    """One event: its clusters in host memory, as numpy arrays or as pinned
+    CPU tensors (as a DMA engine would deliver them), which are transferred
+    to the device without a host copy."""
     arrival: float                 # seconds from the start of the run
     sector: np.ndarray
     row: np.ndarray
@@ -85,22 +88,36 @@ class _Worker:
         self.batch: list[int] = []
 
     def submit(self, reqs: list[Request], ids: list[int], plain: bool, calib=None):
+        # requests in host numpy arrays are staged through the pinned buffers
+        # (one host copy each, then one transfer per field for all of them);
+        # requests already in pinned host tensors are transferred from where
+        # they are, after the staged ones
+        staged = [i for i in ids if not isinstance(reqs[i].y, torch.Tensor)]
+        direct = [i for i in ids if isinstance(reqs[i].y, torch.Tensor)]
+        ids = staged + direct
         offs = np.zeros(len(ids) + 1, np.int64)
         for k, i in enumerate(ids):
             offs[k + 1] = offs[k] + reqs[i].n
         n = int(offs[-1])
+        ns = int(offs[len(staged)])
         hs, hr, hy, hz = (t.numpy() for t in (self.h_sector, self.h_row, self.h_y, self.h_z))
-        for k, i in enumerate(ids):
+        for k, i in enumerate(staged):
             a, b = offs[k], offs[k + 1]
             r = reqs[i]
             hs[a:b] = r.sector
             hr[a:b] = r.row
             hy[a:b] = r.y
             hz[a:b] = r.z
+        dev = (self.d_sector, self.d_row, self.d_y, self.d_z)
         with torch.cuda.stream(self.trk.stream):
-            for d, h in ((self.d_sector, self.h_sector), (self.d_row, self.h_row),
-                         (self.d_y, self.h_y), (self.d_z, self.h_z)):
-                d[:n].copy_(h[:n], non_blocking=True)
+            if ns:
+                for d, h in zip(dev, (self.h_sector, self.h_row, self.h_y, self.h_z)):
+                    d[:ns].copy_(h[:ns], non_blocking=True)
+            for k, i in enumerate(direct, start=len(staged)):
+                a, b = int(offs[k]), int(offs[k + 1])
+                r = reqs[i]
+                for d, src in zip(dev, (r.sector, r.row, r.y, r.z)):
+                    d[a:b].copy_(src, non_blocking=True)
             self.tag = calib.on_submit(self.trk, self.d_sector, self.d_z, n) if calib else None
             self.trk.load_batch(0, offs, self.d_sector[:n], self.d_row[:n], self.d_y[:n],
                                 self.d_z[:n])

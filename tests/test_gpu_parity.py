@@ -396,15 +396,20 @@ def test_graph_replays_match_eager(dev):
 def test_serving_results_equal_alone(dev, oracle_lib):
     """Requests served with continuous batching over several streams (and
     with the plain one-at-a-time path) give each event exactly the oracle's
-    tracks of that event alone."""
+    tracks of that event alone; every third request arrives in pinned host
+    tensors (transferred from there) and the others in numpy arrays (staged),
+    so batches mix the two."""
     from paper_1712_09416_amd.serve import Server, Request, poisson_arrivals
     pool = [tpcgen.pbpb_event(tpcgen.seed_for(4, e), m) for e, m in enumerate([60, 300, 900, 150])]
     geo = pool[0].geometry()
     refs = [oracle_lib.run(ev.sector, ev.row, ev.y, ev.z, geo, precision=32, nthreads=ORACLE_THREADS)
             for ev in pool]
+    pinned = [[torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+               for a in (ev.sector, ev.row, ev.y, ev.z)] for ev in pool]
     arr = poisson_arrivals(40, 2000.0, seed=5)
-    reqs = [Request(float(arr[i]), pool[i % 4].sector, pool[i % 4].row, pool[i % 4].y,
-                    pool[i % 4].z, tag=str(i % 4)) for i in range(40)]
+    reqs = [Request(float(arr[i]), *(pinned[i % 4] if i % 3 == 0 else
+                                     (pool[i % 4].sector, pool[i % 4].row, pool[i % 4].y,
+                                      pool[i % 4].z)), tag=str(i % 4)) for i in range(40)]
     for plain in (False, True):
         srv = Server(geo, n_streams=3, max_events=4, cap_clusters=600_000, plain=plain)
         st = srv.run(reqs, collect=True)
