@@ -367,8 +367,9 @@ def test_repeat_runs_identical(dev):
 
 def test_graph_replays_match_eager(dev):
     """The captured tracking graph, replayed several times with other eager
-    work in between, gives the eager result every time; a slot re-staged with
-    another shape is refused."""
+    work in between, gives the eager result every time (and so does the
+    merger run on a replayed slot); a slot re-staged with another shape is
+    refused."""
     from paper_1712_09416_amd import Tracker, TpcError
     ev = tpcgen.pbpb_event(tpcgen.seed_for(2) + 90, 1500)
     trk = Tracker(ev.geometry(), max_clusters=ev.n + 100)
@@ -376,6 +377,8 @@ def test_graph_replays_match_eager(dev):
     trk.load(0, *ins)
     trk.track_event(0)
     ref_t, ref_h = trk.get_tracks(0)
+    trk.merge(0)
+    ref_m = trk.get_merged(0)
     trk.load(0, *ins)
     trk.capture(0)
     for k in range(4):
@@ -385,6 +388,10 @@ def test_graph_replays_match_eager(dev):
         t, h = trk.get_tracks(0)
         assert np.array_equal(h, ref_h), k
         assert np.array_equal(t, ref_t), k
+        if k % 2 == 1:                  # the merger runs on a replayed slot too
+            trk.merge(0)
+            for a, b in zip(trk.get_merged(0), ref_m):
+                assert np.array_equal(a, b), k
         trk.load(0, *ins)
     other = [a[:-10].contiguous() for a in ins]
     trk.load(0, *other)
