@@ -9,6 +9,9 @@ selection change only the order of loads and lanes.  So the tracks do not
 depend on them: for a given batch the tuner times graph replays of each
 candidate, checks that its tracks are identical to the first candidate's,
 and keeps the fastest, one group of knobs at a time (coordinate descent).
+A candidate replaces the values held so far only when it is faster by more
+than a margin (1% by default, about the replays' run-to-run spread), so the
+shape does not wander between equally fast ones from run to run.
 """
 from __future__ import annotations
 
@@ -42,9 +45,10 @@ def _label(cand: dict) -> str:
 
 
 def autotune(geometry: dict, offsets, sector, row, y, z, reps: int = 5, groups=GROUPS,
-             knobs=None, **params) -> dict:
+             knobs=None, margin: float = 0.01, **params) -> dict:
     """Tune the launch shape for the batch given as device tensors and event
-    offsets.  knobs: candidate values per knob (default KNOBS).  Returns
+    offsets.  knobs: candidate values per knob (default KNOBS); margin: the
+    fraction by which a candidate must beat the values held so far.  Returns
     {"best": {knob: value}, "ms": {label: ms per replay}}; raises if any
     candidate's tracks differ from the first one's."""
     knobs = dict(KNOBS, **(knobs or {}))
@@ -89,5 +93,8 @@ def autotune(geometry: dict, offsets, sector, row, y, z, reps: int = 5, groups=G
             cand = dict(best)
             cand.update(zip(group, vals))
             timed[vals] = run(cand)
-        best.update(zip(group, min(timed, key=timed.get)))
+        held = tuple(best[k] for k in group)
+        top = min(timed, key=timed.get)
+        if held not in timed or timed[top] < timed[held] * (1.0 - margin):
+            best.update(zip(group, top))
     return {"best": best, "ms": ms, "best_ms": ms[_label(best)]}
