@@ -253,6 +253,21 @@ int tpc_track_event_noalloc(const tpc_geometry* g, const tpc_params* p, const ui
 int tpc_get_tracks(tpc_ctx* ctx, int slot, int event, tpc_track* out, int64_t max_tracks,
                    int32_t* hit_ids, int64_t max_hits, int64_t* n_tracks, int64_t* n_hits);
 
+/* The same output for every event of a slot in one copy (Section 2: the
+ * event stream's results leave the tracker together; the serving loop reads
+ * a continuous-batching slot this way, with a few synchronisations per slot
+ * instead of per event).  out[max_tracks], hit_ids[max_hits]: the slot's
+ * tracks and hit IDs, event after event, each event's block exactly what
+ * tpc_get_tracks returns for it (hit_off relative to the event);
+ * event_track_off, event_hit_off: host arrays of n_events + 1 entries (2 for
+ * a slot staged with tpc_load_clusters) receiving the start of each event's
+ * block and the totals, also when the buffers are too small.  *n_tracks,
+ * *n_hits receive the totals.  Errors: as tpc_get_tracks, and TPC_EINVAL
+ * for a NULL offset array. */
+int tpc_get_slot_tracks(tpc_ctx* ctx, int slot, tpc_track* out, int64_t max_tracks,
+                        int32_t* hit_ids, int64_t max_hits, uint32_t* event_track_off,
+                        uint32_t* event_hit_off, int64_t* n_tracks, int64_t* n_hits);
+
 /* Output of the tracker, as in tpc_get_tracks.  Device-resident results of
  * a tracked slot, without copies or
  * synchronisation: tracks of all events of the slot in canonical order,

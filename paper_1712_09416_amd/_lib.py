@@ -18,6 +18,7 @@ ERROR_NAMES = {0: "TPC_OK", -1: "TPC_EINVAL", -2: "TPC_ENOMEM", -3: "TPC_EOVERFL
 EXPORTS = ("tpc_params_default", "tpc_workspace_bytes", "tpc_init_geometry", "tpc_load_clusters",
            "tpc_load_batch", "tpc_track_sector", "tpc_track_event", "tpc_track_events",
            "tpc_submit", "tpc_track_event_streams", "tpc_track_event_noalloc", "tpc_get_tracks",
+           "tpc_get_slot_tracks",
            "tpc_device_results", "tpc_get_links", "tpc_kf_step_f32", "tpc_graph_capture",
            "tpc_graph_launch", "tpc_poll", "tpc_set_profiling", "tpc_get_profile",
            "tpc_merge_params_default", "tpc_merge", "tpc_get_merged", "tpc_get_merge_links",
@@ -96,6 +97,7 @@ def load() -> ctypes.CDLL:
     L.tpc_track_event_noalloc.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(Params), P, P, P,
                                           P, I64, P, I64, P, I64, P, P]
     L.tpc_get_tracks.argtypes = [P, I, I, P, I64, P, I64, P, P]
+    L.tpc_get_slot_tracks.argtypes = [P, I, P, I64, P, I64, P, P, P, P]
     L.tpc_device_results.argtypes = [P, I, P, P, P, P, P]
     L.tpc_get_links.argtypes = [P, I, I, P, P, P, P]
     L.tpc_kf_step_f32.argtypes = [P, P, P, P, P, I64]

@@ -1155,6 +1155,48 @@ int tpc_get_tracks(tpc_ctx* ctx, int slot, int event, tpc_track* out, int64_t ma
   return TPC_OK;
 }
 
+int tpc_get_slot_tracks(tpc_ctx* ctx, int slot, tpc_track* out, int64_t max_tracks,
+                        int32_t* hit_ids, int64_t max_hits, uint32_t* event_track_off,
+                        uint32_t* event_hit_off, int64_t* n_tracks, int64_t* n_hits) {
+  if (!ctx) return TPC_EINVAL;
+  if (slot < 0 || slot >= ctx->p.max_slots) return ctx->fail(TPC_EINVAL, "slot out of range");
+  SlotHost& h = ctx->slots[slot];
+  if (max_tracks < 0 || max_hits < 0) return ctx->fail(TPC_EINVAL, "negative buffer size");
+  if ((max_tracks > 0 && !out) || (max_hits > 0 && !hit_ids))
+    return ctx->fail(TPC_EINVAL, "null output buffer");
+  if (!event_track_off || !event_hit_off) return ctx->fail(TPC_EINVAL, "null offset array");
+  if (h.state == 3) {
+    const int rc = finalize(ctx, h);
+    if (rc) return rc;
+  }
+  if (h.state != 4) return ctx->fail(TPC_ESTATE, "slot not tracked");
+  const int ne = std::max(1, h.n_events);
+  hipStream_t st = ctx->stream;
+  uint32_t err[4];
+  TPC_HIP(hipMemcpyAsync(err, h.d.err, sizeof(err), hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipMemcpyAsync(event_track_off, h.d.ev_track_off, (ne + 1) * sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipMemcpyAsync(event_hit_off, h.d.ev_hit_off, (ne + 1) * sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipStreamSynchronize(st));
+  if (err[0]) return ctx->fail(TPC_EINVAL, std::to_string(err[0]) + " invalid clusters (sector, row or coordinates)");
+  if (err[1]) return ctx->fail(TPC_EINVAL, "a pad row holds more than 4096 clusters");
+  if (err[2]) return ctx->fail(TPC_EDEVICE, "internal capacity exceeded");
+  const uint32_t t0 = event_track_off[0], h0 = event_hit_off[0];
+  for (int e = 0; e <= ne; ++e) {
+    event_track_off[e] -= t0;
+    event_hit_off[e] -= h0;
+  }
+  const int64_t nt = event_track_off[ne], nh = event_hit_off[ne];
+  if (n_tracks) *n_tracks = nt;
+  if (n_hits) *n_hits = nh;
+  if (nt > max_tracks || nh > max_hits) return ctx->fail(TPC_EOVERFLOW, "output buffers too small");
+  if (nt) TPC_HIP(hipMemcpyAsync(out, h.d.out_tracks + t0, nt * sizeof(tpc_track), hipMemcpyDeviceToHost, st));
+  if (nh) TPC_HIP(hipMemcpyAsync(hit_ids, h.d.out_hits + h0, nh * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  TPC_HIP(hipStreamSynchronize(st));
+  return TPC_OK;
+}
+
 int tpc_get_links(tpc_ctx* ctx, int slot, int event, int32_t* up, int32_t* dn, int32_t* up_clean,
                   int32_t* dn_clean) {
   if (!ctx) return TPC_EINVAL;

@@ -184,8 +184,9 @@ class Server:
                 wk = self.workers[w]
                 if not wk.trk.poll(0):
                     continue
+                out = wk.trk.get_slot_tracks(0)
                 for e, i in enumerate(wk.batch):
-                    tracks, hits = wk.trk.get_tracks(0, e)
+                    tracks, hits = out[e]
                     done_at[i] = time.perf_counter() - t0
                     in_flight -= reqs[i].n
                     if collect:

@@ -64,6 +64,7 @@ class Tracker:
                                       nbytes, self.stream.cuda_stream)
         check(rc, None)
         self._keep = {}
+        self._n_events = {}
 
     # -- staging -------------------------------------------------------------
     def load(self, slot: int, sector, row, y, z, q=None):
@@ -78,6 +79,7 @@ class Tracker:
         n = int(arrs[2].shape[0])
         check(self.L.tpc_load_clusters(self.ctx, slot, _ptr(arrs[0]), _ptr(arrs[1]), _ptr(arrs[2]),
                                        _ptr(arrs[3]), None, n, flags), self.ctx)
+        self._n_events[slot] = 1
         self._staged(slot)
 
     def load_batch(self, slot: int, offsets, sector, row, y, z):
@@ -92,6 +94,7 @@ class Tracker:
         check(self.L.tpc_load_batch(self.ctx, slot, len(offs) - 1, offs.ctypes.data, _ptr(arrs[0]),
                                     _ptr(arrs[1]), _ptr(arrs[2]), _ptr(arrs[3]), None, flags),
               self.ctx)
+        self._n_events[slot] = len(offs) - 1
         self._staged(slot)
 
     def _hold(self, slot, arrs, dev):
@@ -176,6 +179,25 @@ class Tracker:
                                     hits.ctypes.data, len(hits), ctypes.byref(nt),
                                     ctypes.byref(nh)), self.ctx)
         return tracks, hits
+
+    def get_slot_tracks(self, slot: int = 0):
+        """[(tracks, hit IDs)] of every event of the slot, as get_tracks gives
+        them, read in one copy (a few synchronisations for the slot)."""
+        ne = self._n_events.get(slot, 1)
+        toff = np.zeros(ne + 1, np.uint32)
+        hoff = np.zeros(ne + 1, np.uint32)
+        nt, nh = ctypes.c_int64(0), ctypes.c_int64(0)
+        rc = self.L.tpc_get_slot_tracks(self.ctx, slot, None, 0, None, 0, toff.ctypes.data,
+                                        hoff.ctypes.data, ctypes.byref(nt), ctypes.byref(nh))
+        if rc not in (_lib.TPC_OK, _lib.TPC_EOVERFLOW):
+            check(rc, self.ctx)
+        tracks = np.zeros(nt.value, TRACK_DTYPE)
+        hits = np.zeros(nh.value, np.int32)
+        check(self.L.tpc_get_slot_tracks(self.ctx, slot, tracks.ctypes.data, len(tracks),
+                                         hits.ctypes.data, len(hits), toff.ctypes.data,
+                                         hoff.ctypes.data, ctypes.byref(nt), ctypes.byref(nh)),
+              self.ctx)
+        return [(tracks[toff[e]:toff[e + 1]], hits[hoff[e]:hoff[e + 1]]) for e in range(ne)]
 
     # -- cross-sector merger ----------------------------------------------------
     def merge(self, slot: int = 0, **over):

@@ -154,6 +154,20 @@ def test_calls_rejected_before_device_work(L):
     assert L.tpc_get_tracks(ctx, 0, 0, None, 5, None, 0, ctypes.byref(nt),
                             ctypes.byref(nh)) == _lib.TPC_EINVAL
     assert L.tpc_get_tracks(ctx, 0, 0, None, -1, None, 0, None, None) == _lib.TPC_EINVAL
+    # the whole slot's output: offset arrays required, buffer sizes, state
+    off = np.zeros(2, np.uint32)
+    assert L.tpc_get_slot_tracks(None, 0, None, 0, None, 0, off.ctypes.data, off.ctypes.data,
+                                 None, None) == _lib.TPC_EINVAL
+    assert L.tpc_get_slot_tracks(ctx, 0, None, 0, None, 0, None, off.ctypes.data,
+                                 None, None) == _lib.TPC_EINVAL
+    assert L.tpc_get_slot_tracks(ctx, 0, None, -1, None, 0, off.ctypes.data, off.ctypes.data,
+                                 None, None) == _lib.TPC_EINVAL
+    assert L.tpc_get_slot_tracks(ctx, 0, None, 4, None, 0, off.ctypes.data, off.ctypes.data,
+                                 None, None) == _lib.TPC_EINVAL
+    assert L.tpc_get_slot_tracks(ctx, 7, None, 0, None, 0, off.ctypes.data, off.ctypes.data,
+                                 None, None) == _lib.TPC_EINVAL
+    assert L.tpc_get_slot_tracks(ctx, 0, None, 0, None, 0, off.ctypes.data, off.ctypes.data,
+                                 None, None) == _lib.TPC_ESTATE
     assert L.tpc_get_links(ctx, 0, 0, None, None, None, None) == _lib.TPC_ESTATE
     assert L.tpc_kf_step_f32(ctx, None, None, None, None, 5) == _lib.TPC_EINVAL
     assert L.tpc_kf_step_f32(ctx, None, None, None, None, 0) == _lib.TPC_OK

@@ -6,6 +6,8 @@ parameters / covariances identical to the oracle's (both refit in double
 from identical float seeds) and within 1e-4 relative (floors 10 cm, 10 cm,
 0.1, 0.1, 0.1) / 1e-3 of sqrt(C_ii C_jj) of the double replay.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -182,7 +184,8 @@ def test_central_event_all_sectors(dev, oracle_lib):
 def test_batch_equals_single_events(dev, oracle_lib):
     """Events tracked together in one slot (one cluster-error model for the
     whole slot: the Pb-Pb one) give exactly the oracle's tracks of each
-    event, and so their single-event results."""
+    event, and so their single-event results; the whole slot read in one
+    copy gives each event the same block."""
     from paper_1712_09416_amd import Tracker
     evs = [tpcgen.pbpb_event(tpcgen.seed_for(3, e), m) for e, m in enumerate([50, 900, 3000])]
     evs.insert(1, tpcgen.pp_event())
@@ -196,15 +199,27 @@ def test_batch_equals_single_events(dev, oracle_lib):
     trk = Tracker(geo, max_events=8, max_clusters=int(offs[-1]) + 16)
     trk.load_batch(0, offs, *[torch.from_numpy(a).to(dev) for a in cat])
     trk.track_event(0)
+    whole = trk.get_slot_tracks(0)              # every event in one copy
+    assert len(whole) == len(evs)
     for e, ev in enumerate(evs):
         tb, hb = trk.get_tracks(0, e)
         assert np.all(tb["event"] == e)
+        assert np.array_equal(whole[e][0], tb) and np.array_equal(whole[e][1], hb), e
         ref = oracle_lib.run(ev.sector, ev.row, ev.y, ev.z, geo, precision=32, nthreads=ORACLE_THREADS)
         compare_tracks(tb, hb, ref)
         ts, hs, _ = gpu_run(ev, dev, links=False, geometry=geo)
         assert np.array_equal(hb, hs)
         for k in ("n_hits", "inner_id", "hit_off", "par", "cov", "chi2", "sector"):
             assert np.array_equal(tb[k], ts[k]), (e, k)
+    # buffers too small: the counts and offsets still come back
+    toff = np.zeros(len(evs) + 1, np.uint32)
+    hoff = np.zeros(len(evs) + 1, np.uint32)
+    nt, nh = ctypes.c_int64(0), ctypes.c_int64(0)
+    rc = trk.L.tpc_get_slot_tracks(trk.ctx, 0, None, 0, None, 0, toff.ctypes.data,
+                                   hoff.ctypes.data, ctypes.byref(nt), ctypes.byref(nh))
+    assert rc == -3                             # TPC_EOVERFLOW
+    assert nt.value == sum(len(w[0]) for w in whole) == toff[-1]
+    assert nh.value == sum(len(w[1]) for w in whole) == hoff[-1]
     trk.close()
 
 
