@@ -199,6 +199,12 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   m.chi_in = c.take<double>(cap_tk);
   m.in_key = c.take<unsigned long long>(cap_tk);
   m.out_key = c.take<unsigned long long>(cap_tk);
+  // compatible pairs: two per track of capacity (a central event has ~0.3)
+  m.pair_cap = (uint32_t)std::min<int64_t>(2 * cap_tk, 0xFFFFFFFFll);
+  m.pair_a = c.take<int32_t>(m.pair_cap);
+  m.pair_b = c.take<int32_t>(m.pair_cap);
+  m.pair_key = c.take<unsigned long long>(m.pair_cap);
+  m.pair_n = c.take<uint32_t>(1);
   m.link_out = c.take<int32_t>(cap_tk);
   m.link_in = c.take<int32_t>(cap_tk);
   m.head_ok = c.take<int32_t>(cap_tk);
@@ -790,6 +796,7 @@ int tpc_merge(tpc_ctx* ctx, int slot, const tpc_merge_params* mp) {
     k_fill_i32<<<grid_stride_blocks(2 * K, 256), 256, 0, st>>>(reinterpret_cast<int32_t*>(p),
                                                                2 * K, -1);
   for (int32_t* p : {m.best_in, m.best_out}) k_fill_i32<<<nb, 256, 0, st>>>(p, K, 0x7FFFFFFF);
+  k_zero_u32<<<1, 64, 0, st>>>(m.pair_n, 1);
   k_mg_count<<<nb, 256, 0, st>>>(s, m);
   scan_u32(st, m.in_off, nullptr, nsr, s.scan_b, nullptr);
   scan_u32(st, m.out_off, nullptr, nsr, s.scan_b, nullptr);
@@ -798,7 +805,10 @@ int tpc_merge(tpc_ctx* ctx, int slot, const tpc_merge_params* mp) {
   // one-wave blocks, four tracks each
   const int nbp = grid_stride_blocks((K + 3) / 4, 1, 16384);
   k_mg_pairs<false><<<nbp, 64, 0, st>>>(s, ctx->k, m, C);
-  k_mg_pairs<true><<<nbp, 64, 0, st>>>(s, ctx->k, m, C);
+  k_mg_pair_best<<<nb, 256, 0, st>>>(m);
+  // walks the candidates again only if the list overflowed (a smaller grid:
+  // its blocks return at once otherwise)
+  k_mg_pairs<true><<<std::min(nbp, 1024), 64, 0, st>>>(s, ctx->k, m, C);
   k_mg_final<<<nb, 256, 0, st>>>(s, m);
   k_mg_link<<<nb, 256, 0, st>>>(s, m);
   k_mg_chain<<<nbt, 256, 0, st>>>(s, ctx->k, m, C);

@@ -319,25 +319,41 @@ __device__ bool pair_chi2(const DevConst& K, const MergeConst& C, const tpc_trac
 
 constexpr int kPairLanes = 16;   // lanes walking one track's candidates
 
-// A compatible pair (A, B): its chi2 lowers A's and B's smallest chi2
-// (kFinal = false; the bit pattern of a non-negative double orders like its
-// value), or, once those are known, offers B as A's best outer partner and
-// A as B's best inner partner where it reaches them (kFinal = true; the
-// smaller track position wins a tie).
+// A pair (A, B) of the candidate walk: if compatible, its chi2 lowers A's
+// and B's smallest chi2 (kFinal = false; the bit pattern of a non-negative
+// double orders like its value) and the pair is listed for the second pass
+// (up to pair_cap pairs, slots taken a wave at a time); or, once those are
+// known, it offers B as A's best outer partner and A as B's best inner
+// partner where it reaches them (kFinal = true; the smaller track position
+// wins a tie).  Called by every active lane of the wave together.
 template <bool kFinal>
 __device__ __forceinline__ void pair_eval(const Slot& S, const DevConst& K, const MergeSlot& M,
                                           const MergeConst& C, int32_t a, int32_t b) {
-  double ch;
-  if (!pair_chi2(K, C, S.out_tracks[a], M.op + (size_t)a * 5, M.oc + (size_t)a * 15,
-                 S.out_tracks[b], ch))
-    return;
+  double ch = 0.0;
+  const bool ok = pair_chi2(K, C, S.out_tracks[a], M.op + (size_t)a * 5,
+                            M.oc + (size_t)a * 15, S.out_tracks[b], ch);
   const unsigned long long key = (unsigned long long)__double_as_longlong(ch);
-  if (!kFinal) {
+  if (kFinal) {
+    if (ok && key == M.out_key[a]) atomicMin(&M.best_out[a], b);
+    if (ok && key == M.in_key[b]) atomicMin(&M.best_in[b], a);
+    return;
+  }
+  if (ok) {
     atomicMin(&M.out_key[a], key);
     atomicMin(&M.in_key[b], key);
-  } else {
-    if (key == M.out_key[a]) atomicMin(&M.best_out[a], b);
-    if (key == M.in_key[b]) atomicMin(&M.best_in[b], a);
+  }
+  const unsigned long long m = __ballot(ok);
+  if (m == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(M.pair_n, (uint32_t)__popcll(m));
+  base = __shfl(base, leader, 64);
+  const uint32_t idx = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+  if (ok && idx < M.pair_cap) {
+    M.pair_a[idx] = a;
+    M.pair_b[idx] = b;
+    M.pair_key[idx] = key;
   }
 }
 
@@ -354,6 +370,9 @@ template <bool kFinal>
 __global__ void __launch_bounds__(64) k_mg_pairs(Slot S, DevConst K, MergeSlot M, MergeConst C) {
   __shared__ int32_t qa[128], qb[128];
   constexpr int kPerWave = 64 / kPairLanes;
+  // the second pass walks the candidates again only if the first pass's
+  // pair list overflowed (k_mg_pair_best has the pairs otherwise)
+  if (kFinal && M.pair_n[0] <= M.pair_cap) return;
   const uint32_t ntk = S.out_count[0];
   const int lane = threadIdx.x;
   const int gl = lane % kPairLanes;
@@ -420,6 +439,20 @@ __global__ void __launch_bounds__(64) k_mg_pairs(Slot S, DevConst K, MergeSlot M
 
 template __global__ void k_mg_pairs<false>(Slot, DevConst, MergeSlot, MergeConst);
 template __global__ void k_mg_pairs<true>(Slot, DevConst, MergeSlot, MergeConst);
+
+// The second pass over the pairs the first one listed (when they all fit):
+// a pair reaching A's (B's) smallest chi2 offers B (A) as its best partner.
+__global__ void k_mg_pair_best(MergeSlot M) {
+  const uint32_t n = M.pair_n[0];
+  if (n > M.pair_cap) return;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int32_t a = M.pair_a[i], b = M.pair_b[i];
+    const unsigned long long key = M.pair_key[i];
+    if (key == M.out_key[a]) atomicMin(&M.best_out[a], b);
+    if (key == M.in_key[b]) atomicMin(&M.best_in[b], a);
+  }
+}
 
 // a track without a compatible partner: -1 and chi2 0
 __global__ void k_mg_final(Slot S, MergeSlot M) {

@@ -198,6 +198,11 @@ struct MergeSlot {
   double* chi_in;           // [K]
   unsigned long long* in_key;   // [K] per B: bits of the smallest chi2 of a compatible A (~0: none)
   unsigned long long* out_key;  // [K] per A: the same over its compatible B's
+  int32_t* pair_a;          // [P] compatible pairs listed by the first pair pass
+  int32_t* pair_b;          // [P]
+  unsigned long long* pair_key;  // [P] their chi2 bit patterns
+  uint32_t* pair_n;         // [1] pairs found (may exceed pair_cap: then not all listed)
+  uint32_t pair_cap;        // P
   int32_t* link_out;        // [K] mutual best outer partner, -1 none
   int32_t* link_in;         // [K]
   int32_t* head_ok;         // [K] per chain head: chain of >= 2 segments refitted

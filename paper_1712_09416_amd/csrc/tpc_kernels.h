@@ -49,6 +49,7 @@ __global__ void k_mg_outer(Slot S, DevConst K, MergeSlot M, MergeConst C);
 template <bool kFinal>
 __global__ void k_mg_pairs(Slot S, DevConst K, MergeSlot M, MergeConst C);
 __global__ void k_mg_final(Slot S, MergeSlot M);
+__global__ void k_mg_pair_best(MergeSlot M);
 __global__ void k_mg_link(Slot S, MergeSlot M);
 __global__ void k_mg_chain(Slot S, DevConst K, MergeSlot M, MergeConst C);
 __global__ void k_mg_emit(Slot S, MergeSlot M);

@@ -752,6 +752,43 @@ def test_merge_params_match_oracle(dev, oracle_lib, over):
     trk.close()
 
 
+def test_merge_pair_list_overflow_matches_oracle(dev, oracle_lib):
+    """The first pair pass lists the compatible pairs for the second, two per
+    track of the slot's capacity; beyond that the second pass walks the
+    candidates again.  With the match cut opened (chi2 <= 1e6) on the
+    boundary jet and a capacity sized for 30-hit tracks, the candidate pairs
+    (3,700) outnumber the list (~1,700): the merged output still equals the
+    oracle's merger with the same cut."""
+    from paper_1712_09416_amd import Tracker
+    ev = tpcgen.boundary_jet_event()
+    trk = Tracker(ev.geometry(), max_clusters=ev.n, n_min_track=30)
+    ins = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (ev.sector, ev.row, ev.y, ev.z)]
+    trk.load(0, *ins)
+    trk.track_event(0)
+    trk.merge(0, chi2_max=1e6)
+    tracks, hits = trk.get_tracks(0, 0)
+    sec = tracks["sector"].astype(int)
+    ri, ro = tracks["row_in"].astype(int), tracks["row_out"].astype(int)
+    n_cand = 0
+    for a in range(len(tracks)):
+        side, k = divmod(sec[a], 18)
+        nb = {side * 18 + (k + 1) % 18, side * 18 + (k + 17) % 18, (1 - side) * 18 + k}
+        n_cand += int(np.count_nonzero(np.isin(sec, list(nb)) & (ri > ro[a]) & (ri <= ro[a] + 12)))
+    cap = 2 * (ev.n // 30 + 36)
+    say(f"pair list: {n_cand} candidate pairs, room for {cap}")
+    assert n_cand > 1.5 * cap
+    gt, gh, gseg = trk.get_merged(0, 0)
+    lk = trk.merge_links(0, 0, len(tracks))
+    ref = oracle_lib.merge(as_oracle_tracks(tracks, oracle_lib), hits, ev.row, ev.y, ev.z,
+                           ev.geometry(), chi2_max=1e6)
+    assert (ref.n_segments > 1).sum() > 30
+    assert np.array_equal(lk["best_out"], ref.best_out)
+    assert np.array_equal(lk["best_chi2"][ref.best_out >= 0], ref.best_chi2[ref.best_out >= 0])
+    assert np.array_equal(lk["link_out"], ref.link_out)
+    compare_merged(gt, gh, gseg, ref)
+    trk.close()
+
+
 def test_merge_batch_equals_single(dev, oracle_lib):
     """Merging a batch slot gives each event its own single-event merge."""
     from paper_1712_09416_amd import Tracker
