@@ -487,7 +487,8 @@ int track_range(tpc_ctx* ctx, SlotHost& h, int g0, int ns, const Lane* lane = nu
   const int tl_block = ctx->p.tl_block;
   const int nb_lane =
       std::max(8, grid_stride_blocks(tl_bound, tl_block, 16384 * 64 / tl_block) / 8 * 8);
-  const int nb_sel = grid_stride_blocks(tl_bound, 256, 4096);
+  // a multiple of 8 blocks: each XCD walks its chunk of the tracklets
+  const int nb_sel = (grid_stride_blocks(tl_bound, 256, 4096) + 7) / 8 * 8;
   // a lane per hit of the range (the grid from the host bound; the kernel
   // strides over the device count)
   launch_neighbours(ctx->p.win_batch, grid_stride_blocks(n_range, 256, 65536) / 8 * 8 + 8, st, s,

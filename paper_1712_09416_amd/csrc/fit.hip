@@ -50,13 +50,34 @@ __device__ __forceinline__ void load_weights(const Slot& S, const int32_t (&hv)[
 // range; the scan of these flags places the tracks.
 // Lane per tracklet; a wave walks the rows its 64 consecutive tracklets
 // span together, so each row's hit-list reads are contiguous (tile layout).
+// The tracklets are in sector order: each XCD (blocks are dispatched
+// round-robin over the 8; the grid is a multiple of 8) walks a contiguous
+// chunk of them, a whole number of waves, so a sector's hit lists and
+// weights are read through one XCD's L2.  Wave-aligned start of this
+// wave's first group of 64, the chunk's end, and the stride.
+struct XcdChunk {
+  uint32_t first, end, stride;
+};
+__device__ __forceinline__ XcdChunk xcd_chunk(uint32_t total) {
+  constexpr uint32_t kXcd = 8;
+  const uint32_t xcd = blockIdx.x % kXcd, jb = blockIdx.x / kXcd;
+  const uint32_t nbx = gridDim.x / kXcd;
+  const uint32_t chunk = ((total + kXcd - 1) / kXcd + 63u) & ~63u;
+  const uint32_t c0 = min(total, xcd * chunk);
+  XcdChunk x;
+  x.first = c0 + ((jb * blockDim.x + threadIdx.x) & ~63u);
+  x.end = min(total, c0 + chunk);
+  x.stride = nbx * blockDim.x;
+  return x;
+}
+
 template <int RB>
 __global__ void __launch_bounds__(256) k_select(Slot S, DevConst K, int g0) {
   const uint32_t total = S.range_cnt[0];
   const uint32_t base = S.tl_base[g0];
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t tb = (blockIdx.x * blockDim.x + threadIdx.x) & ~63u; tb < total; tb += stride) {
+  const XcdChunk xc = xcd_chunk(total);
+  for (uint32_t tb = xc.first; tb < xc.end; tb += xc.stride) {
     const uint32_t t = tb + lane;
     const uint32_t T = base + t;
     bool valid = false;
@@ -100,8 +121,8 @@ __global__ void __launch_bounds__(256) k_track_write(Slot S, int g0, int ns) {
   const uint32_t tl0 = S.tl_base[g0], tk0 = S.tk_base[g0];
   const uint32_t tk_room = S.tk_base[g0 + ns] - tk0;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t tb = (blockIdx.x * blockDim.x + threadIdx.x) & ~63u; tb < total; tb += stride) {
+  const XcdChunk xc = xcd_chunk(total);
+  for (uint32_t tb = xc.first; tb < xc.end; tb += xc.stride) {
     const uint32_t t = tb + lane;
     const uint32_t T = tl0 + t;
     bool sel = false;
