@@ -2,6 +2,7 @@
 #pragma once
 
 #include "tpc_device.h"
+#include "tpc_merge.h"
 
 namespace tpc {
 
