@@ -199,12 +199,13 @@ void carve_slot(Carver& c, const tpc_params& p, Slot& s, SlotHost* h) {
   m.chi_in = c.take<double>(cap_tk);
   m.in_key = c.take<unsigned long long>(cap_tk);
   m.out_key = c.take<unsigned long long>(cap_tk);
-  // compatible pairs: two per track of capacity (a central event has ~0.3)
-  m.pair_cap = (uint32_t)std::min<int64_t>(2 * cap_tk, 0xFFFFFFFFll);
-  m.pair_a = c.take<int32_t>(m.pair_cap);
-  m.pair_b = c.take<int32_t>(m.pair_cap);
-  m.pair_key = c.take<unsigned long long>(m.pair_cap);
-  m.pair_n = c.take<uint32_t>(1);
+  // compatible pairs: two per track of capacity in all (a central event has
+  // ~0.3), spread over the segments
+  m.pair_cap = (uint32_t)std::min<int64_t>((2 * cap_tk + kPairSegs - 1) / kPairSegs, 0x7FFFFFFFll);
+  m.pair_a = c.take<int32_t>((int64_t)m.pair_cap * kPairSegs);
+  m.pair_b = c.take<int32_t>((int64_t)m.pair_cap * kPairSegs);
+  m.pair_key = c.take<unsigned long long>((int64_t)m.pair_cap * kPairSegs);
+  m.pair_n = c.take<uint32_t>(kPairSegs * kPairPad);
   m.link_out = c.take<int32_t>(cap_tk);
   m.link_in = c.take<int32_t>(cap_tk);
   m.head_ok = c.take<int32_t>(cap_tk);
@@ -797,7 +798,7 @@ int tpc_merge(tpc_ctx* ctx, int slot, const tpc_merge_params* mp) {
     k_fill_i32<<<grid_stride_blocks(2 * K, 256), 256, 0, st>>>(reinterpret_cast<int32_t*>(p),
                                                                2 * K, -1);
   for (int32_t* p : {m.best_in, m.best_out}) k_fill_i32<<<nb, 256, 0, st>>>(p, K, 0x7FFFFFFF);
-  k_zero_u32<<<1, 64, 0, st>>>(m.pair_n, 1);
+  k_zero_u32<<<grid_stride_blocks(kPairSegs * kPairPad, 256), 256, 0, st>>>(m.pair_n, kPairSegs * kPairPad);
   k_mg_count<<<nb, 256, 0, st>>>(s, m);
   scan_u32(st, m.in_off, nullptr, nsr, s.scan_b, nullptr);
   scan_u32(st, m.out_off, nullptr, nsr, s.scan_b, nullptr);

@@ -346,15 +346,24 @@ __device__ __forceinline__ void pair_eval(const Slot& S, const DevConst& K, cons
   if (m == 0ull) return;
   const int lane = threadIdx.x & 63;
   const int leader = __ffsll((long long)m) - 1;
+  const uint32_t seg = blockIdx.x % kPairSegs;
   uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(M.pair_n, (uint32_t)__popcll(m));
+  if (lane == leader) base = atomicAdd(M.pair_n + seg * kPairPad, (uint32_t)__popcll(m));
   base = __shfl(base, leader, 64);
   const uint32_t idx = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
   if (ok && idx < M.pair_cap) {
-    M.pair_a[idx] = a;
-    M.pair_b[idx] = b;
-    M.pair_key[idx] = key;
+    const size_t at = (size_t)seg * M.pair_cap + idx;
+    M.pair_a[at] = a;
+    M.pair_b[at] = b;
+    M.pair_key[at] = key;
   }
+}
+
+// The pair count of segment (lane of the wave), read once per lane; every
+// lane of the wave must call (one segment per lane).
+static_assert(kPairSegs == 64, "one pair-list segment per lane of a wave");
+__device__ __forceinline__ uint32_t pair_seg_count(const MergeSlot& M) {
+  return M.pair_n[(threadIdx.x & 63) * kPairPad];
 }
 
 // M2 + M3 over every pair the sector and row conditions admit: the tracks
@@ -372,7 +381,7 @@ __global__ void __launch_bounds__(64) k_mg_pairs(Slot S, DevConst K, MergeSlot M
   constexpr int kPerWave = 64 / kPairLanes;
   // the second pass walks the candidates again only if the first pass's
   // pair list overflowed (k_mg_pair_best has the pairs otherwise)
-  if (kFinal && M.pair_n[0] <= M.pair_cap) return;
+  if (kFinal && !__any(pair_seg_count(M) > M.pair_cap)) return;
   const uint32_t ntk = S.out_count[0];
   const int lane = threadIdx.x;
   const int gl = lane % kPairLanes;
@@ -442,15 +451,33 @@ template __global__ void k_mg_pairs<true>(Slot, DevConst, MergeSlot, MergeConst)
 
 // The second pass over the pairs the first one listed (when they all fit):
 // a pair reaching A's (B's) smallest chi2 offers B (A) as its best partner.
+__device__ __forceinline__ void offer_listed(const MergeSlot& M, size_t at) {
+  const int32_t a = M.pair_a[at], b = M.pair_b[at];
+  const unsigned long long key = M.pair_key[at];
+  if (key == M.out_key[a]) atomicMin(&M.best_out[a], b);
+  if (key == M.in_key[b]) atomicMin(&M.best_in[b], a);
+}
+
+// Waves are dealt to the segments (with 64 waves or more, the waves w = s
+// mod 64 share segment s, lane by lane; with fewer, each wave takes whole
+// segments), so every pair is read by one lane in one round.
 __global__ void k_mg_pair_best(MergeSlot M) {
-  const uint32_t n = M.pair_n[0];
-  if (n > M.pair_cap) return;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const int32_t a = M.pair_a[i], b = M.pair_b[i];
-    const unsigned long long key = M.pair_key[i];
-    if (key == M.out_key[a]) atomicMin(&M.best_out[a], b);
-    if (key == M.in_key[b]) atomicMin(&M.best_in[b], a);
+  const uint32_t cnt = pair_seg_count(M);
+  if (__any(cnt > M.pair_cap)) return;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+  if (n_waves >= (uint32_t)kPairSegs) {
+    const uint32_t s = wave % kPairSegs, per = n_waves / kPairSegs;
+    const uint32_t n = __shfl(cnt, (int)s, 64);
+    if (wave >= per * kPairSegs) return;
+    for (uint32_t i = (wave / kPairSegs) * 64 + lane; i < n; i += per * 64)
+      offer_listed(M, (size_t)s * M.pair_cap + i);
+  } else {
+    for (uint32_t s = wave; s < (uint32_t)kPairSegs; s += n_waves) {
+      const uint32_t n = __shfl(cnt, (int)s, 64);
+      for (uint32_t i = lane; i < n; i += 64) offer_listed(M, (size_t)s * M.pair_cap + i);
+    }
   }
 }
 

@@ -9,6 +9,12 @@ namespace tpc {
 // Buffers of the cross-sector merger, per slot (K = track capacity, S =
 // sectors, E = events).  Track positions are the slot's canonical output
 // positions.
+// The compatible pairs are listed in segments, each with its own counter
+// (a block lists into segment blockIdx % kPairSegs), so the counters'
+// atomics are spread over many addresses instead of meeting at one.
+constexpr int kPairSegs = 64;
+constexpr int kPairPad = 16;        // counters 16 x 4 bytes apart
+
 struct MergeSlot {
   uint32_t* in_off;         // [S*159+1] tracks per (event, sector, first row), then offsets
   uint32_t* in_cur;         // [S*159] scatter cursors
@@ -25,11 +31,13 @@ struct MergeSlot {
   double* chi_in;           // [K]
   unsigned long long* in_key;   // [K] per B: bits of the smallest chi2 of a compatible A (~0: none)
   unsigned long long* out_key;  // [K] per A: the same over its compatible B's
-  int32_t* pair_a;          // [P] compatible pairs listed by the first pair pass
-  int32_t* pair_b;          // [P]
+  int32_t* pair_a;          // [P] compatible pairs listed by the first pair pass, in
+  int32_t* pair_b;          //     kPairSegs segments of pair_cap entries
   unsigned long long* pair_key;  // [P] their chi2 bit patterns
-  uint32_t* pair_n;         // [1] pairs found (may exceed pair_cap: then not all listed)
-  uint32_t pair_cap;        // P
+  uint32_t* pair_n;         // [kPairSegs * kPairPad] pairs found per segment, one
+                            //     counter per 64 bytes (may exceed pair_cap: then
+                            //     not all listed)
+  uint32_t pair_cap;        // entries per segment
   int32_t* link_out;        // [K] mutual best outer partner, -1 none
   int32_t* link_in;         // [K]
   int32_t* head_ok;         // [K] per chain head: chain of >= 2 segments refitted
