@@ -31,7 +31,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from .tracker import Tracker
+from .tracker import TRACK_DTYPE, Tracker
 
 
 @dataclass
@@ -85,6 +85,14 @@ class _Worker:
         self.d_row = torch.empty(cap, dtype=torch.uint8, device=device)
         self.d_y = torch.empty(cap, dtype=torch.float32, device=device)
         self.d_z = torch.empty(cap, dtype=torch.float32, device=device)
+        # pinned result buffers for the slot's most tracks and hits: the
+        # results come back into them (much faster than into pageable memory)
+        p = self.trk.params
+        max_tracks = p.max_clusters // p.n_min_track + 36 * max_events
+        self.r_tracks_t = torch.empty(max_tracks * TRACK_DTYPE.itemsize, dtype=torch.uint8, **pin)
+        self.r_tracks = self.r_tracks_t.numpy().view(TRACK_DTYPE)
+        self.r_hits_t = torch.empty(cap, dtype=torch.int32, **pin)
+        self.r_hits = self.r_hits_t.numpy()
         self.batch: list[int] = []
 
     def submit(self, reqs: list[Request], ids: list[int], plain: bool, calib=None):
@@ -184,13 +192,13 @@ class Server:
                 wk = self.workers[w]
                 if not wk.trk.poll(0):
                     continue
-                out = wk.trk.get_slot_tracks(0)
+                out = wk.trk.get_slot_tracks(0, wk.r_tracks, wk.r_hits)
                 for e, i in enumerate(wk.batch):
                     tracks, hits = out[e]
                     done_at[i] = time.perf_counter() - t0
                     in_flight -= reqs[i].n
-                    if collect:
-                        results[i] = (tracks, hits)
+                    if collect:      # the worker's buffers are reused: keep copies
+                        results[i] = (tracks.copy(), hits.copy())
                 if self.calib:
                     self.calib.on_complete(wk.tag, len(wk.batch))
                 del busy[w]

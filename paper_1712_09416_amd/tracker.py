@@ -180,13 +180,27 @@ class Tracker:
                                     ctypes.byref(nh)), self.ctx)
         return tracks, hits
 
-    def get_slot_tracks(self, slot: int = 0):
+    def get_slot_tracks(self, slot: int = 0, tracks_buf=None, hits_buf=None):
         """[(tracks, hit IDs)] of every event of the slot, as get_tracks gives
-        them, read in one copy (a few synchronisations for the slot)."""
+        them, read in one copy (a few synchronisations for the slot).
+        tracks_buf (TRACK_DTYPE) and hits_buf (int32): optional host arrays to
+        copy into, e.g. views of pinned memory, into which the copy is much
+        faster; the returned arrays are then views of them, valid until they
+        are written again (if they are too small, new arrays are used)."""
         ne = self._n_events.get(slot, 1)
         toff = np.zeros(ne + 1, np.uint32)
         hoff = np.zeros(ne + 1, np.uint32)
         nt, nh = ctypes.c_int64(0), ctypes.c_int64(0)
+        if tracks_buf is not None and hits_buf is not None:
+            assert tracks_buf.dtype == TRACK_DTYPE and hits_buf.dtype == np.int32
+            rc = self.L.tpc_get_slot_tracks(self.ctx, slot, tracks_buf.ctypes.data, len(tracks_buf),
+                                            hits_buf.ctypes.data, len(hits_buf), toff.ctypes.data,
+                                            hoff.ctypes.data, ctypes.byref(nt), ctypes.byref(nh))
+            if rc == _lib.TPC_OK:
+                return [(tracks_buf[toff[e]:toff[e + 1]], hits_buf[hoff[e]:hoff[e + 1]])
+                        for e in range(ne)]
+            if rc != _lib.TPC_EOVERFLOW:
+                check(rc, self.ctx)
         rc = self.L.tpc_get_slot_tracks(self.ctx, slot, None, 0, None, 0, toff.ctypes.data,
                                         hoff.ctypes.data, ctypes.byref(nt), ctypes.byref(nh))
         if rc not in (_lib.TPC_OK, _lib.TPC_EOVERFLOW):

@@ -201,6 +201,15 @@ def test_batch_equals_single_events(dev, oracle_lib):
     trk.track_event(0)
     whole = trk.get_slot_tracks(0)              # every event in one copy
     assert len(whole) == len(evs)
+    # into caller buffers (pinned host memory), large enough or not
+    from paper_1712_09416_amd._lib import TRACK_DTYPE
+    for n_t, n_h in ((1 << 14, 1 << 20), (3, 5)):
+        tb_buf = torch.empty(n_t * TRACK_DTYPE.itemsize, dtype=torch.uint8,
+                             pin_memory=True).numpy().view(TRACK_DTYPE)
+        hb_buf = torch.empty(n_h, dtype=torch.int32, pin_memory=True).numpy()
+        again = trk.get_slot_tracks(0, tb_buf, hb_buf)
+        for (t1, h1), (t2, h2) in zip(again, whole):
+            assert np.array_equal(t1, t2) and np.array_equal(h1, h2)
     for e, ev in enumerate(evs):
         tb, hb = trk.get_tracks(0, e)
         assert np.all(tb["event"] == e)
