@@ -531,16 +531,23 @@ def main() -> int:
     else:
         wall1_ms, lat1, stage1_ms, _ = run_steps(trks[:1], args.steps)
 
-    # end to end: clusters in pinned host memory -> tracks in host memory
+    # end to end: clusters in pinned host memory -> tracks in (pinned) host
+    # memory
     e2e = []
     if args.e2e_steps > 0:
+        from paper_1712_09416_amd._lib import TRACK_DTYPE
         pin = [torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
                for a in (ev.sector, ev.row, ev.y, ev.z)]
+        p = trk.params
+        max_tracks = p.max_clusters // p.n_min_track + 36
+        out_t = torch.empty(max_tracks * TRACK_DTYPE.itemsize, dtype=torch.uint8,
+                            pin_memory=True).numpy().view(TRACK_DTYPE)
+        out_h = torch.empty(ev.n, dtype=torch.int32, pin_memory=True).numpy()
         for k in range(args.e2e_steps + 2):
             t0 = time.perf_counter()
             trk.load(0, *pin)
             trk.track_event(0)
-            trk.get_tracks(0)
+            trk.get_slot_tracks(0, out_t, out_h)
             if k >= 2:
                 e2e.append((time.perf_counter() - t0) * 1e3)
 
@@ -687,7 +694,7 @@ def main() -> int:
         "track_hits": int(len(hits)),
         "plain": plain,
         "merge": merge,
-        "end_to_end": ({"what": "pinned host clusters -> H2D -> tracking -> tracks in host memory",
+        "end_to_end": ({"what": "pinned host clusters -> H2D -> tracking -> tracks in pinned host memory",
                         "p50_ms": float(np.percentile(e2e, 50)),
                         "p99_ms": float(np.percentile(e2e, 99)),
                         "clusters_per_s": ev.n / (float(np.mean(e2e)) * 1e-3)} if e2e else None),
