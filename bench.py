@@ -293,14 +293,14 @@ def bench_serve(pool, geo, n_req: int) -> dict:
         return [Request(float(t), *src[id(e)], tag=e.name) for t, e in zip(times, picks)]
 
     def capacity(plain):
-        srv = Server(geo, n_streams=4, max_events=8, cap_clusters=cap, plain=plain, **shape)
+        srv = Server(geo, n_streams=4, max_events=32, cap_clusters=cap, plain=plain, **shape)
         srv.run(requests(np.zeros(len(picks[:40])))[:40])          # warm-up
         st = srv.run(requests(np.zeros(len(picks))))
         srv.close()
         return st.n_requests / st.wall_s
 
     def serve(plain, rate):
-        srv = Server(geo, n_streams=4, max_events=8, cap_clusters=cap, plain=plain, **shape)
+        srv = Server(geo, n_streams=4, max_events=32, cap_clusters=cap, plain=plain, **shape)
         srv.run(requests(np.zeros(40))[:40])
         st = srv.run(requests(poisson_arrivals(len(picks), rate, seed=7)), warmup=warm)
         srv.close()
@@ -318,7 +318,7 @@ def bench_serve(pool, geo, n_req: int) -> dict:
         rq = [Request(float(t), e.sector, e.row, e.y, dist[id(e)], tag=e.name)
               for t, e in zip(times, picks)]
         cal = DriftCalibration(250.0, every=50) if with_calib else None
-        srv = Server(geo, n_streams=4, max_events=8, cap_clusters=cap, calib=cal, **shape)
+        srv = Server(geo, n_streams=4, max_events=32, cap_clusters=cap, calib=cal, **shape)
         srv.run(rq[:40])
         st = srv.run(rq, warmup=warm)
         srv.close()
