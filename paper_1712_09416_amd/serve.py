@@ -150,7 +150,7 @@ class Server:
     cap_clusters clusters; at most budget_clusters clusters in flight;
     params: tracker params (e.g. a tuned launch shape)."""
 
-    def __init__(self, geometry: dict, n_streams: int = 4, max_events: int = 8,
+    def __init__(self, geometry: dict, n_streams: int = 4, max_events: int = 32,
                  cap_clusters: int = 4 << 20, budget_clusters: int | None = None,
                  device: str = "cuda:0", plain: bool = False, calib=None, **params):
         self.plain = plain
