@@ -232,6 +232,31 @@ def test_batch_equals_single_events(dev, oracle_lib):
     trk.close()
 
 
+def test_events_in_flight_match_oracle(dev, oracle_lib):
+    """Events in flight as in the bench's timed region: three trackers, each
+    with its own stream and workspace, take six events round-robin with no
+    synchronisation between the launches; every event's tracks equal the
+    oracle's."""
+    from paper_1712_09416_amd import Tracker
+    evs = [tpcgen.pbpb_event(tpcgen.seed_for(2) + 200 + e, m)
+           for e, m in enumerate([1500, 300, 2500, 800, 60, 1200])]
+    geo = evs[0].geometry()
+    cap = max(e.n for e in evs)
+    trks = [Tracker(geo, max_slots=2, max_clusters=cap) for _ in range(3)]
+    ins = [[torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (e.sector, e.row, e.y, e.z)]
+           for e in evs]
+    for i, e in enumerate(evs):                  # slot i // 3 of tracker i % 3
+        t = trks[i % 3]
+        t.load(i // 3, *ins[i])
+        t.track_event(i // 3)
+    for i, e in enumerate(evs):
+        tracks, hits = trks[i % 3].get_tracks(i // 3)
+        ref = oracle_lib.run(e.sector, e.row, e.y, e.z, geo, precision=32, nthreads=ORACLE_THREADS)
+        compare_tracks(tracks, hits, ref)
+    for t in trks:
+        t.close()
+
+
 def test_full_batch_graph_matches_oracle(dev, oracle_lib):
     """The bench's batch at full size (64 Pb-Pb-shaped events of
     multiplicity 50-15000, 31.5M clusters, 2304 sectors in one launch per
