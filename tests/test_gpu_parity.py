@@ -17,7 +17,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 FLOOR = np.array([10.0, 10.0, 0.1, 0.1, 0.1])
-ORACLE_THREADS = 16          # the GPU machine's CPU share
+ORACLE_THREADS = 16          # host threads for the oracle runs
 PACK = [(i, j) for i in range(5) for j in range(i + 1)]
 
 
