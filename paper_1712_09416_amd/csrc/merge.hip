@@ -322,7 +322,8 @@ constexpr int kPairLanes = 16;   // lanes walking one track's candidates
 // A pair (A, B) of the candidate walk: if compatible, its chi2 lowers A's
 // and B's smallest chi2 (kFinal = false; the bit pattern of a non-negative
 // double orders like its value) and the pair is listed for the second pass
-// (up to pair_cap pairs, slots taken a wave at a time); or, once those are
+// (in the block's segment of the list, up to pair_cap pairs each, slots
+// taken a wave at a time); or, once those are
 // known, it offers B as A's best outer partner and A as B's best inner
 // partner where it reaches them (kFinal = true; the smaller track position
 // wins a tie).  Called by every active lane of the wave together.
